@@ -1,0 +1,303 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: closed forms,
+a brute-force dense inverse, the Moore-Penrose route, the global FEM solve the
+torn system is equivalent to (Sec. II, eq. femsystem vs eq. fetisystem),
+central finite differences, and exact identities.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from synth import make_problem, config_problem, element_matrix
+from synth.problems import assemble_stiffness, regularise
+from oracle import feti
+from oracle import implicit as orc_impl
+
+
+# ---------------------------------------------------------------- helpers
+
+def dense_B(sub):
+    B = np.zeros((sub.m, sub.n))
+    for j in range(sub.m):
+        B[j, sub.b_dof[j]] = sub.b_sign[j]
+    return B
+
+
+def global_fem_solve(prob):
+    """Direct solve of the untorn FEM system with Dirichlet dofs eliminated."""
+    dpn = prob.dpn
+    nn = int(np.prod([e + 1 for e in prob.n_elems]))
+    N = nn * dpn
+    rows, cols, vals = [], [], []
+    f = np.zeros(N)
+    for s in prob.subs:
+        g = (s.gnode[:, None] * dpn + np.arange(dpn)[None, :]).ravel()
+        K = s.K.tocoo()
+        rows.append(g[K.row]); cols.append(g[K.col]); vals.append(K.data)
+        np.add.at(f, g, s.f)
+    K = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(N, N)).tocsr()
+    coords = np.stack(np.unravel_index(np.arange(nn), [e + 1 for e in prob.n_elems][::-1])[::-1],
+                      axis=-1)
+    fixed = np.zeros(N, dtype=bool)
+    if prob.dirichlet_axis is not None:
+        fixed = np.repeat(coords[:, prob.dirichlet_axis] == 0, dpn)
+    free = ~fixed
+    u = np.zeros(N)
+    u[free] = spla.spsolve(K[free][:, free].tocsc(), f[free])
+    return u
+
+
+def solve_feti(prob, tol=1e-12):
+    invs = [feti.RegInverse(s.Kreg) for s in prob.subs]
+    Fs = [feti.local_dual_operator(s.Kreg, s.b_dof, s.b_sign, inv)
+          for s, inv in zip(prob.subs, invs)]
+    Ds = [s.dual_map for s in prob.subs]
+    applyF = lambda x: feti.apply_explicit(Fs, Ds, x, prob.n_lambda)
+    G = feti.G_matrix(prob)
+    e = feti.e_vector(prob)
+    d = feti.d_vector(prob, invs)
+    lam, it, hist = feti.pcpg(applyF, d, G, e, tol=tol, maxit=5000)
+    alpha = feti.alpha_from_lambda(G, d, applyF(lam))
+    us = feti.primal_solution(prob, invs, lam, alpha)
+    return dict(invs=invs, Fs=Fs, G=G, e=e, d=d, lam=lam, it=it, alpha=alpha, us=us,
+                applyF=applyF)
+
+
+def tiny(kind, seed=7):
+    if kind == "heat2d":
+        return make_problem(2, "heat", [[3, 4], [4, 3]], 0.5, dirichlet_axis=0, seed=seed)
+    if kind == "heat3d":
+        return make_problem(3, "heat", [[3, 2], [2, 3], [3, 2]], 0.5, dirichlet_axis=2, seed=seed)
+    if kind == "elast3d":
+        return make_problem(3, "elasticity", [[2, 3], [2, 2], [3, 2]], 0.3, dirichlet_axis=2,
+                            seed=seed)
+    if kind == "elast2d":
+        return make_problem(2, "elasticity", [[3, 2, 3], [3, 2]], 0.3, dirichlet_axis=0,
+                            seed=seed)
+    raise ValueError(kind)
+
+
+KINDS = ["heat2d", "heat3d", "elast3d", "elast2d"]
+
+
+# ---------------------------------------------------------------- element matrices
+
+def test_element_matrices_closed_form():
+    K2 = element_matrix(2, "heat")
+    # bilinear unit square: 2/3 on the diagonal, -1/6 along edges, -1/3 across
+    assert np.allclose(np.diag(K2), 2 / 3)
+    assert np.isclose(K2[0, 1], -1 / 6) and np.isclose(K2[0, 2], -1 / 6)
+    assert np.isclose(K2[0, 3], -1 / 3)
+    K3 = element_matrix(3, "heat", h=0.25)
+    # trilinear cube of edge h: h/3 diagonal, 0 along edges, -h/12 face and body diagonals
+    assert np.allclose(np.diag(K3), 0.25 / 3)
+    assert np.isclose(K3[0, 1], 0.0, atol=1e-15)
+    assert np.isclose(K3[0, 3], -0.25 / 12) and np.isclose(K3[0, 7], -0.25 / 12)
+    for K in (K2, K3):
+        assert np.allclose(K.sum(axis=1), 0.0, atol=1e-15)
+    Ke = element_matrix(3, "elasticity", h=1.0, E=1.0, nu=0.3)
+    assert np.allclose(Ke, Ke.T)
+    ev = np.linalg.eigvalsh(Ke)
+    assert np.sum(ev < 1e-10) == 6  # six rigid-body modes
+    # rigid-body modes of one cube are in its null space
+    corners = np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)], float)
+    for t in np.eye(3):
+        assert np.allclose(Ke @ np.tile(t, 8), 0, atol=1e-14)
+    rot = np.zeros(24)
+    rot[0::3] = -corners[:, 1]
+    rot[1::3] = corners[:, 0]
+    assert np.allclose(Ke @ rot, 0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- 1D closed form
+
+@pytest.mark.parametrize("nsub,nel", [(2, 5), (3, 4)])
+def test_local_dual_operator_1d_closed_form(nsub, nel):
+    """1D bar, nodes 0..n, unit conductivity, edge h, K_reg = K + rho e0 e0^T:
+    (K_reg^{-1})_{ij} = 1/rho + h*min(i,j).  With the chain gluing and the
+    Dirichlet row at x=0 this fixes every F~_i entry."""
+    P = make_problem(1, "heat", [[nel] * nsub], 0.0, dirichlet_axis=0, seed=1)
+    h = P.h
+    for s in P.subs:
+        rho = s.rho
+        Ginv = lambda i, j: 1.0 / rho + h * min(i, j)
+        expect = np.array([[s.b_sign[a] * s.b_sign[b] * Ginv(s.b_dof[a], s.b_dof[b])
+                            for b in range(s.m)] for a in range(s.m)])
+        F = feti.local_dual_operator(s.Kreg, s.b_dof, s.b_sign)
+        assert np.allclose(F, expect, rtol=1e-14, atol=0)
+    # explicit structure of the first two subdomains
+    s0, s1 = P.subs[0], P.subs[1]
+    F0 = feti.local_dual_operator(s0.Kreg, s0.b_dof, s0.b_sign)
+    r = 1.0 / s0.rho
+    assert np.allclose(F0, [[r, r], [r, r + nel * h]], rtol=1e-14)
+    F1 = feti.local_dual_operator(s1.Kreg, s1.b_dof, s1.b_sign)
+    r1 = 1.0 / s1.rho
+    if nsub == 2:
+        assert np.allclose(F1, [[r1]], rtol=1e-14)
+    else:  # middle subdomain: -1 at its left end, +1 at its right end
+        assert np.allclose(F1, [[r1, -r1], [-r1, r1 + nel * h]], rtol=1e-14)
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_local_dual_operator_brute_force(kind):
+    P = tiny(kind)
+    for s in P.subs:
+        F = feti.local_dual_operator(s.Kreg, s.b_dof, s.b_sign)
+        B = dense_B(s)
+        Fb = B @ np.linalg.inv(s.Kreg.toarray()) @ B.T
+        assert np.allclose(F, Fb, rtol=0, atol=1e-11 * np.abs(Fb).max())
+        assert np.array_equal(F, F.T)
+        ev = np.linalg.eigvalsh(F)
+        assert ev.min() >= -1e-12 * ev.max()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_generalized_inverse(kind):
+    """K K_reg^{-1} K = K (the defining property of K^+, Sec. II)."""
+    P = tiny(kind)
+    for s in P.subs:
+        K = s.K.toarray()
+        X = feti.RegInverse(s.Kreg).solve(K)
+        assert np.linalg.norm(K @ X - K) <= 1e-12 * np.linalg.norm(K)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_projected_operator_matches_moore_penrose(kind):
+    """P F P does not depend on the generalised inverse: it equals the value
+    obtained with the Moore-Penrose pseudo-inverse of K."""
+    P = tiny(kind)
+    G = feti.G_matrix(P)
+    Pr = feti.Projector(G)
+    nl = P.n_lambda
+    F = np.zeros((nl, nl))
+    Fmp = np.zeros((nl, nl))
+    for s in P.subs:
+        Fi = feti.local_dual_operator(s.Kreg, s.b_dof, s.b_sign)
+        F[np.ix_(s.dual_map, s.dual_map)] += Fi
+        B = dense_B(s)
+        Fmp[np.ix_(s.dual_map, s.dual_map)] += B @ np.linalg.pinv(s.K.toarray(), rcond=1e-12,
+                                                                 hermitian=True) @ B.T
+    PF = np.stack([Pr(Pr(F[:, j])) for j in range(nl)], 1)
+    PF = np.stack([Pr(PF[i, :]) for i in range(nl)], 0)
+    PM = np.stack([Pr(Fmp[:, j]) for j in range(nl)], 1)
+    PM = np.stack([Pr(PM[i, :]) for i in range(nl)], 0)
+    assert np.abs(PF - PM).max() <= 1e-9 * np.abs(PM).max()
+
+
+def test_F_additivity_and_apply_routes():
+    """sum_i D_i^T F~_i D_i equals B K^+ B^T assembled globally (Sec. II-A),
+    and explicit application equals the implicit right-to-left one (Sec. III)."""
+    P = tiny("heat3d")
+    nl = P.n_lambda
+    Fsum = np.zeros((nl, nl))
+    Bg = np.zeros((nl, sum(s.n for s in P.subs)))
+    Kinv = []
+    off = 0
+    for s in P.subs:
+        Fsum[np.ix_(s.dual_map, s.dual_map)] += feti.local_dual_operator(
+            s.Kreg, s.b_dof, s.b_sign)
+        Bg[s.dual_map, off + s.b_dof] = s.b_sign
+        Kinv.append(np.linalg.inv(s.Kreg.toarray()))
+        off += s.n
+    from scipy.linalg import block_diag
+    Fglob = Bg @ block_diag(*Kinv) @ Bg.T
+    assert np.abs(Fsum - Fglob).max() <= 1e-11 * np.abs(Fglob).max()
+    invs = [feti.RegInverse(s.Kreg) for s in P.subs]
+    Fs = [feti.local_dual_operator(s.Kreg, s.b_dof, s.b_sign, i) for s, i in zip(P.subs, invs)]
+    qe = feti.apply_explicit(Fs, [s.dual_map for s in P.subs], P.lam, nl)
+    qi = feti.apply_implicit(invs, P.subs, P.lam, nl)
+    assert np.abs(qe - qi).max() <= 1e-13 * np.abs(qi).max()
+    assert np.allclose(qe, Fglob @ P.lam, rtol=0, atol=1e-11 * np.abs(qe).max())
+
+
+# ---------------------------------------------------------------- whole FETI
+
+@pytest.mark.parametrize("kind", ["C1", "heat3d", "elast3d", "elast2d"])
+def test_feti_solution_equals_global_fem(kind):
+    """The torn system is equivalent to the FEM system: PCPG (Alg. 1) + alpha
+    (eq. alphacompute) + u recovery (eq. solutionUeval) reproduce the global
+    direct solve, and the constraints G^T lambda = e, B u = c hold."""
+    P = config_problem(1) if kind == "C1" else tiny(kind)
+    r = solve_feti(P, tol=1e-13)
+    ug = global_fem_solve(P)
+    dpn = P.dpn
+    err = 0.0
+    for s, u in zip(P.subs, r["us"]):
+        g = (s.gnode[:, None] * dpn + np.arange(dpn)[None, :]).ravel()
+        err = max(err, np.abs(u - ug[g]).max())
+    assert err <= 1e-8 * np.abs(ug).max()
+    assert np.abs(r["G"].T @ r["lam"] - r["e"]).max() <= 1e-10 * max(1, np.abs(r["e"]).max())
+    Bu = np.zeros(P.n_lambda)
+    for s, u in zip(P.subs, r["us"]):
+        np.add.at(Bu, s.dual_map, s.b_sign * u[s.b_dof])
+    assert np.abs(Bu - P.c).max() <= 1e-8 * np.abs(ug).max()
+
+
+def test_pcpg_fixed_iterations_and_lambda_uniqueness():
+    """lambda does not depend on rho (a different valid generalised inverse)."""
+    P = tiny("heat2d")
+    r1 = solve_feti(P)
+    for s in P.subs:
+        s.Kreg = regularise(s.K, s.R, s.fix_dofs, 7.5 * s.rho)
+    r2 = solve_feti(P)
+    assert np.abs(r1["lam"] - r2["lam"]).max() <= 1e-8 * np.abs(r1["lam"]).max()
+    # fixed iteration count is honoured
+    lam, it, hist = feti.pcpg(r1["applyF"], r1["d"], r1["G"], r1["e"], fixed_iters=3)
+    assert it == 3 and len(hist) == 4
+
+
+# ---------------------------------------------------------------- derivatives
+
+def _J(sub, theta, mu, lam):
+    K = assemble_stiffness(sub, theta)
+    Kr = regularise(K, sub.R, sub.fix_dofs, sub.rho)
+    F = feti.local_dual_operator(Kr, sub.b_dof, sub.b_sign)
+    return mu[sub.dual_map] @ F @ lam[sub.dual_map]
+
+
+def test_gradient_central_differences():
+    P = make_problem(3, "heat", [[3, 3], [3, 3], [3, 3]], 0.3, dirichlet_axis=2, seed=11)
+    rng = np.random.default_rng(0)
+    for s in P.subs[:3]:
+        inv = feti.RegInverse(s.Kreg)
+        g = feti.grad_theta(inv, s, P.mu, P.lam)
+        for e in rng.choice(len(s.theta), 6, replace=False):
+            h = 1e-6
+            tp = s.theta.copy(); tp[e] += h
+            tm = s.theta.copy(); tm[e] -= h
+            fd = (_J(s, tp, P.mu, P.lam) - _J(s, tm, P.mu, P.lam)) / (2 * h)
+            assert abs(fd - g[e]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max())
+
+
+def test_gradient_euler_identity():
+    """P F P is homogeneous of degree -1 in theta (heat), so with projected
+    mu, lambda: sum_e theta_e dJ/dtheta_e = -J exactly."""
+    P = make_problem(3, "heat", [[3, 2], [2, 3], [2, 2]], 0.3, dirichlet_axis=2, seed=5)
+    Pr = feti.Projector(feti.G_matrix(P))
+    mu, lam = Pr(P.mu), Pr(P.lam)
+    J, S = 0.0, 0.0
+    for s in P.subs:
+        inv = feti.RegInverse(s.Kreg)
+        F = feti.local_dual_operator(s.Kreg, s.b_dof, s.b_sign, inv)
+        J += mu[s.dual_map] @ F @ lam[s.dual_map]
+        S += s.theta @ feti.grad_theta(inv, s, mu, lam)
+    assert abs(S + J) <= 1e-10 * abs(J)
+
+
+# ---------------------------------------------------------------- C oracle
+
+@pytest.mark.parametrize("kind", ["heat3d", "elast3d"])
+def test_c_implicit_apply_matches_python_oracle(kind):
+    P = tiny(kind)
+    invs = [feti.RegInverse(s.Kreg) for s in P.subs]
+    q = feti.apply_implicit(invs, P.subs, P.lam, P.n_lambda)
+    for perms in (None, [np.arange(s.n, dtype=np.int32) for s in P.subs]):
+        I = orc_impl.ImplicitCPU(P.subs, P.n_lambda, nthreads=3, perms=perms)
+        I.factor()
+        qc = I.apply(P.lam)
+        assert np.abs(qc - q).max() <= 1e-11 * np.abs(q).max()
