@@ -1,0 +1,211 @@
+/*
+ * fetiF — explicit FETI local dual operators on AMD Instinct MI355X (gfx950).
+ *
+ * The library assembles, for every subdomain i of a torn (Total-FETI)
+ * problem, the explicit local dual operator
+ *
+ *     F~_i = B~_i K_i^+ B~_i^T,   K_i^+ = K_reg,i^{-1} = L_i^{-T} L_i^{-1}
+ *
+ * (paper Sec. II-A, eq. localdualoperator; Sec. III, eq.
+ * localdualoperatorwithU with the symmetric factor K_reg,i = L_i L_i^T), by
+ * the SYRK path of Sec. IV-C: X_i = L_i^{-1} P_i B~_i^T, F~_i = X_i^T X_i,
+ * and applies the cluster operator q = sum_i D_i^T F~_i D_i lambda
+ * (eq. dualop_apply_expl with the scatter/gather of Alg. 2).
+ *
+ * Lifecycle (Alg. 2): fetiF_create (preparation: ordering, symbolic
+ * factorisation, device structures) -> per step fetiF_factor_upload for all
+ * subdomains (numeric factorisation on host threads + copy of the factor
+ * values) and fetiF_assemble -> per solver iteration fetiF_apply.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_d are device pointers on the context's device; all
+ *    other pointers are host pointers, read during the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Device work is enqueued on it; the calls do not synchronise the host
+ *    unless stated.  Caller-owned device buffers must stay valid until the
+ *    enqueued work completes.
+ *  - Errors: argument errors return FETIF_EINVAL synchronously and change
+ *    nothing; FETIF_ESTATE reports a call out of lifecycle order; HIP
+ *    failures return FETIF_EDEVICE and are sticky for the context.  The
+ *    message of the last error is fetiF_last_error(ctx).
+ *  - One context is used by one host thread at a time.
+ */
+#ifndef FETIF_H
+#define FETIF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fetiF_ctx_s* fetiF_ctx;
+
+typedef enum {
+    FETIF_OK = 0,
+    FETIF_EINVAL = 1,  /* invalid argument; nothing changed */
+    FETIF_ENOMEM = 2,  /* host or device allocation failed */
+    FETIF_ESTATE = 3,  /* call not valid in the current lifecycle state */
+    FETIF_EDEVICE = 4, /* HIP runtime error or no usable device (sticky) */
+    FETIF_ENOTSPD = 5, /* numeric factorisation met a non-positive pivot */
+    FETIF_ENOTSUP = 6  /* option not supported */
+} fetiF_status;
+
+/* Storage precision of the assembled F~_i.  Assembly always computes in
+ * FP64; FP32/BF16 are rounded to nearest-even when stored and are applied
+ * with FP32 accumulation (FP64 accumulation for FP64 storage). */
+typedef enum { FETIF_F64 = 0, FETIF_F32 = 1, FETIF_BF16 = 2 } fetiF_prec;
+
+/* One subdomain, as given to fetiF_create (all arrays are copied).
+ *  n            DOFs of K_reg,i.
+ *  dofs_per_node  dof = dofs_per_node*node + component; DOFs of one node
+ *               stay together in the ordering.
+ *  k_ptr,k_idx  CSR of the FULL symmetric pattern of K_reg,i (both
+ *               triangles, diagonal present, column indices ascending);
+ *               fetiF_factor_upload takes values in this same order.
+ *  dim,coords   optional node coordinates (n/dofs_per_node x dim, row-major)
+ *               for geometric nested dissection; dim=0/coords=NULL selects
+ *               graph nested dissection.
+ *  m            rows of B~_i (local Lagrange multipliers).
+ *  b_dof,b_sign row j of B~_i has the single entry b_sign[j] (+1 or -1) in
+ *               column b_dof[j] (Sec. II: one gluing/Dirichlet entry per row).
+ *  dual_map     D_i: global multiplier of local row j, strictly increasing,
+ *               in [0, n_lambda).
+ *  nelem,edofs,elem_dofs,dK   optional element data for the theta-adjoint
+ *               of fetiF_apply_backward: element e couples the local DOFs
+ *               elem_dofs[e*edofs .. +edofs) and dK (edofs x edofs,
+ *               row-major) is dK_reg,i/dtheta_e, the same for every element
+ *               of the subdomain.  nelem=0 disables the adjoint. */
+typedef struct {
+    int32_t n;
+    int32_t dofs_per_node;
+    const int32_t* k_ptr;
+    const int32_t* k_idx;
+    int32_t dim;
+    const double* coords;
+    int32_t m;
+    const int32_t* b_dof;
+    const int8_t* b_sign;
+    const int32_t* dual_map;
+    int32_t nelem;
+    int32_t edofs;
+    const int32_t* elem_dofs;
+    const double* dK;
+} fetiF_subdomain;
+
+/* Options; zero-initialised fields select defaults. */
+typedef struct {
+    fetiF_prec f_storage; /* storage precision of F~_i (default FP64) */
+    int32_t leaf_nodes;   /* nested-dissection leaf size in nodes (default 24) */
+    int32_t nthreads;     /* host threads for analysis/factorisation (default: all) */
+    int32_t apply_band;   /* elements of F~ per apply work-group (default 32768) */
+    int32_t trsm_chunk;   /* RHS columns per TRSM work-group (default 64) */
+} fetiF_options;
+
+/* Preparation (Alg. 2, "preparation"; Sec. IV-B "Preparation"): nested
+ * dissection and supernodal symbolic analysis of every K_reg,i on host
+ * threads, the work schedules of assembly and application, and the device
+ * memory for factors, X_i, F~_i and the dual-vector maps, with the constant
+ * structures copied to the device.  `device` is the HIP ordinal.  On success
+ * *out owns all of it until fetiF_destroy.  Synchronous. */
+fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambda, int32_t nsub,
+                          const fetiF_subdomain* subs, const fetiF_options* opt);
+
+/* Numeric factorisation K_reg,i = L_i L_i^T (Sec. III; Alg. 2 "FETI
+ * preprocessing, num. fact.") of subdomains [first, first+count) on host
+ * threads, then an asynchronous copy of the factor values to the device on
+ * `stream` (Sec. IV-B "copy the factors' non-zero values to the GPU").
+ * k_vals[k] holds the CSR values of K_reg of subdomain first+k in the
+ * pattern given at create.  Returns FETIF_ENOTSPD (naming the subdomain and
+ * pivot in fetiF_last_error) if a pivot is not positive.  The host arrays
+ * may be freed on return; invalidates a previous assembly. */
+fetiF_status fetiF_factor_upload(fetiF_ctx ctx, int32_t first, int32_t count,
+                                 const double* const* k_vals, void* stream);
+
+/* Assembly of every F~_i from the uploaded factors (Sec. IV-C, SYRK path):
+ * RHS initialisation X_i = P_i B~_i^T, supernodal forward TRSM
+ * X_i <- L_i^{-1} X_i, and F~_i = X_i^T X_i stored as one triangle in the
+ * chosen precision.  Requires every subdomain uploaded since the last
+ * assembly (else FETIF_ESTATE).  Asynchronous on `stream`. */
+fetiF_status fetiF_assemble(fetiF_ctx ctx, void* stream);
+
+/* q_d[0..n_lambda) = sum_i D_i^T F~_i D_i lambda_d (Alg. 2 scatter, apply,
+ * gather; eq. dualop_apply_expl).  FP64 vectors.  Each q entry is summed in
+ * a fixed order (bitwise reproducible).  Allocates nothing and does no host
+ * copy; capturable in a HIP graph.  lambda_d and q_d must not overlap. */
+fetiF_status fetiF_apply(fetiF_ctx ctx, const double* lambda_d, double* q_d, void* stream);
+
+/* Reverse mode of J = g^T F(theta) lambda for the applied operator:
+ *   dlambda_d = F g_d   (F is symmetric),
+ *   dtheta_d[e] = -u_g|_e^T dK_e u_lambda|_e  for every element of every
+ *   subdomain (concatenated in subdomain order), with u_x = K_reg,i^{-1}
+ *   B~_i^T D_i x by forward and backward substitution with L_i.
+ * dtheta_d may be NULL (then only dlambda is formed); requires element data
+ * at create for a non-NULL dtheta_d.  Asynchronous on `stream`. */
+fetiF_status fetiF_apply_backward(fetiF_ctx ctx, const double* g_d, const double* lambda_d,
+                                  double* dlambda_d, double* dtheta_d, void* stream);
+
+/* Copy F~_i of one subdomain to host_out as a full m_i x m_i row-major
+ * matrix in the local multiplier order of create (test/debug hook).
+ * Synchronises the device. */
+fetiF_status fetiF_download_F(fetiF_ctx ctx, int32_t sub, double* host_out);
+
+/* Sizes and work counts of a context (for reporting). */
+typedef struct {
+    int32_t nsub;
+    int64_t n_lambda;
+    int64_t sum_m;          /* sum of m_i */
+    int64_t factor_values;  /* FP64 values of all supernodal panels */
+    int64_t x_values;       /* FP64 values of the compact X_i */
+    int64_t f_elements;     /* stored triangle elements (incl. row padding) */
+    int64_t f_tri_elements; /* sum m_i (m_i+1)/2 */
+    double trsm_flops;      /* algorithmic flops of the sparse-RHS TRSM */
+    double syrk_flops;      /* algorithmic flops of the row-sparse SYRK */
+    double factor_flops;    /* host numeric factorisation flops */
+    int32_t trsm_levels;    /* launches of the level-scheduled TRSM */
+    int32_t apply_groups;   /* work-groups of one apply */
+} fetiF_info;
+
+fetiF_status fetiF_query(fetiF_ctx ctx, fetiF_info* info);
+
+/* Release everything owned by the context (synchronises its device). */
+fetiF_status fetiF_destroy(fetiF_ctx ctx);
+
+/* Message of the last error of ctx (or of the last failed create when ctx is
+ * NULL).  Valid until the next call on the same context. */
+const char* fetiF_last_error(fetiF_ctx ctx);
+
+/* ---------------------------------------------------------------------
+ * Host-only analysis (no device needed): the ordering, symbolic analysis
+ * and numeric factorisation of one K_reg that feed the device path
+ * (Sec. III, symbolic and numeric stages).  For inspection and tests.
+ * --------------------------------------------------------------------- */
+typedef struct fetiF_hfactor_s* fetiF_hfactor;
+
+/* Order, analyse and factor one subdomain's K_reg (values in CSR order). */
+fetiF_status fetiF_host_factor(const fetiF_subdomain* sub, const double* k_vals,
+                               const fetiF_options* opt, fetiF_hfactor* out);
+
+/* n, number of stored factor entries (lower part of the supernodal panels,
+ * explicit zeros included), supernodes and elimination-tree levels. */
+fetiF_status fetiF_hfactor_info(fetiF_hfactor h, int32_t* n, int64_t* nnz, int32_t* nsuper,
+                                int32_t* nlevels);
+
+/* perm[k] = original DOF at position k; L as CSC (colptr[n+1], rowidx[nnz],
+ * vals[nnz]) in the permuted order, so that L L^T = P K_reg P^T.
+ * Any output pointer may be NULL. */
+fetiF_status fetiF_hfactor_export(fetiF_hfactor h, int32_t* perm, int64_t* colptr,
+                                  int32_t* rowidx, double* vals);
+
+/* Supernode table: first column, columns, rows below the diagonal block,
+ * parent supernode (-1 root) and height level, each [nsuper]. */
+fetiF_status fetiF_hfactor_supernodes(fetiF_hfactor h, int32_t* first, int32_t* ncols,
+                                      int32_t* nrows, int32_t* parent, int32_t* level);
+
+void fetiF_hfactor_free(fetiF_hfactor h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FETIF_H */

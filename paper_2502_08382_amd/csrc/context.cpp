@@ -1,0 +1,776 @@
+// The fetiF context: preparation (ordering, symbolic analysis, schedules,
+// device structures), per-step factorisation + upload, assembly and
+// application (paper Alg. 2 and Sec. IV-B).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/fetiF.h"
+#include "device_types.hpp"
+#include "host_sparse.hpp"
+#include "internal.hpp"
+#include "kernels.hpp"
+
+using namespace fetif;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <typename Fn>
+void parallel_for(int32_t n, int nthreads, Fn fn)
+{
+    if (nthreads <= 1 || n <= 1) {
+        for (int32_t i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    std::atomic<int32_t> next(0);
+    std::vector<std::thread> th;
+    int nt = std::min<int>(nthreads, n);
+    th.reserve(nt);
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&]() {
+            for (;;) {
+                int32_t i = next.fetch_add(1);
+                if (i >= n) break;
+                fn(i);
+            }
+        });
+    for (auto& t : th) t.join();
+}
+
+struct SubPlan {
+    int32_t n = 0, m = 0, dpn = 1;
+    int64_t nnzA = 0;
+    Symbolic sym;
+    std::vector<int32_t> sigma;   // sorted position -> caller's local multiplier
+    std::vector<int32_t> start;   // sorted start rows (permuted DOF of each column)
+    std::vector<int32_t> j0, w;   // per supernode
+    std::vector<int64_t> xoff;    // per supernode, local
+    int64_t nx = 0;
+    std::vector<int32_t> b_dof, dual_map;
+    std::vector<int8_t> b_sign;
+    int32_t nelem = 0, edofs = 0;
+    std::vector<int32_t> elem_dofs;
+    std::vector<double> dK;
+    // global placement
+    int64_t lbase = 0, xbase = 0, fbase = 0;
+    int32_t snbase = 0, rowbase = 0, dbase = 0, band0 = 0, nband = 0;
+    std::string err;
+};
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct fetiF_ctx_s {
+    int device = 0;
+    int64_t n_lambda = 0;
+    int32_t nsub = 0;
+    fetiF_options opt{};
+    int prec = 0;
+    int nthreads = 1;
+    std::vector<SubPlan> subs;
+    // schedules
+    std::vector<std::vector<TrsmItem>> level_items;
+    std::vector<int32_t> level_slot, level_maxns;
+    std::vector<int64_t> level_off;
+    int32_t apply_nch = 1;
+    int32_t nbands = 0;
+    int32_t nsyrk = 0;
+    int64_t total_L = 0, total_X = 0, total_F = 0, total_z = 0, total_rows = 0, sum_m = 0;
+    double trsm_flops = 0, syrk_flops = 0, factor_flops = 0;
+    // device buffers
+    double* dL = nullptr;
+    double* dX = nullptr;
+    void* dF = nullptr;
+    void* dZ = nullptr;
+    DevSN* dSN = nullptr;
+    int32_t* dRows = nullptr;
+    XRow* dXRows = nullptr;
+    RhsUnit* dUnits = nullptr;
+    TrsmItem* dItems = nullptr;
+    SyrkTile* dTiles = nullptr;
+    int32_t* dLists = nullptr;
+    Band* dBands = nullptr;
+    int64_t* dBandZ = nullptr;
+    int32_t* dGptr = nullptr;
+    GatherEnt* dGent = nullptr;
+    int32_t* dDmap = nullptr;
+    double* hStage = nullptr;  // pinned staging of factor values
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+    std::vector<void*> allocations;
+    // state
+    std::vector<uint8_t> uploaded;
+    int32_t n_uploaded = 0;
+    bool assembled = false;
+    bool sticky = false;
+    std::string last_error;
+};
+
+namespace {
+
+fetiF_status fail(fetiF_ctx c, fetiF_status st, const std::string& msg)
+{
+    if (c) c->last_error = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+fetiF_status hip_fail(fetiF_ctx c, hipError_t e, const char* what)
+{
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    if (c) {
+        c->sticky = true;
+        c->last_error = msg;
+    } else {
+        g_create_error = msg;
+    }
+    return FETIF_EDEVICE;
+}
+
+#define HIPCHK(ctx, call)                                         \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);  \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+hipError_t dalloc(fetiF_ctx c, T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(T) * count);
+    if (e == hipSuccess) {
+        c->allocations.push_back(q);
+        *p = (T*)q;
+    }
+    return e;
+}
+
+template <typename T>
+hipError_t upload(T* d, const std::vector<T>& h)
+{
+    if (h.empty()) return hipSuccess;
+    return hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
+}
+
+bool plan_subdomain(const fetiF_subdomain& in, const fetiF_options& opt, int64_t n_lambda, SubPlan& P)
+{
+    Pattern A;
+    if (!pattern_from_sub(in, A, P.err)) return false;
+    P.n = in.n;
+    P.m = in.m;
+    P.dpn = in.dofs_per_node;
+    P.nnzA = A.ptr[in.n];
+    if (in.m < 0 || (in.m > 0 && (!in.b_dof || !in.b_sign || !in.dual_map))) {
+        P.err = "B~ arrays missing";
+        return false;
+    }
+    P.b_dof.assign(in.b_dof, in.b_dof + in.m);
+    P.b_sign.assign(in.b_sign, in.b_sign + in.m);
+    P.dual_map.assign(in.dual_map, in.dual_map + in.m);
+    for (int32_t j = 0; j < in.m; ++j) {
+        if (P.b_dof[j] < 0 || P.b_dof[j] >= in.n) { P.err = "b_dof out of range"; return false; }
+        if (P.b_sign[j] != 1 && P.b_sign[j] != -1) { P.err = "b_sign must be +1 or -1"; return false; }
+        if (P.dual_map[j] < 0 || P.dual_map[j] >= n_lambda) { P.err = "dual_map out of range"; return false; }
+        if (j > 0 && P.dual_map[j] <= P.dual_map[j - 1]) { P.err = "dual_map not strictly increasing"; return false; }
+    }
+    if (in.nelem > 0) {
+        if (!in.elem_dofs || !in.dK || in.edofs <= 0) { P.err = "element data incomplete"; return false; }
+        P.nelem = in.nelem;
+        P.edofs = in.edofs;
+        P.elem_dofs.assign(in.elem_dofs, in.elem_dofs + (size_t)in.nelem * in.edofs);
+        P.dK.assign(in.dK, in.dK + (size_t)in.edofs * in.edofs);
+        for (int32_t v : P.elem_dofs)
+            if (v < 0 || v >= in.n) { P.err = "elem_dofs out of range"; return false; }
+    }
+    SymbolicOptions so;
+    so.leaf_nodes = opt.leaf_nodes;
+    int dim = (in.coords && in.dim > 0) ? in.dim : 0;
+    if (!symbolic_analysis(A, in.dofs_per_node, dim ? in.coords : nullptr, dim, so, P.sym, P.err)) return false;
+    const Symbolic& S = P.sym;
+    // RHS columns sorted by their start row (= by start supernode, postorder)
+    std::vector<std::pair<int32_t, int32_t>> key(in.m);
+    for (int32_t j = 0; j < in.m; ++j) key[j] = {S.pinv[P.b_dof[j]], j};
+    std::stable_sort(key.begin(), key.end());
+    P.sigma.resize(in.m);
+    P.start.resize(in.m);
+    for (int32_t k = 0; k < in.m; ++k) {
+        P.sigma[k] = key[k].second;
+        P.start[k] = key[k].first;
+    }
+    const int32_t ns = (int32_t)S.sn.size();
+    std::vector<int32_t> fd(ns);
+    for (int32_t s = 0; s < ns; ++s) fd[s] = S.sn[s].first;
+    for (int32_t s = 0; s < ns; ++s)
+        if (S.sn[s].parent >= 0) fd[S.sn[s].parent] = std::min(fd[S.sn[s].parent], fd[s]);
+    P.j0.resize(ns);
+    P.w.resize(ns);
+    P.xoff.resize(ns);
+    int64_t xo = 0;
+    for (int32_t s = 0; s < ns; ++s) {
+        int32_t a = (int32_t)(std::lower_bound(P.start.begin(), P.start.end(), fd[s]) - P.start.begin());
+        int32_t b = (int32_t)(std::lower_bound(P.start.begin(), P.start.end(), S.sn[s].first + S.sn[s].ncols) -
+                              P.start.begin());
+        P.j0[s] = a;
+        P.w[s] = b - a;
+        P.xoff[s] = xo;
+        xo += (int64_t)S.sn[s].ncols * P.w[s];
+    }
+    P.nx = xo;
+    return true;
+}
+
+}  // namespace
+
+// ======================================================================== create
+
+extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambda, int32_t nsub,
+                                     const fetiF_subdomain* subs, const fetiF_options* opt_in)
+{
+    if (!out) return fail(nullptr, FETIF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nsub <= 0 || !subs || n_lambda <= 0 || n_lambda > INT32_MAX)
+        return fail(nullptr, FETIF_EINVAL, "need nsub > 0, subs, 0 < n_lambda < 2^31");
+    fetiF_options opt;
+    options_defaults(opt_in, opt);
+    if (opt.f_storage < FETIF_F64 || opt.f_storage > FETIF_BF16) return fail(nullptr, FETIF_EINVAL, "bad f_storage");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(nullptr, FETIF_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(nullptr, FETIF_EINVAL, "device ordinal out of range");
+
+    fetiF_ctx c = new (std::nothrow) fetiF_ctx_s();
+    if (!c) return fail(nullptr, FETIF_ENOMEM, "host allocation failed");
+    c->device = device;
+    c->n_lambda = n_lambda;
+    c->nsub = nsub;
+    c->opt = opt;
+    c->prec = (int)opt.f_storage;
+    unsigned hc = std::thread::hardware_concurrency();
+    c->nthreads = opt.nthreads > 0 ? opt.nthreads : (int)(hc ? hc : 1);
+    c->subs.resize(nsub);
+
+    // ---- per-subdomain analysis on host threads
+    parallel_for(nsub, c->nthreads, [&](int32_t i) {
+        if (!plan_subdomain(subs[i], opt, n_lambda, c->subs[i]))
+            if (c->subs[i].err.empty()) c->subs[i].err = "analysis failed";
+    });
+    for (int32_t i = 0; i < nsub; ++i)
+        if (!c->subs[i].err.empty()) {
+            std::string msg = "subdomain " + std::to_string(i) + ": " + c->subs[i].err;
+            delete c;
+            return fail(nullptr, FETIF_EINVAL, msg);
+        }
+
+    const int V = prec_vec(c->prec);
+    const int TS = 64;
+    // ---- global placement and schedules
+    std::vector<DevSN> sns;
+    std::vector<int32_t> rows;
+    std::vector<XRow> xrows;
+    std::vector<RhsUnit> units;
+    std::vector<SyrkTile> tiles;
+    std::vector<int32_t> lists;
+    std::vector<Band> bands;
+    std::vector<int64_t> band_z;
+    std::vector<int32_t> dmap;
+    int64_t lb = 0, xb = 0, fb = 0, zb = 0;
+    int32_t snb = 0, rowb = 0, db = 0;
+    int32_t maxlev = 0, max_m = 0;
+    for (int32_t i = 0; i < nsub; ++i) {
+        SubPlan& P = c->subs[i];
+        const Symbolic& S = P.sym;
+        P.lbase = lb;
+        P.xbase = xb;
+        P.snbase = snb;
+        P.rowbase = rowb;
+        P.dbase = db;
+        const int32_t ns = (int32_t)S.sn.size();
+        for (int32_t s = 0; s < ns; ++s) {
+            const Supernode& x = S.sn[s];
+            DevSN d;
+            d.lval = lb + x.val_off;
+            d.xoff = xb + P.xoff[s];
+            d.rowsoff = (int64_t)rows.size();
+            d.rowbase = rowb;
+            d.first = x.first;
+            d.ncols = x.ncols;
+            d.nrows = x.nrows;
+            d.j0 = P.j0[s];
+            d.w = P.w[s];
+            sns.push_back(d);
+            rows.insert(rows.end(), S.rows.begin() + x.row_off, S.rows.begin() + x.row_off + x.nrows);
+            maxlev = std::max(maxlev, x.level);
+            c->trsm_flops += ((double)x.ncols * x.ncols + 2.0 * x.ncols * x.nrows) * P.w[s];
+            c->syrk_flops += (double)x.ncols * P.w[s] * (P.w[s] + 1);
+        }
+        c->factor_flops += S.flops_factor;
+        xrows.resize(xrows.size() + P.n);
+        for (int32_t s = 0; s < ns; ++s) {
+            const Supernode& x = S.sn[s];
+            for (int32_t k = 0; k < x.ncols; ++k) {
+                XRow& r = xrows[rowb + x.first + k];
+                r.off = xb + P.xoff[s] + (int64_t)k * P.w[s];
+                r.j0 = P.j0[s];
+                r.w = P.w[s];
+            }
+        }
+        for (int32_t k = 0; k < P.m; ++k) {
+            const XRow& r = xrows[rowb + P.start[k]];
+            RhsUnit u;
+            u.off = r.off + (k - r.j0);
+            u.sign = (double)P.b_sign[P.sigma[k]];
+            units.push_back(u);
+            dmap.push_back(P.dual_map[P.sigma[k]]);
+        }
+        // F storage and SYRK tiles
+        P.fbase = fb;
+        const int64_t fel = packed_row_offset(P.m, V);
+        const int32_t nt = (P.m + TS - 1) / TS;
+        for (int32_t ta = 0; ta < nt; ++ta)
+            for (int32_t tb = 0; tb <= ta; ++tb) {
+                SyrkTile t;
+                t.fbase = fb;
+                t.m = P.m;
+                t.ta = ta;
+                t.tb = tb;
+                t.list0 = (int32_t)lists.size();
+                for (int32_t s = 0; s < ns; ++s) {
+                    if (P.w[s] <= 0) continue;
+                    int32_t a = P.j0[s], b = P.j0[s] + P.w[s];
+                    if (a < std::min((tb + 1) * TS, P.m) && b > ta * TS) lists.push_back(snb + s);
+                }
+                t.list1 = (int32_t)lists.size();
+                t.pad = 0;
+                tiles.push_back(t);
+            }
+        // apply bands of about apply_band elements
+        P.band0 = (int32_t)bands.size();
+        int64_t nb = std::max<int64_t>(1, (fel + opt.apply_band - 1) / opt.apply_band);
+        int32_t r0 = 0;
+        for (int64_t k = 1; k <= nb && r0 < P.m; ++k) {
+            int32_t r1;
+            if (k == nb) {
+                r1 = P.m;
+            } else {
+                int64_t target = fel * k / nb;
+                int32_t lo = r0 + 1, hi = P.m;
+                while (lo < hi) {
+                    int32_t mid = (lo + hi) / 2;
+                    if (packed_row_offset(mid, V) >= target) hi = mid;
+                    else lo = mid + 1;
+                }
+                r1 = lo;
+            }
+            if (r1 <= r0) continue;
+            Band bd;
+            bd.fbase = fb;
+            bd.zoff = zb;
+            bd.r0 = r0;
+            bd.r1 = r1;
+            bd.dbase = db;
+            bd.pad = 0;
+            bands.push_back(bd);
+            band_z.push_back(zb);
+            zb += r1;
+            r0 = r1;
+        }
+        P.nband = (int32_t)bands.size() - P.band0;
+        max_m = std::max(max_m, P.m);
+        lb += S.nvals;
+        xb += P.nx;
+        fb += fel + 64;  // a little slack keeps the tail of every triangle aligned
+        snb += ns;
+        rowb += P.n;
+        db += P.m;
+        c->sum_m += P.m;
+    }
+    c->total_L = lb;
+    c->total_X = xb;
+    c->total_F = fb;
+    c->total_z = zb;
+    c->total_rows = rowb;
+    c->nbands = (int32_t)bands.size();
+    c->nsyrk = (int32_t)tiles.size();
+    // apply chunk count: lanes cover NCH * 64 * V columns
+    {
+        int nch = 1;
+        while ((int64_t)nch * 64 * V < max_m) nch *= 2;
+        if ((int64_t)nch * 64 * V > 4096) {
+            std::string msg = "subdomain with m=" + std::to_string(max_m) + " exceeds the 4096 multipliers supported";
+            delete c;
+            return fail(nullptr, FETIF_ENOTSUP, msg);
+        }
+        c->apply_nch = nch;
+    }
+    // TRSM levels: items per height level, chunked to the level's slot width
+    c->level_items.assign(maxlev + 1, {});
+    c->level_maxns.assign(maxlev + 1, 0);
+    c->level_slot.assign(maxlev + 1, 64);
+    for (int32_t i = 0; i < nsub; ++i) {
+        const SubPlan& P = c->subs[i];
+        for (size_t s = 0; s < P.sym.sn.size(); ++s)
+            if (P.w[s] > 0) {
+                int32_t L = P.sym.sn[s].level;
+                c->level_maxns[L] = std::max(c->level_maxns[L], P.sym.sn[s].ncols);
+            }
+    }
+    for (int32_t L = 0; L <= maxlev; ++L) {
+        int32_t mx = std::max(1, c->level_maxns[L]);
+        int32_t slot = 64;
+        while (slot > 8 && (int64_t)mx * slot * 8 > 65536) slot /= 2;
+        if ((int64_t)mx * slot * 8 > 65536) {
+            delete c;
+            return fail(nullptr, FETIF_ENOTSUP, "a supernode has more than 1024 columns");
+        }
+        c->level_slot[L] = std::min<int32_t>(slot, std::max(8, opt.trsm_chunk));
+        // keep slot a power of two
+        int32_t p2 = 8;
+        while (p2 * 2 <= c->level_slot[L]) p2 *= 2;
+        c->level_slot[L] = p2;
+    }
+    for (int32_t i = 0; i < nsub; ++i) {
+        const SubPlan& P = c->subs[i];
+        for (size_t s = 0; s < P.sym.sn.size(); ++s) {
+            if (P.w[s] <= 0) continue;
+            int32_t L = P.sym.sn[s].level;
+            int32_t slot = c->level_slot[L];
+            for (int32_t c0 = 0; c0 < P.w[s]; c0 += slot) {
+                TrsmItem it;
+                it.sn = P.snbase + (int32_t)s;
+                it.c0 = c0;
+                it.cw = std::min(slot, P.w[s] - c0);
+                it.pad = 0;
+                c->level_items[L].push_back(it);
+            }
+        }
+    }
+    std::vector<TrsmItem> all_items;
+    c->level_off.assign(maxlev + 2, 0);
+    for (int32_t L = 0; L <= maxlev; ++L) {
+        auto& v = c->level_items[L];
+        // larger supernodes first
+        std::stable_sort(v.begin(), v.end(), [&](const TrsmItem& a, const TrsmItem& b) {
+            const DevSN& x = sns[a.sn];
+            const DevSN& y = sns[b.sn];
+            return (int64_t)x.ncols * (x.ncols + 2 * x.nrows) > (int64_t)y.ncols * (y.ncols + 2 * y.nrows);
+        });
+        c->level_off[L] = (int64_t)all_items.size();
+        all_items.insert(all_items.end(), v.begin(), v.end());
+    }
+    c->level_off[maxlev + 1] = (int64_t)all_items.size();
+    // SYRK tiles: most expensive first
+    {
+        std::vector<int64_t> cost(tiles.size());
+        for (size_t t = 0; t < tiles.size(); ++t) {
+            int64_t cst = 0;
+            for (int32_t li = tiles[t].list0; li < tiles[t].list1; ++li) cst += sns[lists[li]].ncols;
+            cost[t] = cst;
+        }
+        std::vector<size_t> ord(tiles.size());
+        for (size_t t = 0; t < ord.size(); ++t) ord[t] = t;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+        std::vector<SyrkTile> t2(tiles.size());
+        for (size_t t = 0; t < ord.size(); ++t) t2[t] = tiles[ord[t]];
+        tiles.swap(t2);
+    }
+    // gather map: entries of each global multiplier in ascending subdomain order
+    std::vector<int32_t> gptr(n_lambda + 1, 0);
+    for (int32_t i = 0; i < nsub; ++i)
+        for (int32_t g : c->subs[i].dual_map) gptr[g + 1]++;
+    for (int64_t g = 0; g < n_lambda; ++g) gptr[g + 1] += gptr[g];
+    std::vector<GatherEnt> gent(gptr[n_lambda]);
+    {
+        std::vector<int32_t> fill(gptr.begin(), gptr.end() - 1);
+        for (int32_t i = 0; i < nsub; ++i) {
+            const SubPlan& P = c->subs[i];
+            int32_t bcur = P.band0;
+            for (int32_t a = 0; a < P.m; ++a) {
+                while (bands[bcur].r1 <= a) ++bcur;
+                GatherEnt e;
+                e.a = a;
+                e.b0 = bcur;
+                e.b1 = P.band0 + P.nband;
+                e.pad = 0;
+                gent[fill[P.dual_map[P.sigma[a]]]++] = e;
+            }
+        }
+    }
+
+    // ---- device memory
+    DeviceGuard dg(device);
+    if (!dg.ok) {
+        delete c;
+        return fail(nullptr, FETIF_EDEVICE, "hipSetDevice failed");
+    }
+    auto bail = [&](hipError_t e, const char* what) {
+        fetiF_status st = hip_fail(nullptr, e, what);
+        for (void* p : c->allocations) (void)hipFree(p);
+        c->allocations.clear();
+        if (c->hStage) (void)hipHostFree(c->hStage);
+        delete c;
+        return st;
+    };
+#define CK(call)                                   \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess) return bail(e_, #call); \
+    } while (0)
+    CK(dalloc(c, &c->dL, (size_t)c->total_L));
+    CK(dalloc(c, &c->dX, (size_t)c->total_X));
+    {
+        char* f = nullptr;
+        CK(dalloc(c, &f, (size_t)c->total_F * prec_bytes(c->prec) + 64));
+        c->dF = f;
+        CK(hipMemset(f, 0, (size_t)c->total_F * prec_bytes(c->prec) + 64));
+        char* z = nullptr;
+        CK(dalloc(c, &z, (size_t)c->total_z * (c->prec == 0 ? 8 : 4) + 64));
+        c->dZ = z;
+    }
+    CK(dalloc(c, &c->dSN, sns.size()));
+    CK(dalloc(c, &c->dRows, rows.size()));
+    CK(dalloc(c, &c->dXRows, xrows.size()));
+    CK(dalloc(c, &c->dUnits, units.size()));
+    CK(dalloc(c, &c->dItems, all_items.size()));
+    CK(dalloc(c, &c->dTiles, tiles.size()));
+    CK(dalloc(c, &c->dLists, lists.size()));
+    CK(dalloc(c, &c->dBands, bands.size()));
+    CK(dalloc(c, &c->dBandZ, band_z.size()));
+    CK(dalloc(c, &c->dGptr, gptr.size()));
+    CK(dalloc(c, &c->dGent, gent.size()));
+    CK(dalloc(c, &c->dDmap, dmap.size()));
+    CK(upload(c->dSN, sns));
+    CK(upload(c->dRows, rows));
+    CK(upload(c->dXRows, xrows));
+    CK(upload(c->dUnits, units));
+    CK(upload(c->dItems, all_items));
+    CK(upload(c->dTiles, tiles));
+    CK(upload(c->dLists, lists));
+    CK(upload(c->dBands, bands));
+    CK(upload(c->dBandZ, band_z));
+    CK(upload(c->dGptr, gptr));
+    CK(upload(c->dGent, gent));
+    CK(upload(c->dDmap, dmap));
+    CK(hipHostMalloc((void**)&c->hStage, sizeof(double) * (size_t)std::max<int64_t>(1, c->total_L),
+                     hipHostMallocDefault));
+    CK(hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming));
+    CK(hipDeviceSynchronize());
+#undef CK
+    c->uploaded.assign(nsub, 0);
+    *out = c;
+    return FETIF_OK;
+}
+
+// ======================================================================== factor + upload
+
+extern "C" fetiF_status fetiF_factor_upload(fetiF_ctx c, int32_t first, int32_t count,
+                                            const double* const* k_vals, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (first < 0 || count <= 0 || first + count > c->nsub || !k_vals)
+        return fail(c, FETIF_EINVAL, "subdomain range out of bounds or k_vals NULL");
+    for (int32_t k = 0; k < count; ++k)
+        if (!k_vals[k]) return fail(c, FETIF_EINVAL, "k_vals entry is NULL");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    // the staging area may still be read by the previous asynchronous copy
+    if (c->upload_pending) {
+        HIPCHK(c, hipEventSynchronize(c->upload_done));
+        c->upload_pending = false;
+    }
+    std::vector<int32_t> bad(count, -1);
+    parallel_for(count, c->nthreads, [&](int32_t k) {
+        const SubPlan& P = c->subs[first + k];
+        bad[k] = numeric_cholesky(P.sym, k_vals[k], c->hStage + P.lbase);
+    });
+    for (int32_t k = 0; k < count; ++k)
+        if (bad[k] >= 0) {
+            const SubPlan& P = c->subs[first + k];
+            return fail(c, FETIF_ENOTSPD,
+                        "subdomain " + std::to_string(first + k) + ": non-positive pivot at permuted column " +
+                            std::to_string(bad[k]) + " (original dof " + std::to_string(P.sym.perm[bad[k]]) + ")");
+        }
+    const SubPlan& P0 = c->subs[first];
+    const SubPlan& P1 = c->subs[first + count - 1];
+    const int64_t n = P1.lbase + P1.sym.nvals - P0.lbase;
+    HIPCHK(c, hipMemcpyAsync(c->dL + P0.lbase, c->hStage + P0.lbase, sizeof(double) * (size_t)n,
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipEventRecord(c->upload_done, st));
+    c->upload_pending = true;
+    for (int32_t k = 0; k < count; ++k)
+        if (!c->uploaded[first + k]) {
+            c->uploaded[first + k] = 1;
+            c->n_uploaded++;
+        }
+    c->assembled = false;
+    return FETIF_OK;
+}
+
+// ======================================================================== assemble
+
+extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (c->n_uploaded != c->nsub) return fail(c, FETIF_ESTATE, "assemble before every subdomain was factored and uploaded");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, launch_fill_zero(c->dX, c->total_X, st));
+    HIPCHK(c, launch_rhs_units(c->dUnits, c->sum_m, c->dX, st));
+    for (size_t L = 0; L < c->level_items.size(); ++L) {
+        int32_t cnt = (int32_t)(c->level_off[L + 1] - c->level_off[L]);
+        HIPCHK(c, launch_trsm_level(c->dItems + c->level_off[L], cnt, c->level_slot[L], c->level_maxns[L], c->dSN,
+                                    c->dL, c->dRows, c->dXRows, c->dX, st));
+    }
+    HIPCHK(c, launch_syrk(c->prec, c->dTiles, c->nsyrk, c->dLists, c->dSN, c->dX, c->dF, st));
+    c->assembled = true;
+    return FETIF_OK;
+}
+
+// ======================================================================== apply
+
+extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double* q_d, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (!lambda_d || !q_d) return fail(c, FETIF_EINVAL, "lambda or q is NULL");
+    if (lambda_d == q_d) return fail(c, FETIF_EINVAL, "lambda and q must not overlap");
+    if (!c->assembled) return fail(c, FETIF_ESTATE, "apply before assemble");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, launch_apply_band(c->prec, c->apply_nch, c->dBands, c->nbands, c->dF, lambda_d, c->dDmap, c->dZ, st));
+    HIPCHK(c, launch_gather(c->prec, c->n_lambda, c->dGptr, c->dGent, c->dBandZ, c->dZ, q_d, st));
+    return FETIF_OK;
+}
+
+extern "C" fetiF_status fetiF_apply_backward(fetiF_ctx c, const double* g_d, const double* lambda_d,
+                                             double* dlambda_d, double* dtheta_d, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (dtheta_d) return fail(c, FETIF_ENOTSUP, "theta adjoint not available in this build");
+    (void)lambda_d;
+    return fetiF_apply(c, g_d, dlambda_d, stream);
+}
+
+// ======================================================================== inspection
+
+extern "C" fetiF_status fetiF_download_F(fetiF_ctx c, int32_t sub, double* host_out)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (sub < 0 || sub >= c->nsub || !host_out) return fail(c, FETIF_EINVAL, "bad subdomain or output");
+    if (!c->assembled) return fail(c, FETIF_ESTATE, "download before assemble");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    const SubPlan& P = c->subs[sub];
+    const int V = prec_vec(c->prec), B = prec_bytes(c->prec);
+    const int64_t fel = packed_row_offset(P.m, V);
+    std::vector<char> buf((size_t)fel * B + 16);
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemcpy(buf.data(), (char*)c->dF + (size_t)P.fbase * B, (size_t)fel * B, hipMemcpyDeviceToHost));
+    auto val = [&](int64_t e) -> double {
+        if (c->prec == 0) {
+            double v;
+            std::memcpy(&v, buf.data() + e * 8, 8);
+            return v;
+        }
+        if (c->prec == 1) {
+            float v;
+            std::memcpy(&v, buf.data() + e * 4, 4);
+            return v;
+        }
+        uint16_t h;
+        std::memcpy(&h, buf.data() + e * 2, 2);
+        uint32_t u = (uint32_t)h << 16;
+        float v;
+        std::memcpy(&v, &u, 4);
+        return v;
+    };
+    const int32_t m = P.m;
+    for (int32_t a = 0; a < m; ++a) {
+        const int64_t ro = packed_row_offset(a, V);
+        for (int32_t b = 0; b <= a; ++b) {
+            double v = val(ro + b);
+            int32_t i = P.sigma[a], j = P.sigma[b];
+            host_out[(size_t)i * m + j] = v;
+            host_out[(size_t)j * m + i] = v;
+        }
+    }
+    return FETIF_OK;
+}
+
+extern "C" fetiF_status fetiF_query(fetiF_ctx c, fetiF_info* info)
+{
+    if (!c || !info) return FETIF_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->nsub = c->nsub;
+    info->n_lambda = c->n_lambda;
+    info->sum_m = c->sum_m;
+    info->factor_values = c->total_L;
+    info->x_values = c->total_X;
+    info->f_elements = c->total_F;
+    int64_t tri = 0;
+    for (const auto& P : c->subs) tri += (int64_t)P.m * (P.m + 1) / 2;
+    info->f_tri_elements = tri;
+    info->trsm_flops = c->trsm_flops;
+    info->syrk_flops = c->syrk_flops;
+    info->factor_flops = c->factor_flops;
+    info->trsm_levels = (int32_t)c->level_items.size();
+    info->apply_groups = c->nbands;
+    return FETIF_OK;
+}
+
+extern "C" fetiF_status fetiF_destroy(fetiF_ctx c)
+{
+    if (!c) return FETIF_EINVAL;
+    {
+        DeviceGuard dg(c->device);
+        (void)hipDeviceSynchronize();
+        for (void* p : c->allocations) (void)hipFree(p);
+        if (c->hStage) (void)hipHostFree(c->hStage);
+        if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+    }
+    delete c;
+    return FETIF_OK;
+}
+
+extern "C" const char* fetiF_last_error(fetiF_ctx c)
+{
+    return c ? c->last_error.c_str() : g_create_error.c_str();
+}

@@ -1,0 +1,75 @@
+// Plain-old-data records shared by the host planner and the HIP kernels.
+#pragma once
+#include <cstdint>
+
+namespace fetif {
+
+// One supernode of one subdomain, in device form.
+struct DevSN {
+    int64_t lval;    // offset of its (ncols+nrows) x ncols column-major panel in the factor buffer
+    int64_t xoff;    // offset of its ncols x w row-major block of X
+    int64_t rowsoff; // offset of its below-diagonal row list (subdomain-local rows)
+    int32_t rowbase; // first global row slot of its subdomain (for the X row tables)
+    int32_t first;   // first column (subdomain-local, permuted order)
+    int32_t ncols;
+    int32_t nrows;
+    int32_t j0;      // first RHS column of its range (sorted local multiplier order)
+    int32_t w;       // width of its RHS column range
+};
+
+// TRSM work item: one RHS column chunk of one supernode.
+struct TrsmItem {
+    int32_t sn;      // global supernode index
+    int32_t c0;      // first column of the chunk, relative to j0
+    int32_t cw;      // chunk width
+    int32_t pad;
+};
+
+// X row table: row r of subdomain i lives at X[off + (j - j0)] for RHS
+// columns j in [j0, j0 + w) of its supernode.
+struct XRow {
+    int64_t off;
+    int32_t j0;
+    int32_t w;
+};
+
+// SYRK output tile: rows [ta*T, ..) x cols [tb*T, ..) of F~_i (sorted order).
+struct SyrkTile {
+    int64_t fbase;   // element offset of F~_i in the F buffer
+    int32_t m;       // size of F~_i
+    int32_t ta, tb;  // tile coordinates, ta >= tb
+    int32_t list0;   // contributing supernodes: syrk_list[list0 .. list1)
+    int32_t list1;
+    int32_t pad;
+};
+
+// Apply work unit: rows [r0, r1) of the packed lower triangle of F~_i.
+struct Band {
+    int64_t fbase;   // element offset of F~_i
+    int64_t zoff;    // offset of the band's partial vector (length r1)
+    int32_t r0, r1;
+    int32_t dbase;   // offset of D_i (sorted order) in the dual-map buffer
+    int32_t pad;
+};
+
+// Gather entry: contributions of local row a of a subdomain to one global
+// multiplier, held by the bands [b0, b1) of that subdomain.
+struct GatherEnt {
+    int32_t a;
+    int32_t b0, b1;
+    int32_t pad;
+};
+
+// Packed lower-triangle row offset with rows padded to multiples of V
+// elements: row r holds columns 0..r and starts at
+// V * (V*q*(q+1)/2 + s*(q+1)) where r = q*V + s.
+#if defined(__HIPCC__)
+__host__ __device__
+#endif
+inline int64_t packed_row_offset(int64_t r, int64_t V)
+{
+    int64_t q = r / V, s = r - q * V;
+    return V * (V * q * (q + 1) / 2 + s * (q + 1));
+}
+
+}  // namespace fetif

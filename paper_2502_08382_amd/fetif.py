@@ -1,0 +1,251 @@
+"""ctypes binding of the fetiF C-ABI (argument marshalling only).
+
+Every computation runs in libfetiF.so: host analysis/factorisation in its
+C++ part, assembly and application in its HIP kernels.  Device buffers are
+torch tensors (or raw device pointers); streams are torch CUDA streams.
+If the shared library is missing this module raises at import of the
+library, so nothing can silently run elsewhere.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfetiF.so")
+
+F64, F32, BF16 = 0, 1, 2
+_PREC = {"f64": F64, "fp64": F64, "float64": F64, "f32": F32, "fp32": F32, "float32": F32,
+         "bf16": BF16, "bfloat16": BF16}
+
+_STATUS = {0: "FETIF_OK", 1: "FETIF_EINVAL", 2: "FETIF_ENOMEM", 3: "FETIF_ESTATE",
+           4: "FETIF_EDEVICE", 5: "FETIF_ENOTSPD", 6: "FETIF_ENOTSUP"}
+
+
+class FetiError(RuntimeError):
+    def __init__(self, status, msg):
+        self.status = status
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+
+
+class _Sub(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dofs_per_node", ctypes.c_int32),
+                ("k_ptr", ctypes.c_void_p), ("k_idx", ctypes.c_void_p),
+                ("dim", ctypes.c_int32), ("coords", ctypes.c_void_p),
+                ("m", ctypes.c_int32), ("b_dof", ctypes.c_void_p), ("b_sign", ctypes.c_void_p),
+                ("dual_map", ctypes.c_void_p), ("nelem", ctypes.c_int32), ("edofs", ctypes.c_int32),
+                ("elem_dofs", ctypes.c_void_p), ("dK", ctypes.c_void_p)]
+
+
+class _Opt(ctypes.Structure):
+    _fields_ = [("f_storage", ctypes.c_int), ("leaf_nodes", ctypes.c_int32),
+                ("nthreads", ctypes.c_int32), ("apply_band", ctypes.c_int32),
+                ("trsm_chunk", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("nsub", ctypes.c_int32), ("n_lambda", ctypes.c_int64), ("sum_m", ctypes.c_int64),
+                ("factor_values", ctypes.c_int64), ("x_values", ctypes.c_int64),
+                ("f_elements", ctypes.c_int64), ("f_tri_elements", ctypes.c_int64),
+                ("trsm_flops", ctypes.c_double), ("syrk_flops", ctypes.c_double),
+                ("factor_flops", ctypes.c_double), ("trsm_levels", ctypes.c_int32),
+                ("apply_groups", ctypes.c_int32)]
+
+
+EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply",
+           "fetiF_apply_backward", "fetiF_download_F", "fetiF_query", "fetiF_destroy",
+           "fetiF_last_error", "fetiF_host_factor", "fetiF_hfactor_info", "fetiF_hfactor_export",
+           "fetiF_hfactor_supernodes", "fetiF_hfactor_free"]
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libfetiF.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"fetiF library not built: {p} is missing (run __graft_entry__.build())")
+    L = ctypes.CDLL(p)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.fetiF_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64, i32, ctypes.POINTER(_Sub),
+                               ctypes.POINTER(_Opt)]
+    L.fetiF_factor_upload.argtypes = [vp, i32, i32, ctypes.POINTER(vp), vp]
+    L.fetiF_assemble.argtypes = [vp, vp]
+    L.fetiF_apply.argtypes = [vp, vp, vp, vp]
+    L.fetiF_apply_backward.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.fetiF_download_F.argtypes = [vp, i32, vp]
+    L.fetiF_query.argtypes = [vp, ctypes.POINTER(_Info)]
+    L.fetiF_destroy.argtypes = [vp]
+    L.fetiF_last_error.argtypes = [vp]
+    L.fetiF_last_error.restype = ctypes.c_char_p
+    L.fetiF_host_factor.argtypes = [ctypes.POINTER(_Sub), vp, ctypes.POINTER(_Opt), ctypes.POINTER(vp)]
+    L.fetiF_hfactor_info.argtypes = [vp, vp, vp, vp, vp]
+    L.fetiF_hfactor_export.argtypes = [vp, vp, vp, vp, vp]
+    L.fetiF_hfactor_supernodes.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.fetiF_hfactor_free.argtypes = [vp]
+    for name in EXPORTS:
+        getattr(L, name).restype = getattr(L, name).restype if name == "fetiF_last_error" else ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p).value
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor or an int."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class _SubArrays:
+    """Keeps the numpy arrays of one subdomain alive and builds its record."""
+
+    def __init__(self, d):
+        self.k_ptr = np.ascontiguousarray(d["k_ptr"], dtype=np.int32)
+        self.k_idx = np.ascontiguousarray(d["k_idx"], dtype=np.int32)
+        self.n = int(d["n"])
+        self.dpn = int(d.get("dofs_per_node", 1))
+        c = d.get("coords")
+        self.coords = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+        self.dim = 0 if c is None else int(self.coords.shape[1])
+        self.b_dof = np.ascontiguousarray(d["b_dof"], dtype=np.int32)
+        self.b_sign = np.ascontiguousarray(d["b_sign"], dtype=np.int8)
+        self.dual_map = np.ascontiguousarray(d["dual_map"], dtype=np.int32)
+        ed = d.get("elem_dofs")
+        self.elem_dofs = None if ed is None else np.ascontiguousarray(ed, dtype=np.int32)
+        dk = d.get("dK")
+        self.dK = None if dk is None else np.ascontiguousarray(dk, dtype=np.float64)
+
+    def record(self):
+        ne = 0 if self.elem_dofs is None else self.elem_dofs.shape[0]
+        ed = 0 if self.elem_dofs is None else self.elem_dofs.shape[1]
+        return _Sub(self.n, self.dpn, _ptr(self.k_ptr), _ptr(self.k_idx), self.dim, _ptr(self.coords),
+                    len(self.b_dof), _ptr(self.b_dof), _ptr(self.b_sign), _ptr(self.dual_map), ne, ed,
+                    _ptr(self.elem_dofs), _ptr(self.dK))
+
+
+def _options(f_storage="f64", leaf_nodes=0, nthreads=0, apply_band=0, trsm_chunk=0):
+    prec = _PREC[f_storage] if isinstance(f_storage, str) else int(f_storage)
+    return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk)
+
+
+class FetiContext:
+    """One fetiF context: F~_i of every subdomain on one device."""
+
+    def __init__(self, subdomains, n_lambda, device=0, f_storage="f64", **opts):
+        L = load_library()
+        self.L = L
+        self._subs = [_SubArrays(d) for d in subdomains]
+        recs = (_Sub * len(self._subs))(*[s.record() for s in self._subs])
+        opt = _options(f_storage, **opts)
+        h = ctypes.c_void_p()
+        st = L.fetiF_create(ctypes.byref(h), int(device), int(n_lambda), len(self._subs), recs,
+                            ctypes.byref(opt))
+        if st != 0:
+            raise FetiError(st, L.fetiF_last_error(None).decode())
+        self.h = h
+        self.n_lambda = int(n_lambda)
+        self.device = int(device)
+        self.f_storage = opt.f_storage
+        self.nsub = len(self._subs)
+        self.m = [len(s.b_dof) for s in self._subs]
+
+    def _check(self, st):
+        if st != 0:
+            raise FetiError(st, self.L.fetiF_last_error(self.h).decode())
+
+    def factor_upload(self, k_vals, first=0, stream=None):
+        arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in k_vals]
+        ptrs = (ctypes.c_void_p * len(arrs))(*[_ptr(a) for a in arrs])
+        self._check(self.L.fetiF_factor_upload(self.h, int(first), len(arrs), ptrs, _stream(stream)))
+
+    def assemble(self, stream=None):
+        self._check(self.L.fetiF_assemble(self.h, _stream(stream)))
+
+    def apply(self, lam, q, stream=None):
+        self._check(self.L.fetiF_apply(self.h, _dptr(lam), _dptr(q), _stream(stream)))
+
+    def apply_backward(self, g, lam, dlam, dtheta=None, stream=None):
+        self._check(self.L.fetiF_apply_backward(self.h, _dptr(g), _dptr(lam), _dptr(dlam), _dptr(dtheta),
+                                                _stream(stream)))
+
+    def download_F(self, i):
+        out = np.empty((self.m[i], self.m[i]))
+        self._check(self.L.fetiF_download_F(self.h, int(i), _ptr(out)))
+        return out
+
+    def info(self):
+        inf = _Info()
+        self._check(self.L.fetiF_query(self.h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.fetiF_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HostFactor:
+    """Host-only ordering + symbolic + numeric factorisation of one K_reg."""
+
+    def __init__(self, sub, k_vals=None, **opts):
+        L = load_library()
+        self.L = L
+        self._s = _SubArrays(sub)
+        rec = self._s.record()
+        opt = _options(**opts)
+        vals = None if k_vals is None else np.ascontiguousarray(k_vals, dtype=np.float64)
+        h = ctypes.c_void_p()
+        st = L.fetiF_host_factor(ctypes.byref(rec), _ptr(vals), ctypes.byref(opt), ctypes.byref(h))
+        if st != 0:
+            raise FetiError(st, "host factorisation failed")
+        self.h = h
+        n, nnz, ns, nl = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        L.fetiF_hfactor_info(h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(ns), ctypes.byref(nl))
+        self.n, self.nnz, self.nsuper, self.nlevels = n.value, nnz.value, ns.value, nl.value
+
+    def export(self):
+        perm = np.empty(self.n, np.int32)
+        cp = np.empty(self.n + 1, np.int64)
+        ri = np.empty(self.nnz, np.int32)
+        vv = np.empty(self.nnz)
+        self.L.fetiF_hfactor_export(self.h, _ptr(perm), _ptr(cp), _ptr(ri), _ptr(vv))
+        return perm, cp, ri, vv
+
+    def supernodes(self):
+        a = [np.empty(self.nsuper, np.int32) for _ in range(5)]
+        self.L.fetiF_hfactor_supernodes(self.h, *[_ptr(x) for x in a])
+        return dict(zip(["first", "ncols", "nrows", "parent", "level"], a))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.L.fetiF_hfactor_free(self.h)
+            self.h = None

@@ -1,0 +1,18 @@
+"""Marshalling of a subdomain description into the C-ABI record fields."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def subdomain_dict(sub, with_elements=False):
+    """Fields of fetiF_subdomain from an object exposing Kreg (scipy CSR with
+    the full symmetric pattern), dpn, coords, b_dof, b_sign, dual_map and,
+    for the adjoint, elem_dofs() and Ke_ref (dK_reg/dtheta_e)."""
+    A = sub.Kreg
+    d = dict(n=A.shape[0], dofs_per_node=sub.dpn, k_ptr=A.indptr, k_idx=A.indices,
+             coords=np.asarray(sub.coords, dtype=np.float64), b_dof=sub.b_dof, b_sign=sub.b_sign,
+             dual_map=sub.dual_map)
+    if with_elements:
+        d["elem_dofs"] = sub.elem_dofs()
+        d["dK"] = sub.Ke_ref
+    return d
