@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the explicit FETI dual operator on one MI355X.
+
+Workload (default): 3D steady heat, 96^3 trilinear hexes torn into 8^3 = 512
+subdomains of 12^3 elements (2197 DOFs each), lognormal(0, 0.5)
+conductivity, Dirichlet on z=0; seeded synthetic data.  One step follows
+the paper's multi-step skeleton (Alg. 2): numeric factorisation of every
+K_reg,i on host threads + copy of the factor values, assembly of every F~_i
+on the GPU (RHS init, supernodal TRSM, SYRK), then 200 applications of
+F = sum_i D_i^T F~_i D_i (the operator products of 200 solver iterations).
+
+Printed: one JSON line with the apply bandwidth as `value`, the assembly
+time per 1000 subdomains, the break-even iteration count against the CPU
+oracle's implicit apply, the roofline of the dominant kernel and the CPU
+oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
+FP64_PEAK_TFS = 78.6         # MI355X dense FP64 (vector and matrix)
+METRIC = "F assembly ms/1k subdomains; F·λ apply GB/s; break-even iters vs implicit"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2, help="workload 1..5")
+    ap.add_argument("--iters", type=int, default=200, help="applies per step")
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--cpu-sample", type=int, default=128, help="subdomains timed by the CPU oracle")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--apply-band", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
+              "is described in DESIGN.md and is not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from synth import config_problem, CONFIGS
+    from paper_2502_08382_amd import FetiContext, subdomain_dict
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    prob = config_problem(args.config)
+    log(f"problem C{args.config}: {prob.nsub} subdomains, n_lambda={prob.n_lambda}, "
+        f"gen {time.time() - t0:.1f}s")
+    t0 = time.time()
+    ctx = FetiContext([subdomain_dict(s) for s in prob.subs], prob.n_lambda, device=0,
+                      f_storage=args.prec, apply_band=args.apply_band)
+    info = ctx.info()
+    log(f"create (ordering + symbolic + plan + device structures) {time.time() - t0:.1f}s; "
+        f"L values {info['factor_values']:.3g}, X values {info['x_values']:.3g}, "
+        f"trsm flops {info['trsm_flops']:.3g}, syrk flops {info['syrk_flops']:.3g}, "
+        f"levels {info['trsm_levels']}, apply groups {info['apply_groups']}")
+    kvals = [s.Kreg.data for s in prob.subs]
+    lam = torch.tensor(prob.lam, dtype=torch.float64, device=dev)
+    q = torch.empty_like(lam)
+    stream = torch.cuda.current_stream()
+
+    host_factor_s = []
+
+    def step():
+        th = time.time()
+        ctx.factor_upload(kvals, stream=stream)
+        host_factor_s.append(time.time() - th)
+        ctx.assemble(stream=stream)
+        x, y = lam, q
+        for _ in range(args.iters):
+            ctx.apply(x, y, stream=stream)
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {w} done")
+    host_factor_s.clear()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ctx.profile(False)
+    prof = ctx.profile_read(reset=True)
+    log(f"timed {args.steps} steps in {elapsed:.3f}s; phases {prof}")
+
+    K = args.steps
+    ms = {p: v[0] for p, v in prof.items()}
+    cnt = {p: max(1, v[1]) for p, v in prof.items()}
+    t_upload = ms["factor_copy"] / cnt["factor_copy"]
+    t_asm = (ms["rhs_init"] + ms["trsm"] + ms["syrk"]) / K
+    t_band = ms["apply_band"] / cnt["apply_band"]
+    t_gather = ms["apply_gather"] / cnt["apply_gather"]
+    t_apply = t_band + t_gather
+    bytes_el = {"f64": 8, "f32": 4, "bf16": 2}[args.prec]
+    sum_m = info["sum_m"]
+    tri_bytes = bytes_el * info["f_tri_elements"]
+    band_bytes = tri_bytes + 12 * sum_m            # triangle + lambda[D_i] gather (value + index)
+    apply_bytes = band_bytes + 8 * prob.n_lambda   # + the q write of the gather kernel
+    apply_gbs = apply_bytes / (t_apply * 1e-3) / 1e9
+    band_gbs = band_bytes / (t_band * 1e-3) / 1e9
+    asm_flops = info["trsm_flops"] + info["syrk_flops"]
+
+    result = {
+        "metric": METRIC,
+        "value": round(apply_gbs, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / K * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32 (F storage; f64 assembly)", "bf16": "bf16 (F storage; f64 assembly)"}[args.prec],
+        "data": "synthetic (seeded structured-grid FETI problem)",
+        "config": {"workload": CONFIGS[args.config], "subdomains": prob.nsub,
+                   "dofs_per_subdomain": int(prob.subs[0].n), "n_lambda": int(prob.n_lambda),
+                   "sum_m": int(sum_m), "applies_per_step": args.iters, "f_storage": args.prec},
+        "assembly_ms_per_1k_subdomains": round(1000.0 * t_asm / prob.nsub, 3),
+        "assembly_ms": round(t_asm, 3),
+        "assembly_phase_ms": {"rhs_init": round(ms["rhs_init"] / K, 4), "trsm": round(ms["trsm"] / K, 4),
+                              "syrk": round(ms["syrk"] / K, 4)},
+        "assembly_tflops": round(asm_flops / (t_asm * 1e-3) / 1e12, 3),
+        "assembly_mfma_frac": round(asm_flops / (t_asm * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
+        "apply_ms": round(t_apply, 4),
+        "apply_band_ms": round(t_band, 4),
+        "apply_gather_ms": round(t_gather, 4),
+        "factor_copy_ms": round(t_upload, 3),
+        "host_factor_s": round(float(np.mean(host_factor_s)), 3) if host_factor_s else None,
+        "roofline": {"bound": "hbm", "kernel": "apply_band_kernel", "achieved": round(band_gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(band_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": int(band_bytes)},
+    }
+
+    # ---- CPU oracle: implicit apply on host threads, bounded sample
+    if not args.no_cpu:
+        from oracle import implicit as orc
+        S = min(args.cpu_sample, prob.nsub)
+        sample = prob.subs[:S]
+        nthreads = len(os.sched_getaffinity(0))
+        t0 = time.time()
+        I = orc.ImplicitCPU(sample, prob.n_lambda, nthreads=nthreads)
+        I.factor()
+        log(f"cpu oracle: ordering + factorisation of {S} subdomains {time.time() - t0:.1f}s")
+        I.apply(prob.lam)
+        reps = 0
+        tc = time.perf_counter()
+        while True:
+            I.apply(prob.lam)
+            reps += 1
+            if time.perf_counter() - tc > 5.0 and reps >= 3:
+                break
+        t_cpu_sample = (time.perf_counter() - tc) / reps
+        t_cpu = t_cpu_sample * prob.nsub / S * 1e3   # ms per apply of the whole workload
+        cpu_gbs = apply_bytes / (t_cpu * 1e-3) / 1e9
+        result["cpu_baseline"] = {
+            "value": round(cpu_gbs, 3), "unit": "GB/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"implicit apply (sparse Cholesky fwd+bwd solves, MMD order) of {S} of "
+                      f"{prob.nsub} subdomains, {reps} repetitions, scaled x{prob.nsub / S:g}; "
+                      f"value = the explicit operator's algorithmic bytes per apply / CPU time per apply",
+            "ms_per_apply": round(t_cpu, 3)}
+        denom = t_cpu - t_apply
+        result["break_even_iters"] = (math.ceil((t_upload + t_asm) / denom) if denom > 0 else None)
+        result["break_even_detail"] = {"t_upload_ms": round(t_upload, 3), "t_assembly_ms": round(t_asm, 3),
+                                       "t_impl_cpu_ms": round(t_cpu, 3), "t_apply_gpu_ms": round(t_apply, 4)}
+    print(json.dumps(result), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -169,6 +169,18 @@ typedef struct {
 
 fetiF_status fetiF_query(fetiF_ctx ctx, fetiF_info* info);
 
+/* Phase timing with HIP events recorded on the caller's stream around each
+ * device phase: 0 factor copy (H2D), 1 RHS initialisation, 2 forward TRSM
+ * (all levels), 3 SYRK, 4 apply band kernel, 5 apply gather kernel,
+ * 6 backward solves and adjoint.  fetiF_profile_enable(ctx, 1) starts
+ * recording (it inserts event records, so keep it off inside captured
+ * graphs); fetiF_profile_read waits for the recorded events and adds their
+ * elapsed times into ms[phase] / counts[phase] for phase < nphases, then
+ * forgets them when reset != 0. */
+#define FETIF_NPHASES 7
+fetiF_status fetiF_profile_enable(fetiF_ctx ctx, int on);
+fetiF_status fetiF_profile_read(fetiF_ctx ctx, int reset, double* ms, int64_t* counts, int32_t nphases);
+
 /* Release everything owned by the context (synchronises its device). */
 fetiF_status fetiF_destroy(fetiF_ctx ctx);
 

@@ -114,6 +114,16 @@ struct fetiF_ctx_s {
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     std::vector<void*> allocations;
+    // phase timing
+    struct Rec {
+        int phase;
+        hipEvent_t a, b;
+    };
+    bool profiling = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> ev_pool;
+    double prof_ms[FETIF_NPHASES] = {0};
+    int64_t prof_cnt[FETIF_NPHASES] = {0};
     // state
     std::vector<uint8_t> uploaded;
     int32_t n_uploaded = 0;
@@ -142,6 +152,40 @@ fetiF_status hip_fail(fetiF_ctx c, hipError_t e, const char* what)
     }
     return FETIF_EDEVICE;
 }
+
+// Event pair around one device phase when profiling is on.
+struct PhaseTimer {
+    fetiF_ctx c;
+    hipStream_t st;
+    int phase;
+    hipEvent_t b = nullptr;
+    hipError_t err = hipSuccess;
+    hipEvent_t get()
+    {
+        if (!c->ev_pool.empty()) {
+            hipEvent_t e = c->ev_pool.back();
+            c->ev_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        err = hipEventCreate(&e);
+        return e;
+    }
+    PhaseTimer(fetiF_ctx c_, hipStream_t s_, int ph) : c(c_), st(s_), phase(ph)
+    {
+        if (!c->profiling) return;
+        hipEvent_t a = get();
+        b = get();
+        if (err == hipSuccess) err = hipEventRecord(a, st);
+        c->recs.push_back({phase, a, b});
+    }
+    hipError_t stop()
+    {
+        if (!c->profiling || !b) return err;
+        if (err == hipSuccess) err = hipEventRecord(b, st);
+        return err;
+    }
+};
 
 #define HIPCHK(ctx, call)                                         \
     do {                                                          \
@@ -266,11 +310,6 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     fetiF_options opt;
     options_defaults(opt_in, opt);
     if (opt.f_storage < FETIF_F64 || opt.f_storage > FETIF_BF16) return fail(nullptr, FETIF_EINVAL, "bad f_storage");
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
-        return fail(nullptr, FETIF_EDEVICE, "no HIP device available");
-    if (device < 0 || device >= ndev) return fail(nullptr, FETIF_EINVAL, "device ordinal out of range");
-
     fetiF_ctx c = new (std::nothrow) fetiF_ctx_s();
     if (!c) return fail(nullptr, FETIF_ENOMEM, "host allocation failed");
     c->device = device;
@@ -530,6 +569,17 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     }
 
     // ---- device memory
+    {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+            delete c;
+            return fail(nullptr, FETIF_EDEVICE, "no HIP device available");
+        }
+        if (device < 0 || device >= ndev) {
+            delete c;
+            return fail(nullptr, FETIF_EINVAL, "device ordinal out of range");
+        }
+    }
     DeviceGuard dg(device);
     if (!dg.ok) {
         delete c;
@@ -627,8 +677,10 @@ extern "C" fetiF_status fetiF_factor_upload(fetiF_ctx c, int32_t first, int32_t 
     const SubPlan& P0 = c->subs[first];
     const SubPlan& P1 = c->subs[first + count - 1];
     const int64_t n = P1.lbase + P1.sym.nvals - P0.lbase;
+    PhaseTimer t0(c, st, 0);
     HIPCHK(c, hipMemcpyAsync(c->dL + P0.lbase, c->hStage + P0.lbase, sizeof(double) * (size_t)n,
                              hipMemcpyHostToDevice, st));
+    HIPCHK(c, t0.stop());
     HIPCHK(c, hipEventRecord(c->upload_done, st));
     c->upload_pending = true;
     for (int32_t k = 0; k < count; ++k)
@@ -650,14 +702,20 @@ extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
+    PhaseTimer t1(c, st, 1);
     HIPCHK(c, launch_fill_zero(c->dX, c->total_X, st));
     HIPCHK(c, launch_rhs_units(c->dUnits, c->sum_m, c->dX, st));
+    HIPCHK(c, t1.stop());
+    PhaseTimer t2(c, st, 2);
     for (size_t L = 0; L < c->level_items.size(); ++L) {
         int32_t cnt = (int32_t)(c->level_off[L + 1] - c->level_off[L]);
         HIPCHK(c, launch_trsm_level(c->dItems + c->level_off[L], cnt, c->level_slot[L], c->level_maxns[L], c->dSN,
                                     c->dL, c->dRows, c->dXRows, c->dX, st));
     }
+    HIPCHK(c, t2.stop());
+    PhaseTimer t3(c, st, 3);
     HIPCHK(c, launch_syrk(c->prec, c->dTiles, c->nsyrk, c->dLists, c->dSN, c->dX, c->dF, st));
+    HIPCHK(c, t3.stop());
     c->assembled = true;
     return FETIF_OK;
 }
@@ -674,8 +732,12 @@ extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double*
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
+    PhaseTimer t4(c, st, 4);
     HIPCHK(c, launch_apply_band(c->prec, c->apply_nch, c->dBands, c->nbands, c->dF, lambda_d, c->dDmap, c->dZ, st));
+    HIPCHK(c, t4.stop());
+    PhaseTimer t5(c, st, 5);
     HIPCHK(c, launch_gather(c->prec, c->n_lambda, c->dGptr, c->dGent, c->dBandZ, c->dZ, q_d, st));
+    HIPCHK(c, t5.stop());
     return FETIF_OK;
 }
 
@@ -756,12 +818,51 @@ extern "C" fetiF_status fetiF_query(fetiF_ctx c, fetiF_info* info)
     return FETIF_OK;
 }
 
+extern "C" fetiF_status fetiF_profile_enable(fetiF_ctx c, int on)
+{
+    if (!c) return FETIF_EINVAL;
+    c->profiling = on != 0;
+    return FETIF_OK;
+}
+
+extern "C" fetiF_status fetiF_profile_read(fetiF_ctx c, int reset, double* ms, int64_t* counts, int32_t nphases)
+{
+    if (!c) return FETIF_EINVAL;
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    for (auto& r : c->recs) {
+        HIPCHK(c, hipEventSynchronize(r.b));
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, r.a, r.b));
+        c->prof_ms[r.phase] += t;
+        c->prof_cnt[r.phase] += 1;
+        c->ev_pool.push_back(r.a);
+        c->ev_pool.push_back(r.b);
+    }
+    c->recs.clear();
+    for (int32_t p = 0; p < nphases && p < FETIF_NPHASES; ++p) {
+        if (ms) ms[p] = c->prof_ms[p];
+        if (counts) counts[p] = c->prof_cnt[p];
+    }
+    if (reset)
+        for (int p = 0; p < FETIF_NPHASES; ++p) {
+            c->prof_ms[p] = 0.0;
+            c->prof_cnt[p] = 0;
+        }
+    return FETIF_OK;
+}
+
 extern "C" fetiF_status fetiF_destroy(fetiF_ctx c)
 {
     if (!c) return FETIF_EINVAL;
     {
         DeviceGuard dg(c->device);
         (void)hipDeviceSynchronize();
+        for (auto& r : c->recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
         for (void* p : c->allocations) (void)hipFree(p);
         if (c->hStage) (void)hipHostFree(c->hStage);
         if (c->upload_done) (void)hipEventDestroy(c->upload_done);

@@ -57,7 +57,10 @@ class _Info(ctypes.Structure):
 EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply",
            "fetiF_apply_backward", "fetiF_download_F", "fetiF_query", "fetiF_destroy",
            "fetiF_last_error", "fetiF_host_factor", "fetiF_hfactor_info", "fetiF_hfactor_export",
-           "fetiF_hfactor_supernodes", "fetiF_hfactor_free"]
+           "fetiF_hfactor_supernodes", "fetiF_hfactor_free", "fetiF_profile_enable",
+           "fetiF_profile_read"]
+
+PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "backward"]
 
 _lib = None
 
@@ -88,6 +91,8 @@ def load_library(path=None):
     L.fetiF_hfactor_export.argtypes = [vp, vp, vp, vp, vp]
     L.fetiF_hfactor_supernodes.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fetiF_hfactor_free.argtypes = [vp]
+    L.fetiF_profile_enable.argtypes = [vp, ctypes.c_int]
+    L.fetiF_profile_read.argtypes = [vp, ctypes.c_int, vp, vp, i32]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype if name == "fetiF_last_error" else ctypes.c_int
     _lib = L
@@ -200,6 +205,17 @@ class FetiContext:
         inf = _Info()
         self._check(self.L.fetiF_query(self.h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def profile(self, on=True):
+        """Record HIP events around every device phase (see PHASES)."""
+        self._check(self.L.fetiF_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self, reset=True):
+        """{phase: (total ms, launches)} of the recorded phases (waits for them)."""
+        ms = np.zeros(len(PHASES))
+        cnt = np.zeros(len(PHASES), np.int64)
+        self._check(self.L.fetiF_profile_read(self.h, 1 if reset else 0, _ptr(ms), _ptr(cnt), len(PHASES)))
+        return {p: (float(ms[i]), int(cnt[i])) for i, p in enumerate(PHASES)}
 
     def close(self):
         if getattr(self, "h", None):
