@@ -48,6 +48,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128, help="subdomains timed by the CPU oracle")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--apply-band", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the apply autotuner")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -79,6 +80,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     host_factor_s = []
+    tune = None
 
     def step():
         th = time.time()
@@ -93,6 +95,12 @@ def main():
         step()
         torch.cuda.synchronize()
         log(f"warmup step {w} done")
+        if w == 0 and not args.no_tune:
+            from paper_2502_08382_amd.autotune import tune_apply
+            tt = time.time()
+            tune = tune_apply(ctx, lam, q, stream=stream)
+            log(f"apply autotune {time.time() - tt:.1f}s: band={tune['band']} rows={tune['rows']} "
+                f"nontemporal={tune['nontemporal']} ({tune['ms'] * 1e3:.1f} us)")
     host_factor_s.clear()
     ctx.profile(True)
     ctx.profile_read(reset=True)
@@ -149,6 +157,7 @@ def main():
         "apply_band_ms": round(t_band, 4),
         "apply_gather_ms": round(t_gather, 4),
         "factor_copy_ms": round(t_upload, 3),
+        "apply_shape": None if tune is None else {k: tune[k] for k in ("band", "rows", "nontemporal")},
         "host_factor_s": round(float(np.mean(host_factor_s)), 3) if host_factor_s else None,
         "roofline": {"bound": "hbm", "kernel": "apply_band_kernel", "achieved": round(band_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(band_gbs / HBM_PEAK_GBS, 4),

@@ -99,8 +99,10 @@ typedef struct {
     fetiF_prec f_storage; /* storage precision of F~_i (default FP64) */
     int32_t leaf_nodes;   /* nested-dissection leaf size in nodes (default 24) */
     int32_t nthreads;     /* host threads for analysis/factorisation (default: all) */
-    int32_t apply_band;   /* elements of F~ per apply work-group (default 32768) */
+    int32_t apply_band;   /* stored elements of F~ per apply work-group (default 131072) */
     int32_t trsm_chunk;   /* RHS columns per TRSM work-group (default 64) */
+    int32_t apply_rows;   /* rows of F~ per wavefront pass in apply, 1 or 2 (default 2) */
+    int32_t apply_nontemporal; /* 1: stream F~ with non-temporal loads (default), 0: cached */
 } fetiF_options;
 
 /* Preparation (Alg. 2, "preparation"; Sec. IV-B "Preparation"): nested
@@ -135,6 +137,13 @@ fetiF_status fetiF_assemble(fetiF_ctx ctx, void* stream);
  * a fixed order (bitwise reproducible).  Allocates nothing and does no host
  * copy; capturable in a HIP graph.  lambda_d and q_d must not overlap. */
 fetiF_status fetiF_apply(fetiF_ctx ctx, const double* lambda_d, double* q_d, void* stream);
+
+/* Re-plan the application (tuning hook): band_elems > 0 sets the stored
+ * elements of F~ per work-group (the band/gather tables are rebuilt, which
+ * synchronises the device), rows (1 or 2; 0 keeps) the rows per wavefront
+ * pass, nontemporal (0/1; -1 keeps) the load policy for F~.  The result of
+ * fetiF_apply does not depend on these up to summation order. */
+fetiF_status fetiF_set_apply(fetiF_ctx ctx, int32_t band_elems, int32_t rows, int32_t nontemporal);
 
 /* Reverse mode of J = g^T F(theta) lambda for the applied operator:
  *   dlambda_d = F g_d   (F is symmetric),

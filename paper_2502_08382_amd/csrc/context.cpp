@@ -114,6 +114,7 @@ struct fetiF_ctx_s {
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     std::vector<void*> allocations;
+    std::vector<void*> apply_allocs;  // buffers of the current apply plan
     // phase timing
     struct Rec {
         int phase;
@@ -298,6 +299,131 @@ bool plan_subdomain(const fetiF_subdomain& in, const fetiF_options& opt, int64_t
 
 }  // namespace
 
+// ======================================================================== apply plan
+
+namespace {
+
+struct ApplyPlan {
+    std::vector<Band> bands;
+    std::vector<int64_t> band_z;
+    std::vector<int32_t> gptr;
+    std::vector<GatherEnt> gent;
+    int64_t total_z = 0;
+};
+
+// Bands of about band_elems stored elements per subdomain triangle (whole
+// rows, boundaries at equal shares of the packed storage) and the gather map:
+// for every global multiplier, the (subdomain, row) entries in ascending
+// subdomain order with the bands whose partials hold that row.
+void plan_apply(fetiF_ctx c, int32_t band_elems, ApplyPlan& A)
+{
+    const int V = prec_vec(c->prec);
+    int64_t zb = 0;
+    for (int32_t i = 0; i < c->nsub; ++i) {
+        SubPlan& P = c->subs[i];
+        const int64_t fel = packed_row_offset(P.m, V);
+        P.band0 = (int32_t)A.bands.size();
+        int64_t nb = std::max<int64_t>(1, (fel + band_elems - 1) / band_elems);
+        int32_t r0 = 0;
+        for (int64_t k = 1; k <= nb && r0 < P.m; ++k) {
+            int32_t r1;
+            if (k == nb) {
+                r1 = P.m;
+            } else {
+                int64_t target = fel * k / nb;
+                int32_t lo = r0 + 1, hi = P.m;
+                while (lo < hi) {
+                    int32_t mid = (lo + hi) / 2;
+                    if (packed_row_offset(mid, V) >= target) hi = mid;
+                    else lo = mid + 1;
+                }
+                r1 = lo;
+            }
+            if (r1 <= r0) continue;
+            Band bd;
+            bd.fbase = P.fbase;
+            bd.zoff = zb;
+            bd.r0 = r0;
+            bd.r1 = r1;
+            bd.dbase = P.dbase;
+            bd.pad = 0;
+            A.bands.push_back(bd);
+            A.band_z.push_back(zb);
+            zb += r1;
+            r0 = r1;
+        }
+        P.nband = (int32_t)A.bands.size() - P.band0;
+    }
+    A.total_z = zb;
+    const int64_t nl = c->n_lambda;
+    A.gptr.assign(nl + 1, 0);
+    for (int32_t i = 0; i < c->nsub; ++i)
+        for (int32_t g : c->subs[i].dual_map) A.gptr[g + 1]++;
+    for (int64_t g = 0; g < nl; ++g) A.gptr[g + 1] += A.gptr[g];
+    A.gent.resize(A.gptr[nl]);
+    std::vector<int32_t> fill(A.gptr.begin(), A.gptr.end() - 1);
+    for (int32_t i = 0; i < c->nsub; ++i) {
+        const SubPlan& P = c->subs[i];
+        int32_t bcur = P.band0;
+        for (int32_t a = 0; a < P.m; ++a) {
+            while (A.bands[bcur].r1 <= a) ++bcur;
+            GatherEnt e;
+            e.a = a;
+            e.b0 = bcur;
+            e.b1 = P.band0 + P.nband;
+            e.pad = 0;
+            A.gent[fill[P.dual_map[P.sigma[a]]]++] = e;
+        }
+    }
+}
+
+void free_apply(fetiF_ctx c)
+{
+    for (void* p : c->apply_allocs) (void)hipFree(p);
+    c->apply_allocs.clear();
+    c->dZ = nullptr;
+    c->dBands = nullptr;
+    c->dBandZ = nullptr;
+    c->dGptr = nullptr;
+    c->dGent = nullptr;
+}
+
+template <typename T>
+hipError_t aalloc(fetiF_ctx c, T** p, size_t count)
+{
+    *p = nullptr;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(T) * std::max<size_t>(1, count));
+    if (e == hipSuccess) {
+        c->apply_allocs.push_back(q);
+        *p = (T*)q;
+    }
+    return e;
+}
+
+// Device copies of an apply plan (replacing the previous one).
+hipError_t install_apply(fetiF_ctx c, const ApplyPlan& A)
+{
+    free_apply(c);
+    hipError_t e;
+    char* z = nullptr;
+    if ((e = aalloc(c, &z, (size_t)A.total_z * (c->prec == 0 ? 8 : 4) + 64)) != hipSuccess) return e;
+    c->dZ = z;
+    if ((e = aalloc(c, &c->dBands, A.bands.size())) != hipSuccess) return e;
+    if ((e = aalloc(c, &c->dBandZ, A.band_z.size())) != hipSuccess) return e;
+    if ((e = aalloc(c, &c->dGptr, A.gptr.size())) != hipSuccess) return e;
+    if ((e = aalloc(c, &c->dGent, A.gent.size())) != hipSuccess) return e;
+    if ((e = upload(c->dBands, A.bands)) != hipSuccess) return e;
+    if ((e = upload(c->dBandZ, A.band_z)) != hipSuccess) return e;
+    if ((e = upload(c->dGptr, A.gptr)) != hipSuccess) return e;
+    if ((e = upload(c->dGent, A.gent)) != hipSuccess) return e;
+    c->nbands = (int32_t)A.bands.size();
+    c->total_z = A.total_z;
+    return hipSuccess;
+}
+
+}  // namespace
+
 // ======================================================================== create
 
 extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambda, int32_t nsub,
@@ -342,10 +468,8 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     std::vector<RhsUnit> units;
     std::vector<SyrkTile> tiles;
     std::vector<int32_t> lists;
-    std::vector<Band> bands;
-    std::vector<int64_t> band_z;
     std::vector<int32_t> dmap;
-    int64_t lb = 0, xb = 0, fb = 0, zb = 0;
+    int64_t lb = 0, xb = 0, fb = 0;
     int32_t snb = 0, rowb = 0, db = 0;
     int32_t maxlev = 0, max_m = 0;
     for (int32_t i = 0; i < nsub; ++i) {
@@ -415,38 +539,6 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
                 t.pad = 0;
                 tiles.push_back(t);
             }
-        // apply bands of about apply_band elements
-        P.band0 = (int32_t)bands.size();
-        int64_t nb = std::max<int64_t>(1, (fel + opt.apply_band - 1) / opt.apply_band);
-        int32_t r0 = 0;
-        for (int64_t k = 1; k <= nb && r0 < P.m; ++k) {
-            int32_t r1;
-            if (k == nb) {
-                r1 = P.m;
-            } else {
-                int64_t target = fel * k / nb;
-                int32_t lo = r0 + 1, hi = P.m;
-                while (lo < hi) {
-                    int32_t mid = (lo + hi) / 2;
-                    if (packed_row_offset(mid, V) >= target) hi = mid;
-                    else lo = mid + 1;
-                }
-                r1 = lo;
-            }
-            if (r1 <= r0) continue;
-            Band bd;
-            bd.fbase = fb;
-            bd.zoff = zb;
-            bd.r0 = r0;
-            bd.r1 = r1;
-            bd.dbase = db;
-            bd.pad = 0;
-            bands.push_back(bd);
-            band_z.push_back(zb);
-            zb += r1;
-            r0 = r1;
-        }
-        P.nband = (int32_t)bands.size() - P.band0;
         max_m = std::max(max_m, P.m);
         lb += S.nvals;
         xb += P.nx;
@@ -459,9 +551,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     c->total_L = lb;
     c->total_X = xb;
     c->total_F = fb;
-    c->total_z = zb;
     c->total_rows = rowb;
-    c->nbands = (int32_t)bands.size();
     c->nsyrk = (int32_t)tiles.size();
     // apply chunk count: lanes cover NCH * 64 * V columns
     {
@@ -545,28 +635,8 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         for (size_t t = 0; t < ord.size(); ++t) t2[t] = tiles[ord[t]];
         tiles.swap(t2);
     }
-    // gather map: entries of each global multiplier in ascending subdomain order
-    std::vector<int32_t> gptr(n_lambda + 1, 0);
-    for (int32_t i = 0; i < nsub; ++i)
-        for (int32_t g : c->subs[i].dual_map) gptr[g + 1]++;
-    for (int64_t g = 0; g < n_lambda; ++g) gptr[g + 1] += gptr[g];
-    std::vector<GatherEnt> gent(gptr[n_lambda]);
-    {
-        std::vector<int32_t> fill(gptr.begin(), gptr.end() - 1);
-        for (int32_t i = 0; i < nsub; ++i) {
-            const SubPlan& P = c->subs[i];
-            int32_t bcur = P.band0;
-            for (int32_t a = 0; a < P.m; ++a) {
-                while (bands[bcur].r1 <= a) ++bcur;
-                GatherEnt e;
-                e.a = a;
-                e.b0 = bcur;
-                e.b1 = P.band0 + P.nband;
-                e.pad = 0;
-                gent[fill[P.dual_map[P.sigma[a]]]++] = e;
-            }
-        }
-    }
+    ApplyPlan aplan;
+    plan_apply(c, opt.apply_band, aplan);
 
     // ---- device memory
     {
@@ -589,6 +659,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         fetiF_status st = hip_fail(nullptr, e, what);
         for (void* p : c->allocations) (void)hipFree(p);
         c->allocations.clear();
+        free_apply(c);
         if (c->hStage) (void)hipHostFree(c->hStage);
         delete c;
         return st;
@@ -605,9 +676,6 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         CK(dalloc(c, &f, (size_t)c->total_F * prec_bytes(c->prec) + 64));
         c->dF = f;
         CK(hipMemset(f, 0, (size_t)c->total_F * prec_bytes(c->prec) + 64));
-        char* z = nullptr;
-        CK(dalloc(c, &z, (size_t)c->total_z * (c->prec == 0 ? 8 : 4) + 64));
-        c->dZ = z;
     }
     CK(dalloc(c, &c->dSN, sns.size()));
     CK(dalloc(c, &c->dRows, rows.size()));
@@ -616,10 +684,6 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     CK(dalloc(c, &c->dItems, all_items.size()));
     CK(dalloc(c, &c->dTiles, tiles.size()));
     CK(dalloc(c, &c->dLists, lists.size()));
-    CK(dalloc(c, &c->dBands, bands.size()));
-    CK(dalloc(c, &c->dBandZ, band_z.size()));
-    CK(dalloc(c, &c->dGptr, gptr.size()));
-    CK(dalloc(c, &c->dGent, gent.size()));
     CK(dalloc(c, &c->dDmap, dmap.size()));
     CK(upload(c->dSN, sns));
     CK(upload(c->dRows, rows));
@@ -628,11 +692,8 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     CK(upload(c->dItems, all_items));
     CK(upload(c->dTiles, tiles));
     CK(upload(c->dLists, lists));
-    CK(upload(c->dBands, bands));
-    CK(upload(c->dBandZ, band_z));
-    CK(upload(c->dGptr, gptr));
-    CK(upload(c->dGent, gent));
     CK(upload(c->dDmap, dmap));
+    CK(install_apply(c, aplan));
     CK(hipHostMalloc((void**)&c->hStage, sizeof(double) * (size_t)std::max<int64_t>(1, c->total_L),
                      hipHostMallocDefault));
     CK(hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming));
@@ -733,11 +794,32 @@ extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double*
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
     PhaseTimer t4(c, st, 4);
-    HIPCHK(c, launch_apply_band(c->prec, c->apply_nch, c->dBands, c->nbands, c->dF, lambda_d, c->dDmap, c->dZ, st));
+    HIPCHK(c, launch_apply_band(c->prec, c->apply_nch, c->opt.apply_rows, c->opt.apply_nontemporal != 0, c->dBands,
+                                c->nbands, c->dF, lambda_d, c->dDmap, c->dZ, st));
     HIPCHK(c, t4.stop());
     PhaseTimer t5(c, st, 5);
     HIPCHK(c, launch_gather(c->prec, c->n_lambda, c->dGptr, c->dGent, c->dBandZ, c->dZ, q_d, st));
     HIPCHK(c, t5.stop());
+    return FETIF_OK;
+}
+
+extern "C" fetiF_status fetiF_set_apply(fetiF_ctx c, int32_t band_elems, int32_t rows, int32_t nontemporal)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (band_elems < 0 || (rows != 0 && rows != 1 && rows != 2) || nontemporal < -1 || nontemporal > 1)
+        return fail(c, FETIF_EINVAL, "band_elems >= 0, rows in {0,1,2}, nontemporal in {-1,0,1}");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    if (rows) c->opt.apply_rows = rows;
+    if (nontemporal >= 0) c->opt.apply_nontemporal = nontemporal;
+    if (band_elems > 0 && band_elems != c->opt.apply_band) {
+        HIPCHK(c, hipDeviceSynchronize());
+        ApplyPlan A;
+        plan_apply(c, band_elems, A);
+        HIPCHK(c, install_apply(c, A));
+        c->opt.apply_band = band_elems;
+    }
     return FETIF_OK;
 }
 
@@ -864,6 +946,7 @@ extern "C" fetiF_status fetiF_destroy(fetiF_ctx c)
         }
         for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
         for (void* p : c->allocations) (void)hipFree(p);
+        free_apply(c);
         if (c->hStage) (void)hipHostFree(c->hStage);
         if (c->upload_done) (void)hipEventDestroy(c->upload_done);
     }

@@ -44,8 +44,10 @@ void options_defaults(const fetiF_options* in, fetiF_options& o)
     std::memset(&o, 0, sizeof(o));
     if (in) o = *in;
     if (o.leaf_nodes <= 0) o.leaf_nodes = 24;
-    if (o.apply_band <= 0) o.apply_band = 32768;
+    if (o.apply_band <= 0) o.apply_band = 131072;
     if (o.trsm_chunk <= 0) o.trsm_chunk = 64;
+    if (o.apply_rows != 1 && o.apply_rows != 2) o.apply_rows = 2;
+    if (o.apply_nontemporal < 0 || o.apply_nontemporal > 1) o.apply_nontemporal = 1;
 }
 
 }  // namespace fetif

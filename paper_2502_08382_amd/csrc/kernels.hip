@@ -243,13 +243,27 @@ __device__ __forceinline__ void unpack<bf16_t, 8>(const uint4& raw, float (&v)[8
     }
 }
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NTL>
+__device__ __forceinline__ uint4 load16(const void* p)
+{
+    if constexpr (NTL) {
+        u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    } else {
+        return *reinterpret_cast<const uint4*>(p);
+    }
+}
+
 // One work-group handles one band of rows [r0, r1) of a packed lower
 // triangle: every stored element F[r][c] (c <= r) contributes F[r][c] p[c] to
 // row r (a dot product, reduced across the wavefront) and, for c < r,
 // F[r][c] p[r] to row c (kept in per-lane registers).  The band writes its
 // partial vector z[0..r1).  Lanes read 16-byte vectors of consecutive
-// columns, so a wavefront streams 1 KiB of a row per load.
-template <typename T, int NCH>
+// columns, so a wavefront streams 1 KiB of a row per load; a wavefront
+// takes ROWS consecutive rows per pass (their loads are in flight together).
+template <typename T, int NCH, int ROWS, bool NTL>
 __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__ bands,
                                                         const T* __restrict__ F,
                                                         const double* __restrict__ lam,
@@ -271,35 +285,60 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
     for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) y[ch][e] = (A)0;
-    for (int r = b.r0 + wv; r < b.r1; r += 4) {
+    for (int r = b.r0 + ROWS * wv; r < b.r1; r += 4 * ROWS) {
         const T* __restrict__ rowp = F + b.fbase + packed_row_offset(r, VEC);
-        uint4 raw[NCH];
+        uint4 raw[ROWS][NCH];
+        int rr[ROWS];
+        const T* rp[ROWS];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            const int col = ch * CH + lane * VEC;
-            if (col <= r) raw[ch] = *reinterpret_cast<const uint4*>(rowp + col);
-            else raw[ch] = make_uint4(0, 0, 0, 0);
+        for (int k = 0; k < ROWS; ++k) {
+            rr[k] = (r + k < b.r1) ? r + k : -1;   // -1: no such row, loads masked off
+            rp[k] = k == 0 ? rowp : rp[k - 1] + VEC * ((r + k - 1) / VEC + 1);
         }
-        const A pr = sp[r];
-        A dot = (A)0;
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k)
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int col = ch * CH + lane * VEC;
+                raw[k][ch] = col <= rr[k] ? load16<NTL>(rp[k] + col) : make_uint4(0, 0, 0, 0);
+            }
+        A pr[ROWS], dot[ROWS];
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            pr[k] = rr[k] >= 0 ? sp[rr[k]] : (A)0;
+            dot[k] = (A)0;
+        }
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int col = ch * CH + lane * VEC;
-            if (col <= r) {
-                A v[VEC];
-                unpack<T, VEC>(raw[ch], v);
+            if (col <= rr[ROWS - 1] || col <= rr[0]) {
+                A pc[VEC];
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) {
-                    const int cc = col + e;
-                    if (cc <= r) {
-                        dot += v[e] * sp[cc];
-                        if (cc < r) y[ch][e] += v[e] * pr;
+                for (int e = 0; e < VEC; ++e) pc[e] = sp[col + e];
+#pragma unroll
+                for (int k = 0; k < ROWS; ++k) {
+                    if (col <= rr[k]) {
+                        A v[VEC];
+                        unpack<T, VEC>(raw[k][ch], v);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            const int cc = col + e;
+                            if (cc <= rr[k]) {
+                                dot[k] += v[e] * pc[e];
+                                if (cc < rr[k]) y[ch][e] += v[e] * pr[k];
+                            }
+                        }
                     }
                 }
             }
         }
-        dot = wave_sum(dot);
-        if (lane == 0) srow[r - b.r0] = dot;
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) dot[k] = wave_sum(dot[k]);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < ROWS; ++k)
+                if (rr[k] >= 0) srow[rr[k] - b.r0] = dot[k];
+        }
     }
     __syncthreads();
     // sp is free now: sum the four wavefronts' column partials in order
@@ -382,43 +421,57 @@ hipError_t launch_syrk(int prec, const SyrkTile* tiles, int32_t ntiles, const in
     return hipGetLastError();
 }
 
-template <typename T, int NCH>
+template <typename T, int NCH, int ROWS, bool NTL>
 static void apply_launch(const Band* bands, int32_t nbands, const T* f, const double* lam, const int32_t* dmap,
                          typename Acc<T>::type* z, hipStream_t st)
 {
     // a band keeps NCH * 64 * VEC columns of p and of the row sums in LDS;
     // only instantiate shapes whose capacity stays within 4096 columns
     if constexpr (NCH * 64 * (16 / (int)sizeof(T)) <= 4096)
-        hipLaunchKernelGGL((apply_band_kernel<T, NCH>), dim3(nbands), dim3(NT), 0, st, bands, f, lam, dmap, z);
+        hipLaunchKernelGGL((apply_band_kernel<T, NCH, ROWS, NTL>), dim3(nbands), dim3(NT), 0, st, bands, f, lam,
+                           dmap, z);
 }
 
-template <typename T>
-static hipError_t apply_dispatch(int nch, const Band* bands, int32_t nbands, const void* F, const double* lam,
-                                 const int32_t* dmap, void* z, hipStream_t st)
+template <typename T, int ROWS, bool NTL>
+static hipError_t apply_dispatch_nch(int nch, const Band* bands, int32_t nbands, const void* F, const double* lam,
+                                     const int32_t* dmap, void* z, hipStream_t st)
 {
     using A = typename Acc<T>::type;
     const T* f = (const T*)F;
     A* zz = (A*)z;
     if (nch * 64 * (16 / (int)sizeof(T)) > 4096) return hipErrorInvalidValue;
     switch (nch) {
-    case 1: apply_launch<T, 1>(bands, nbands, f, lam, dmap, zz, st); break;
-    case 2: apply_launch<T, 2>(bands, nbands, f, lam, dmap, zz, st); break;
-    case 4: apply_launch<T, 4>(bands, nbands, f, lam, dmap, zz, st); break;
-    case 8: apply_launch<T, 8>(bands, nbands, f, lam, dmap, zz, st); break;
-    case 16: apply_launch<T, 16>(bands, nbands, f, lam, dmap, zz, st); break;
-    case 32: apply_launch<T, 32>(bands, nbands, f, lam, dmap, zz, st); break;
+    case 1: apply_launch<T, 1, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
+    case 2: apply_launch<T, 2, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
+    case 4: apply_launch<T, 4, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
+    case 8: apply_launch<T, 8, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
+    case 16: apply_launch<T, 16, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
+    case 32: apply_launch<T, 32, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_apply_band(int prec, int nch, const Band* bands, int32_t nbands, const void* F,
-                             const double* lam, const int32_t* dmap, void* z, hipStream_t st)
+template <typename T>
+static hipError_t apply_dispatch(int nch, int rows, bool ntl, const Band* bands, int32_t nbands, const void* F,
+                                 const double* lam, const int32_t* dmap, void* z, hipStream_t st)
+{
+    if (rows == 1)
+        return ntl ? apply_dispatch_nch<T, 1, true>(nch, bands, nbands, F, lam, dmap, z, st)
+                   : apply_dispatch_nch<T, 1, false>(nch, bands, nbands, F, lam, dmap, z, st);
+    if (rows == 2)
+        return ntl ? apply_dispatch_nch<T, 2, true>(nch, bands, nbands, F, lam, dmap, z, st)
+                   : apply_dispatch_nch<T, 2, false>(nch, bands, nbands, F, lam, dmap, z, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* bands, int32_t nbands,
+                             const void* F, const double* lam, const int32_t* dmap, void* z, hipStream_t st)
 {
     if (nbands <= 0) return hipSuccess;
-    if (prec == 0) return apply_dispatch<double>(nch, bands, nbands, F, lam, dmap, z, st);
-    if (prec == 1) return apply_dispatch<float>(nch, bands, nbands, F, lam, dmap, z, st);
-    return apply_dispatch<bf16_t>(nch, bands, nbands, F, lam, dmap, z, st);
+    if (prec == 0) return apply_dispatch<double>(nch, rows, ntl, bands, nbands, F, lam, dmap, z, st);
+    if (prec == 1) return apply_dispatch<float>(nch, rows, ntl, bands, nbands, F, lam, dmap, z, st);
+    return apply_dispatch<bf16_t>(nch, rows, ntl, bands, nbands, F, lam, dmap, z, st);
 }
 
 hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* gptr, const GatherEnt* ents,

@@ -21,8 +21,9 @@ hipError_t launch_trsm_level(const TrsmItem* items, int32_t nitems, int32_t slot
 // prec: 0 f64, 1 f32, 2 bf16
 hipError_t launch_syrk(int prec, const SyrkTile* tiles, int32_t ntiles, const int32_t* lists,
                        const DevSN* sns, const double* X, void* F, hipStream_t st);
-hipError_t launch_apply_band(int prec, int nch, const Band* bands, int32_t nbands, const void* F,
-                             const double* lam, const int32_t* dmap, void* z, hipStream_t st);
+// rows: rows per wavefront pass (1 or 2); ntl: non-temporal loads of F
+hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* bands, int32_t nbands,
+                             const void* F, const double* lam, const int32_t* dmap, void* z, hipStream_t st);
 hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* gptr, const GatherEnt* ents,
                          const int64_t* band_zoff, const void* z, double* q, hipStream_t st);
 

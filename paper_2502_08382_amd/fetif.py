@@ -42,7 +42,8 @@ class _Sub(ctypes.Structure):
 class _Opt(ctypes.Structure):
     _fields_ = [("f_storage", ctypes.c_int), ("leaf_nodes", ctypes.c_int32),
                 ("nthreads", ctypes.c_int32), ("apply_band", ctypes.c_int32),
-                ("trsm_chunk", ctypes.c_int32)]
+                ("trsm_chunk", ctypes.c_int32), ("apply_rows", ctypes.c_int32),
+                ("apply_nontemporal", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -58,7 +59,7 @@ EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply
            "fetiF_apply_backward", "fetiF_download_F", "fetiF_query", "fetiF_destroy",
            "fetiF_last_error", "fetiF_host_factor", "fetiF_hfactor_info", "fetiF_hfactor_export",
            "fetiF_hfactor_supernodes", "fetiF_hfactor_free", "fetiF_profile_enable",
-           "fetiF_profile_read"]
+           "fetiF_profile_read", "fetiF_set_apply"]
 
 PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "backward"]
 
@@ -93,6 +94,7 @@ def load_library(path=None):
     L.fetiF_hfactor_free.argtypes = [vp]
     L.fetiF_profile_enable.argtypes = [vp, ctypes.c_int]
     L.fetiF_profile_read.argtypes = [vp, ctypes.c_int, vp, vp, i32]
+    L.fetiF_set_apply.argtypes = [vp, i32, i32, i32]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype if name == "fetiF_last_error" else ctypes.c_int
     _lib = L
@@ -151,9 +153,10 @@ class _SubArrays:
                     _ptr(self.elem_dofs), _ptr(self.dK))
 
 
-def _options(f_storage="f64", leaf_nodes=0, nthreads=0, apply_band=0, trsm_chunk=0):
+def _options(f_storage="f64", leaf_nodes=0, nthreads=0, apply_band=0, trsm_chunk=0, apply_rows=0,
+             apply_nontemporal=-1):
     prec = _PREC[f_storage] if isinstance(f_storage, str) else int(f_storage)
-    return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk)
+    return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk, apply_rows, apply_nontemporal)
 
 
 class FetiContext:
@@ -205,6 +208,10 @@ class FetiContext:
         inf = _Info()
         self._check(self.L.fetiF_query(self.h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def set_apply(self, band_elems=0, rows=0, nontemporal=-1):
+        """Re-plan the apply (band size in stored elements, rows per pass, load policy)."""
+        self._check(self.L.fetiF_set_apply(self.h, int(band_elems), int(rows), int(nontemporal)))
 
     def profile(self, on=True):
         """Record HIP events around every device phase (see PHASES)."""
