@@ -100,7 +100,7 @@ typedef struct {
     int32_t leaf_nodes;   /* nested-dissection leaf size in nodes (default 24) */
     int32_t nthreads;     /* host threads for analysis/factorisation (default: all) */
     int32_t apply_band;   /* stored elements of F~ per apply work-group (default 131072) */
-    int32_t trsm_chunk;   /* RHS columns per TRSM work-group (default 64) */
+    int32_t trsm_chunk;   /* most RHS columns per TRSM work-group: 16, 32 or 64 (default 64) */
     int32_t apply_rows;   /* rows of F~ per wavefront pass in apply, 1 or 2 (default 2) */
     int32_t apply_nontemporal; /* 1: stream F~ with non-temporal loads (default), 0: cached */
 } fetiF_options;

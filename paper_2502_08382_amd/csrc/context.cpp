@@ -86,7 +86,9 @@ struct fetiF_ctx_s {
     std::vector<SubPlan> subs;
     // schedules
     std::vector<std::vector<TrsmItem>> level_items;
-    std::vector<int32_t> level_slot, level_maxns;
+    std::vector<int32_t> level_waves, level_maxns;
+    int32_t ninv = 0;
+    int64_t total_linv = 0;
     std::vector<int64_t> level_off;
     int32_t apply_nch = 1;
     int32_t nbands = 0;
@@ -96,6 +98,8 @@ struct fetiF_ctx_s {
     // device buffers
     double* dL = nullptr;
     double* dX = nullptr;
+    double* dLinv = nullptr;
+    InvItem* dInv = nullptr;
     void* dF = nullptr;
     void* dZ = nullptr;
     DevSN* dSN = nullptr;
@@ -463,6 +467,8 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     const int TS = 64;
     // ---- global placement and schedules
     std::vector<DevSN> sns;
+    std::vector<InvItem> inv_items;
+    int64_t linv_b = 0;
     std::vector<int32_t> rows;
     std::vector<XRow> xrows;
     std::vector<RhsUnit> units;
@@ -485,6 +491,13 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
             const Supernode& x = S.sn[s];
             DevSN d;
             d.lval = lb + x.val_off;
+            d.linv = -1;
+            if (P.w[s] > 0) {
+                d.linv = linv_b;
+                const int32_t nbk = (x.ncols + 15) / 16;
+                for (int32_t rb = 0; rb < nbk; ++rb) inv_items.push_back({snb + s, rb});
+                linv_b += (int64_t)nbk * 256;
+            }
             d.xoff = xb + P.xoff[s];
             d.rowsoff = (int64_t)rows.size();
             d.rowbase = rowb;
@@ -564,10 +577,12 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         }
         c->apply_nch = nch;
     }
-    // TRSM levels: items per height level, chunked to the level's slot width
+    // TRSM levels: items per height level.  A work-group has W wavefronts of
+    // 16 RHS columns each; W shrinks for large supernodes so that the solved
+    // blocks (W * ceil(ns/16) * 2 KiB of LDS) fit.
     c->level_items.assign(maxlev + 1, {});
     c->level_maxns.assign(maxlev + 1, 0);
-    c->level_slot.assign(maxlev + 1, 64);
+    c->level_waves.assign(maxlev + 1, 4);
     for (int32_t i = 0; i < nsub; ++i) {
         const SubPlan& P = c->subs[i];
         for (size_t s = 0; s < P.sym.sn.size(); ++s)
@@ -576,26 +591,23 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
                 c->level_maxns[L] = std::max(c->level_maxns[L], P.sym.sn[s].ncols);
             }
     }
+    const int32_t wmax = std::max(1, std::min(4, opt.trsm_chunk / 16));
     for (int32_t L = 0; L <= maxlev; ++L) {
         int32_t mx = std::max(1, c->level_maxns[L]);
-        int32_t slot = 64;
-        while (slot > 8 && (int64_t)mx * slot * 8 > 65536) slot /= 2;
-        if ((int64_t)mx * slot * 8 > 65536) {
+        int32_t W = wmax;
+        while (W > 1 && trsm_lds_bytes(W, mx) > 65536) W /= 2;
+        if (trsm_lds_bytes(W, mx) > 160 * 1024) {
             delete c;
-            return fail(nullptr, FETIF_ENOTSUP, "a supernode has more than 1024 columns");
+            return fail(nullptr, FETIF_ENOTSUP, "a supernode has more than 1280 columns");
         }
-        c->level_slot[L] = std::min<int32_t>(slot, std::max(8, opt.trsm_chunk));
-        // keep slot a power of two
-        int32_t p2 = 8;
-        while (p2 * 2 <= c->level_slot[L]) p2 *= 2;
-        c->level_slot[L] = p2;
+        c->level_waves[L] = W;
     }
     for (int32_t i = 0; i < nsub; ++i) {
         const SubPlan& P = c->subs[i];
         for (size_t s = 0; s < P.sym.sn.size(); ++s) {
             if (P.w[s] <= 0) continue;
             int32_t L = P.sym.sn[s].level;
-            int32_t slot = c->level_slot[L];
+            int32_t slot = 16 * c->level_waves[L];
             for (int32_t c0 = 0; c0 < P.w[s]; c0 += slot) {
                 TrsmItem it;
                 it.sn = P.snbase + (int32_t)s;
@@ -677,6 +689,11 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         c->dF = f;
         CK(hipMemset(f, 0, (size_t)c->total_F * prec_bytes(c->prec) + 64));
     }
+    c->total_linv = linv_b;
+    c->ninv = (int32_t)inv_items.size();
+    CK(dalloc(c, &c->dLinv, (size_t)linv_b));
+    CK(dalloc(c, &c->dInv, inv_items.size()));
+    CK(upload(c->dInv, inv_items));
     CK(dalloc(c, &c->dSN, sns.size()));
     CK(dalloc(c, &c->dRows, rows.size()));
     CK(dalloc(c, &c->dXRows, xrows.size()));
@@ -768,10 +785,11 @@ extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
     HIPCHK(c, launch_rhs_units(c->dUnits, c->sum_m, c->dX, st));
     HIPCHK(c, t1.stop());
     PhaseTimer t2(c, st, 2);
+    HIPCHK(c, launch_diag_inverse(c->dInv, c->ninv, c->dSN, c->dL, c->dLinv, st));
     for (size_t L = 0; L < c->level_items.size(); ++L) {
         int32_t cnt = (int32_t)(c->level_off[L + 1] - c->level_off[L]);
-        HIPCHK(c, launch_trsm_level(c->dItems + c->level_off[L], cnt, c->level_slot[L], c->level_maxns[L], c->dSN,
-                                    c->dL, c->dRows, c->dXRows, c->dX, st));
+        HIPCHK(c, launch_trsm_level(c->dItems + c->level_off[L], cnt, c->level_waves[L], c->level_maxns[L], c->dSN,
+                                    c->dL, c->dLinv, c->dRows, c->dXRows, c->dX, st));
     }
     HIPCHK(c, t2.stop());
     PhaseTimer t3(c, st, 3);

@@ -7,6 +7,7 @@ namespace fetif {
 // One supernode of one subdomain, in device form.
 struct DevSN {
     int64_t lval;    // offset of its (ncols+nrows) x ncols column-major panel in the factor buffer
+    int64_t linv;    // offset of the inverses of its 16x16 diagonal blocks (-1: none)
     int64_t xoff;    // offset of its ncols x w row-major block of X
     int64_t rowsoff; // offset of its below-diagonal row list (subdomain-local rows)
     int32_t rowbase; // first global row slot of its subdomain (for the X row tables)
@@ -15,6 +16,12 @@ struct DevSN {
     int32_t nrows;
     int32_t j0;      // first RHS column of its range (sorted local multiplier order)
     int32_t w;       // width of its RHS column range
+};
+
+// Diagonal-block inversion item: block rb of supernode sn.
+struct InvItem {
+    int32_t sn;
+    int32_t rb;
 };
 
 // TRSM work item: one RHS column chunk of one supernode.

@@ -85,54 +85,124 @@ __global__ void rhs_units_kernel(const RhsUnit* __restrict__ u, int64_t n, doubl
 
 // ---------------------------------------------------------------- TRSM
 
-// One work-group solves one RHS column chunk of one supernode:
-//   X_s <- L_ss^{-1} X_s          (column-parallel forward substitution in LDS)
-//   X[rows(s)] -= L_rs X_s        (update of the ancestors' rows)
-// slot_w (a power of two <= 64) columns are processed; the chunk's own width
-// cw <= slot_w, extra columns stay zero.
-__global__ __launch_bounds__(NT) void trsm_level_kernel(const TrsmItem* __restrict__ items, int32_t slot_w,
-                                                        const DevSN* __restrict__ sns,
-                                                        const double* __restrict__ L,
-                                                        const int32_t* __restrict__ rows,
-                                                        const XRow* __restrict__ xrows,
-                                                        double* __restrict__ X)
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 operand layout on gfx950 (lane l, q = l / 16,
+// j = l % 16): A holds A[j][q], B holds B[q][j], and accumulator register r
+// holds D[q + 4r][j].  Register r of a product is therefore exactly the B
+// operand of k-step r of the next product, with no data movement.
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c)
 {
-    extern __shared__ double sx[];
-    const TrsmItem it = items[blockIdx.x];
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Inverse of one 16x16 lower-triangular diagonal block of a supernode panel
+// (rows/columns beyond the supernode are the identity).  Thread j of the
+// block forms column j by forward substitution.  Stored column-major.
+__global__ __launch_bounds__(NT) void diag_inverse_kernel(const InvItem* __restrict__ items, int32_t nitems,
+                                                          const DevSN* __restrict__ sns,
+                                                          const double* __restrict__ L,
+                                                          double* __restrict__ Linv)
+{
+    const int t = blockIdx.x * NT + threadIdx.x;
+    const int item = t >> 4, j = t & 15;
+    if (item >= nitems) return;
+    const InvItem it = items[item];
     const DevSN s = sns[it.sn];
-    const int tid = threadIdx.x;
-    const int CW = slot_w;
-    const int cw = it.cw;
-    const int ns = s.ncols, nr = s.nrows, d = ns + nr;
+    const int ns = s.ncols, d = s.ncols + s.nrows, base = it.rb * 16;
     const double* __restrict__ P = L + s.lval;
-    const int c = tid & (CW - 1);
-    const int g = tid / CW;
-    const int G = NT / CW;
-    for (int idx = tid; idx < ns * CW; idx += NT) {
-        int r = idx / CW, cc = idx - r * CW;
-        sx[idx] = cc < cw ? X[s.xoff + (int64_t)r * s.w + it.c0 + cc] : 0.0;
+    double x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int gi = base + i;
+        double v = (i == j) ? 1.0 : 0.0;
+        if (gi < ns) {
+#pragma unroll
+            for (int k = 0; k < i; ++k) v -= P[(int64_t)(base + k) * d + gi] * x[k];
+            v /= P[(int64_t)gi * d + gi];
+        }
+        x[i] = v;
     }
-    __syncthreads();
-    for (int k = 0; k < ns; ++k) {
-        if (g == 0) sx[k * CW + c] /= P[(int64_t)k * d + k];
-        __syncthreads();
-        const double xk = sx[k * CW + c];
-        const double* __restrict__ colk = P + (int64_t)k * d;
-        for (int i = k + 1 + g; i < ns; i += G) sx[i * CW + c] -= colk[i] * xk;
-        __syncthreads();
-    }
-    for (int i = g; i < nr; i += G) {
-        double acc = 0.0;
-        for (int k = 0; k < ns; ++k) acc += P[(int64_t)k * d + ns + i] * sx[k * CW + c];
-        if (c < cw) {
-            const int r = rows[s.rowsoff + i];
-            const XRow xr = xrows[s.rowbase + r];
-            X[xr.off + (s.j0 + it.c0 + c - xr.j0)] -= acc;
+    double* out = Linv + s.linv + (int64_t)it.rb * 256 + j * 16;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) out[i] = x[i];
+}
+
+// One work-group solves one RHS column chunk of one supernode s; each of its
+// W wavefronts owns 16 columns and works alone (no barriers):
+//   for each 16-row block rb:  acc = X[rb] - sum_{kb<rb} L[rb,kb] X[kb]
+//                              X[rb] = inv(L[rb,rb]) acc          (MFMA)
+//   for each 16-row block of rows(s):  X[rows] -= L[rows, s] X_s   (MFMA)
+// The solved blocks stay in wave-private LDS in B-operand order.  Items of
+// one level touch disjoint RHS column ranges, so the updates need no atomics.
+__global__ void trsm_level_kernel(const TrsmItem* __restrict__ items, int32_t nbmax,
+                                  const DevSN* __restrict__ sns, const double* __restrict__ L,
+                                  const double* __restrict__ Linv, const int32_t* __restrict__ rows,
+                                  const XRow* __restrict__ xrows, double* __restrict__ X)
+{
+    extern __shared__ double smem[];
+    const TrsmItem it = items[blockIdx.x];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = lane >> 4, j = lane & 15;
+    const int cbeg = wv * 16;
+    if (cbeg >= it.cw) return;  // this wavefront has no columns
+    const DevSN s = sns[it.sn];
+    const int ns = s.ncols, nr = s.nrows, d = ns + nr;
+    const int nb = (ns + 15) >> 4;
+    const int col = it.c0 + cbeg + j;             // column relative to j0
+    const bool cv = (cbeg + j) < it.cw;
+    const double* __restrict__ P = L + s.lval;
+    const double* __restrict__ PI = Linv + s.linv;
+    double* __restrict__ sx = smem + (size_t)wv * nbmax * 256;
+    double* __restrict__ xs = X + s.xoff + col;   // X_s[row][col] = xs[row * w]
+    for (int rb = 0; rb < nb; ++rb) {
+        d4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = rb * 16 + q + 4 * r;
+            acc[r] = (cv && row < ns) ? xs[(int64_t)row * s.w] : 0.0;
+        }
+        const int arow = rb * 16 + j;
+        const bool av = arow < ns;
+        for (int kb = 0; kb < rb; ++kb) {
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int kc = kb * 16 + 4 * kk + q;
+                const double a = av ? -P[(int64_t)kc * d + arow] : 0.0;
+                acc = mfma16(a, sx[(kb * 4 + kk) * 64 + lane], acc);
+            }
+        }
+        d4 xn = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) xn = mfma16(PI[rb * 256 + (4 * kk + q) * 16 + j], acc[kk], xn);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            sx[(rb * 4 + r) * 64 + lane] = xn[r];
+            const int row = rb * 16 + q + 4 * r;
+            if (cv && row < ns) xs[(int64_t)row * s.w] = xn[r];
         }
     }
-    for (int idx = tid; idx < ns * CW; idx += NT) {
-        int r = idx / CW, cc = idx - r * CW;
-        if (cc < cw) X[s.xoff + (int64_t)r * s.w + it.c0 + cc] = sx[idx];
+    const int jglob = s.j0 + col;
+    for (int rb = 0; rb * 16 < nr; ++rb) {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        const int arow = ns + rb * 16 + j;
+        const bool av = arow < d;
+        for (int kb = 0; kb < nb; ++kb) {
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int kc = kb * 16 + 4 * kk + q;
+                const double a = (av && kc < ns) ? P[(int64_t)kc * d + arow] : 0.0;
+                acc = mfma16(a, sx[(kb * 4 + kk) * 64 + lane], acc);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = rb * 16 + q + 4 * r;
+            if (cv && i < nr) {
+                const XRow xr = xrows[s.rowbase + rows[s.rowsoff + i]];
+                X[xr.off + (jglob - xr.j0)] -= acc[r];
+            }
+        }
     }
 }
 
@@ -140,28 +210,37 @@ __global__ __launch_bounds__(NT) void trsm_level_kernel(const TrsmItem* __restri
 
 constexpr int ST = 64;   // output tile edge
 constexpr int SK = 16;   // rows of X per LDS stage
+constexpr int SP = ST + 2;
 
+// One work-group forms one 64x64 tile (rows ta, columns tb) of the lower
+// triangle of F~_i = X_i^T X_i, summing over the supernodes whose RHS range
+// meets both column ranges (only their rows of X are non-zero there).
+// Wavefront w computes the 32x32 quadrant (w/2, w%2) as 2x2 MFMA blocks; X
+// rows are staged 16 at a time through LDS, zero outside the range.
 template <typename T>
 __global__ __launch_bounds__(NT) void syrk_kernel(const SyrkTile* __restrict__ tiles,
                                                   const int32_t* __restrict__ lists,
                                                   const DevSN* __restrict__ sns,
                                                   const double* __restrict__ X, T* __restrict__ F)
 {
-    __shared__ double sa[SK][ST + 1];
-    __shared__ double sb[SK][ST + 1];
+    __shared__ double sa[SK][SP];
+    __shared__ double sb[SK][SP];
     const SyrkTile t = tiles[blockIdx.x];
-    const int tid = threadIdx.x;
-    const int ty = tid >> 4, tx = tid & 15;
-    double acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int q = lane >> 4, j = lane & 15;
+    const int wi = wv >> 1, wj = wv & 1;
     const int ca0 = t.ta * ST, cb0 = t.tb * ST;
+    d4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     for (int li = t.list0; li < t.list1; ++li) {
         const DevSN s = sns[lists[li]];
         for (int k0 = 0; k0 < s.ncols; k0 += SK) {
-            for (int idx = tid; idx < SK * ST; idx += NT) {
+#pragma unroll
+            for (int u = 0; u < (SK * ST) / NT; ++u) {
+                const int idx = tid + u * NT;
                 const int kk = idx / ST, cc = idx - kk * ST;
                 const int k = k0 + kk;
                 const int ja = ca0 + cc - s.j0, jb = cb0 + cc - s.j0;
@@ -171,32 +250,33 @@ __global__ __launch_bounds__(NT) void syrk_kernel(const SyrkTile* __restrict__ t
                 sb[kk][cc] = (kin && jb >= 0 && jb < s.w) ? xr[jb] : 0.0;
             }
             __syncthreads();
-#pragma unroll 4
-            for (int kk = 0; kk < SK; ++kk) {
-                double ra[4], rb[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) ra[i] = sa[kk][ty * 4 + i];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) rb[j] = sb[kk][tx * 4 + j];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] += ra[i] * rb[j];
+            for (int k4 = 0; k4 < SK / 4; ++k4) {
+                const int kr = 4 * k4 + q;
+                const double a0 = sa[kr][32 * wi + j], a1 = sa[kr][32 * wi + 16 + j];
+                const double b0 = sb[kr][32 * wj + j], b1 = sb[kr][32 * wj + 16 + j];
+                acc[0][0] = mfma16(a0, b0, acc[0][0]);
+                acc[0][1] = mfma16(a0, b1, acc[0][1]);
+                acc[1][0] = mfma16(a1, b0, acc[1][0]);
+                acc[1][1] = mfma16(a1, b1, acc[1][1]);
             }
             __syncthreads();
         }
     }
+    constexpr int64_t V = 16 / sizeof(T);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = ca0 + ty * 4 + i;
-        if (row >= t.m) continue;
-        T* frow = F + t.fbase + packed_row_offset(row, (int64_t)(16 / sizeof(T)));
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = cb0 + tx * 4 + j;
-            if (col <= row) store_f<T>(frow + col, acc[i][j]);
+        for (int r = 0; r < 4; ++r) {
+            const int row = ca0 + 32 * wi + 16 * a + q + 4 * r;
+            if (row >= t.m) continue;
+            T* frow = F + t.fbase + packed_row_offset(row, V);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int col = cb0 + 32 * wj + 16 * b + j;
+                if (col <= row) store_f<T>(frow + col, acc[a][b][r]);
+            }
         }
-    }
 }
 
 // ---------------------------------------------------------------- apply
@@ -394,14 +474,30 @@ hipError_t launch_rhs_units(const RhsUnit* u, int64_t n, double* X, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_trsm_level(const TrsmItem* items, int32_t nitems, int32_t slot_w, int32_t max_ns,
-                             const DevSN* sns, const double* L, const int32_t* rows, const XRow* xrows,
-                             double* X, hipStream_t st)
+hipError_t launch_diag_inverse(const InvItem* items, int32_t nitems, const DevSN* sns, const double* L,
+                               double* Linv, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    size_t lds = sizeof(double) * (size_t)max_ns * slot_w;
-    hipLaunchKernelGGL(trsm_level_kernel, dim3(nitems), dim3(NT), lds, st, items, slot_w, sns, L, rows,
-                       xrows, X);
+    const int64_t threads = (int64_t)nitems * 16;
+    hipLaunchKernelGGL(diag_inverse_kernel, dim3((unsigned)((threads + NT - 1) / NT)), dim3(NT), 0, st, items,
+                       nitems, sns, L, Linv);
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm_level(const TrsmItem* items, int32_t nitems, int32_t waves, int32_t max_ns,
+                             const DevSN* sns, const double* L, const double* Linv, const int32_t* rows,
+                             const XRow* xrows, double* X, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    const size_t lds = trsm_lds_bytes(waves, max_ns);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)trsm_level_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const int32_t nbmax = (max_ns + 15) / 16;
+    hipLaunchKernelGGL(trsm_level_kernel, dim3(nitems), dim3(64 * waves), lds, st, items, nbmax, sns, L, Linv,
+                       rows, xrows, X);
     return hipGetLastError();
 }
 
