@@ -155,6 +155,18 @@ fetiF_status fetiF_set_apply(fetiF_ctx ctx, int32_t band_elems, int32_t rows, in
 fetiF_status fetiF_apply_backward(fetiF_ctx ctx, const double* g_d, const double* lambda_d,
                                   double* dlambda_d, double* dtheta_d, void* stream);
 
+/* Implicit application (eq. dualop_apply_impl): q_d = sum_i D_i^T B~_i
+ * L_i^{-T} L_i^{-1} B~_i^T D_i lambda_d by batched supernodal forward and
+ * backward substitution with the uploaded factors (no assembled F needed).
+ * Requires every subdomain factored.  Deterministic.  Asynchronous. */
+fetiF_status fetiF_apply_implicit(fetiF_ctx ctx, const double* lambda_d, double* q_d, void* stream);
+
+/* Dual right-hand side d = B K^+ f - c (Sec. II, below eq. alphaconstraint):
+ * f_d is the concatenation of the subdomain load vectors f_i (local DOF
+ * order, sum n_i entries), c_d the n_lambda constraint values (may be NULL
+ * for c = 0).  Requires every subdomain factored.  Asynchronous. */
+fetiF_status fetiF_dual_rhs(fetiF_ctx ctx, const double* f_d, const double* c_d, double* d_d, void* stream);
+
 /* Copy F~_i of one subdomain to host_out as a full m_i x m_i row-major
  * matrix in the local multiplier order of create (test/debug hook).
  * Synchronises the device. */

@@ -65,6 +65,7 @@ struct SubPlan {
     // global placement
     int64_t lbase = 0, xbase = 0, fbase = 0;
     int32_t snbase = 0, rowbase = 0, dbase = 0, band0 = 0, nband = 0;
+    int32_t inv0 = 0, ninv = 0;
     std::string err;
 };
 
@@ -89,6 +90,13 @@ struct fetiF_ctx_s {
     std::vector<int32_t> level_waves, level_maxns;
     int32_t ninv = 0;
     int64_t total_linv = 0;
+    // batched solves with L: levels of all supernodes, tree tables
+    std::vector<std::vector<int32_t>> solve_levels;
+    std::vector<int32_t> solve_maxfront;
+    std::vector<int64_t> solve_off;
+    int64_t total_u = 0;
+    int64_t nelem_total = 0;
+    bool has_elems = false;
     std::vector<int64_t> level_off;
     int32_t apply_nch = 1;
     int32_t nbands = 0;
@@ -100,6 +108,22 @@ struct fetiF_ctx_s {
     double* dX = nullptr;
     double* dLinv = nullptr;
     InvItem* dInv = nullptr;
+    int32_t* dSolveSn = nullptr;    // supernode ids per solve level
+    int32_t* dChildPtr = nullptr;
+    int32_t* dChildIdx = nullptr;
+    int32_t* dRelpos = nullptr;
+    double* dU = nullptr;           // update vectors (2 rhs)
+    double* dXv = nullptr;          // solve vectors (2 rhs, permuted rows)
+    int32_t* dSubRow = nullptr;     // nsub+1 row bases
+    int32_t* dSubM = nullptr;       // nsub+1 multiplier bases
+    int32_t* dStartRows = nullptr;  // sorted start rows per subdomain
+    int8_t* dSignsSorted = nullptr;
+    int32_t* dXGptr = nullptr;
+    XGatherEnt* dXGent = nullptr;
+    int32_t* dXperm = nullptr;      // x row -> position in the concatenated DOF vector
+    ElemRef* dElems = nullptr;
+    int32_t* dEpos = nullptr;
+    double* dDK = nullptr;
     void* dF = nullptr;
     void* dZ = nullptr;
     DevSN* dSN = nullptr;
@@ -484,6 +508,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         P.lbase = lb;
         P.xbase = xb;
         P.snbase = snb;
+        P.inv0 = (int32_t)inv_items.size();
         P.rowbase = rowb;
         P.dbase = db;
         const int32_t ns = (int32_t)S.sn.size();
@@ -491,8 +516,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
             const Supernode& x = S.sn[s];
             DevSN d;
             d.lval = lb + x.val_off;
-            d.linv = -1;
-            if (P.w[s] > 0) {
+            {
                 d.linv = linv_b;
                 const int32_t nbk = (x.ncols + 15) / 16;
                 for (int32_t rb = 0; rb < nbk; ++rb) inv_items.push_back({snb + s, rb});
@@ -513,6 +537,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
             c->syrk_flops += (double)x.ncols * P.w[s] * (P.w[s] + 1);
         }
         c->factor_flops += S.flops_factor;
+        P.ninv = (int32_t)inv_items.size() - P.inv0;
         xrows.resize(xrows.size() + P.n);
         for (int32_t s = 0; s < ns; ++s) {
             const Supernode& x = S.sn[s];
@@ -650,6 +675,104 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     ApplyPlan aplan;
     plan_apply(c, opt.apply_band, aplan);
 
+    // ---- tables of the batched solves with L
+    std::vector<int32_t> relpos(rows.size(), -1), child_ptr(sns.size() + 1, 0), child_idx;
+    std::vector<int32_t> sub_row(nsub + 1, 0), sub_m(nsub + 1, 0), start_rows, xperm;
+    std::vector<int8_t> signs_sorted;
+    c->solve_levels.assign(maxlev + 1, {});
+    c->solve_maxfront.assign(maxlev + 1, 1);
+    {
+        std::vector<std::vector<int32_t>> kids(sns.size());
+        for (int32_t i = 0; i < nsub; ++i) {
+            const SubPlan& P = c->subs[i];
+            const Symbolic& S = P.sym;
+            std::vector<int32_t> pos(P.n, -1);
+            for (size_t sl = 0; sl < S.sn.size(); ++sl) {
+                const Supernode& x = S.sn[sl];
+                const int32_t g = P.snbase + (int32_t)sl;
+                c->solve_levels[x.level].push_back(g);
+                c->solve_maxfront[x.level] = std::max(c->solve_maxfront[x.level], x.ncols + x.nrows);
+                if (x.parent < 0) continue;
+                kids[P.snbase + x.parent].push_back(g);
+                const Supernode& p = S.sn[x.parent];
+                for (int32_t k = 0; k < p.ncols; ++k) pos[p.first + k] = k;
+                for (int32_t k = 0; k < p.nrows; ++k) pos[S.rows[p.row_off + k]] = p.ncols + k;
+                for (int32_t k = 0; k < x.nrows; ++k) {
+                    int32_t pr = pos[S.rows[x.row_off + k]];
+                    if (pr < 0) {
+                        delete c;
+                        return fail(nullptr, FETIF_EINVAL, "internal: child rows outside the parent front");
+                    }
+                    relpos[sns[g].rowsoff + k] = pr;
+                }
+                for (int32_t k = 0; k < p.ncols; ++k) pos[p.first + k] = -1;
+                for (int32_t k = 0; k < p.nrows; ++k) pos[S.rows[p.row_off + k]] = -1;
+            }
+            sub_row[i + 1] = sub_row[i] + P.n;
+            sub_m[i + 1] = sub_m[i] + P.m;
+            for (int32_t k = 0; k < P.m; ++k) {
+                start_rows.push_back(P.start[k]);
+                signs_sorted.push_back(P.b_sign[P.sigma[k]]);
+            }
+            for (int32_t k = 0; k < P.n; ++k) xperm.push_back(P.rowbase + S.perm[k]);
+        }
+        for (size_t g = 0; g < sns.size(); ++g) {
+            child_ptr[g + 1] = child_ptr[g] + (int32_t)kids[g].size();
+            child_idx.insert(child_idx.end(), kids[g].begin(), kids[g].end());
+        }
+    }
+    std::vector<int32_t> solve_sn;
+    c->solve_off.assign(maxlev + 2, 0);
+    for (int32_t L = 0; L <= maxlev; ++L) {
+        c->solve_off[L] = (int64_t)solve_sn.size();
+        solve_sn.insert(solve_sn.end(), c->solve_levels[L].begin(), c->solve_levels[L].end());
+    }
+    c->solve_off[maxlev + 1] = (int64_t)solve_sn.size();
+    c->total_u = (int64_t)rows.size();
+    // implicit gather: global multiplier -> (x position, sign), ascending subdomain
+    std::vector<int32_t> xgptr(n_lambda + 1, 0);
+    for (int32_t i = 0; i < nsub; ++i)
+        for (int32_t g : c->subs[i].dual_map) xgptr[g + 1]++;
+    for (int64_t g = 0; g < n_lambda; ++g) xgptr[g + 1] += xgptr[g];
+    std::vector<XGatherEnt> xgent(xgptr[n_lambda]);
+    {
+        std::vector<int32_t> fill(xgptr.begin(), xgptr.end() - 1);
+        for (int32_t i = 0; i < nsub; ++i) {
+            const SubPlan& P = c->subs[i];
+            for (int32_t j = 0; j < P.m; ++j) {
+                XGatherEnt e;
+                e.xpos = P.rowbase + P.sym.pinv[P.b_dof[j]];
+                e.sign = (double)P.b_sign[j];
+                xgent[fill[P.dual_map[j]]++] = e;
+            }
+        }
+    }
+    // element tables of the theta-adjoint
+    std::vector<ElemRef> elems;
+    std::vector<int32_t> epos;
+    std::vector<double> dks;
+    c->has_elems = true;
+    for (int32_t i = 0; i < nsub; ++i)
+        if (c->subs[i].nelem <= 0) c->has_elems = false;
+    if (c->has_elems) {
+        for (int32_t i = 0; i < nsub; ++i) {
+            const SubPlan& P = c->subs[i];
+            const int64_t dko = (int64_t)dks.size();
+            dks.insert(dks.end(), P.dK.begin(), P.dK.end());
+            for (int32_t e = 0; e < P.nelem; ++e) {
+                ElemRef r;
+                r.sub = i;
+                r.edofs = P.edofs;
+                r.pos_off = (int64_t)epos.size();
+                r.dk_off = dko;
+                for (int32_t a = 0; a < P.edofs; ++a)
+                    epos.push_back(P.rowbase + P.sym.pinv[P.elem_dofs[(size_t)e * P.edofs + a]]);
+                elems.push_back(r);
+            }
+        }
+        c->nelem_total = (int64_t)elems.size();
+    }
+
     // ---- device memory
     {
         int ndev = 0;
@@ -694,6 +817,38 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     CK(dalloc(c, &c->dLinv, (size_t)linv_b));
     CK(dalloc(c, &c->dInv, inv_items.size()));
     CK(upload(c->dInv, inv_items));
+    CK(dalloc(c, &c->dSolveSn, solve_sn.size()));
+    CK(upload(c->dSolveSn, solve_sn));
+    CK(dalloc(c, &c->dChildPtr, child_ptr.size()));
+    CK(upload(c->dChildPtr, child_ptr));
+    CK(dalloc(c, &c->dChildIdx, child_idx.size()));
+    CK(upload(c->dChildIdx, child_idx));
+    CK(dalloc(c, &c->dRelpos, relpos.size()));
+    CK(upload(c->dRelpos, relpos));
+    CK(dalloc(c, &c->dU, (size_t)c->total_u * 2));
+    CK(dalloc(c, &c->dXv, (size_t)c->total_rows * 2));
+    CK(dalloc(c, &c->dSubRow, sub_row.size()));
+    CK(upload(c->dSubRow, sub_row));
+    CK(dalloc(c, &c->dSubM, sub_m.size()));
+    CK(upload(c->dSubM, sub_m));
+    CK(dalloc(c, &c->dStartRows, start_rows.size()));
+    CK(upload(c->dStartRows, start_rows));
+    CK(dalloc(c, &c->dSignsSorted, signs_sorted.size()));
+    CK(upload(c->dSignsSorted, signs_sorted));
+    CK(dalloc(c, &c->dXGptr, xgptr.size()));
+    CK(upload(c->dXGptr, xgptr));
+    CK(dalloc(c, &c->dXGent, xgent.size()));
+    CK(upload(c->dXGent, xgent));
+    CK(dalloc(c, &c->dXperm, xperm.size()));
+    CK(upload(c->dXperm, xperm));
+    if (c->has_elems) {
+        CK(dalloc(c, &c->dElems, elems.size()));
+        CK(upload(c->dElems, elems));
+        CK(dalloc(c, &c->dEpos, epos.size()));
+        CK(upload(c->dEpos, epos));
+        CK(dalloc(c, &c->dDK, dks.size()));
+        CK(upload(c->dDK, dks));
+    }
     CK(dalloc(c, &c->dSN, sns.size()));
     CK(dalloc(c, &c->dRows, rows.size()));
     CK(dalloc(c, &c->dXRows, xrows.size()));
@@ -758,9 +913,12 @@ extern "C" fetiF_status fetiF_factor_upload(fetiF_ctx c, int32_t first, int32_t 
     PhaseTimer t0(c, st, 0);
     HIPCHK(c, hipMemcpyAsync(c->dL + P0.lbase, c->hStage + P0.lbase, sizeof(double) * (size_t)n,
                              hipMemcpyHostToDevice, st));
-    HIPCHK(c, t0.stop());
     HIPCHK(c, hipEventRecord(c->upload_done, st));
     c->upload_pending = true;
+    // inverses of the 16x16 diagonal blocks of the uploaded supernodes, used
+    // by the assembly TRSM and by the solves
+    HIPCHK(c, launch_diag_inverse(c->dInv + P0.inv0, P1.inv0 + P1.ninv - P0.inv0, c->dSN, c->dL, c->dLinv, st));
+    HIPCHK(c, t0.stop());
     for (int32_t k = 0; k < count; ++k)
         if (!c->uploaded[first + k]) {
             c->uploaded[first + k] = 1;
@@ -785,7 +943,6 @@ extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
     HIPCHK(c, launch_rhs_units(c->dUnits, c->sum_m, c->dX, st));
     HIPCHK(c, t1.stop());
     PhaseTimer t2(c, st, 2);
-    HIPCHK(c, launch_diag_inverse(c->dInv, c->ninv, c->dSN, c->dL, c->dLinv, st));
     for (size_t L = 0; L < c->level_items.size(); ++L) {
         int32_t cnt = (int32_t)(c->level_off[L + 1] - c->level_off[L]);
         HIPCHK(c, launch_trsm_level(c->dItems + c->level_off[L], cnt, c->level_waves[L], c->level_maxns[L], c->dSN,
@@ -841,13 +998,93 @@ extern "C" fetiF_status fetiF_set_apply(fetiF_ctx c, int32_t band_elems, int32_t
     return FETIF_OK;
 }
 
+namespace {
+
+// Forward and backward substitution with every L_i on the nrhs vectors held
+// in c->dXv (permuted rows, interleaved); phase 6 of the timers.
+hipError_t solve_all(fetiF_ctx c, int nrhs, hipStream_t st)
+{
+    hipError_t e;
+    const int32_t nl = (int32_t)c->solve_levels.size();
+    for (int32_t L = 0; L < nl; ++L) {
+        const int32_t n = (int32_t)(c->solve_off[L + 1] - c->solve_off[L]);
+        if ((e = launch_trsv_forward_level(nrhs, c->dSolveSn + c->solve_off[L], n, c->solve_maxfront[L], c->dSN, c->dL,
+                                           c->dLinv, c->dChildPtr, c->dChildIdx, c->dRelpos, c->dU, c->dXv, st)) !=
+            hipSuccess)
+            return e;
+    }
+    for (int32_t L = nl - 1; L >= 0; --L) {
+        const int32_t n = (int32_t)(c->solve_off[L + 1] - c->solve_off[L]);
+        if ((e = launch_trsv_backward_level(nrhs, c->dSolveSn + c->solve_off[L], n, c->solve_maxfront[L], c->dSN,
+                                            c->dL, c->dLinv, c->dRows, c->dXv, st)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+fetiF_status need_factors(fetiF_ctx c)
+{
+    if (c->n_uploaded != c->nsub) return fail(c, FETIF_ESTATE, "solve before every subdomain was factored");
+    return FETIF_OK;
+}
+
+}  // namespace
+
+extern "C" fetiF_status fetiF_apply_implicit(fetiF_ctx c, const double* lambda_d, double* q_d, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (!lambda_d || !q_d || lambda_d == q_d) return fail(c, FETIF_EINVAL, "lambda/q NULL or overlapping");
+    if (fetiF_status st0 = need_factors(c)) return st0;
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    PhaseTimer t6(c, st, 6);
+    HIPCHK(c, launch_scatter_dual(1, c->nsub, c->dSubRow, c->dSubM, c->dStartRows, c->dSignsSorted, c->dDmap,
+                                  lambda_d, nullptr, c->dXv, c->total_rows, st));
+    HIPCHK(c, solve_all(c, 1, st));
+    HIPCHK(c, launch_xgather(1, c->n_lambda, c->dXGptr, c->dXGent, c->dXv, nullptr, q_d, st));
+    HIPCHK(c, t6.stop());
+    return FETIF_OK;
+}
+
+extern "C" fetiF_status fetiF_dual_rhs(fetiF_ctx c, const double* f_d, const double* c_d, double* d_d, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (!f_d || !d_d) return fail(c, FETIF_EINVAL, "f or d is NULL");
+    if (fetiF_status st0 = need_factors(c)) return st0;
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    PhaseTimer t6(c, st, 6);
+    HIPCHK(c, launch_permute_in(c->total_rows, c->dXperm, f_d, c->dXv, st));
+    HIPCHK(c, solve_all(c, 1, st));
+    HIPCHK(c, launch_xgather(1, c->n_lambda, c->dXGptr, c->dXGent, c->dXv, c_d, d_d, st));
+    HIPCHK(c, t6.stop());
+    return FETIF_OK;
+}
+
 extern "C" fetiF_status fetiF_apply_backward(fetiF_ctx c, const double* g_d, const double* lambda_d,
                                              double* dlambda_d, double* dtheta_d, void* stream)
 {
     if (!c) return FETIF_EINVAL;
-    if (dtheta_d) return fail(c, FETIF_ENOTSUP, "theta adjoint not available in this build");
-    (void)lambda_d;
-    return fetiF_apply(c, g_d, dlambda_d, stream);
+    if (c->sticky) return FETIF_EDEVICE;
+    if (!g_d || !dlambda_d || g_d == dlambda_d) return fail(c, FETIF_EINVAL, "g/dlambda NULL or overlapping");
+    if (dtheta_d && !lambda_d) return fail(c, FETIF_EINVAL, "dtheta needs lambda");
+    if (dtheta_d && !c->has_elems) return fail(c, FETIF_EINVAL, "dtheta needs element data at create");
+    fetiF_status st0 = fetiF_apply(c, g_d, dlambda_d, stream);
+    if (st0 != FETIF_OK || !dtheta_d) return st0;
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    PhaseTimer t6(c, st, 6);
+    HIPCHK(c, launch_scatter_dual(2, c->nsub, c->dSubRow, c->dSubM, c->dStartRows, c->dSignsSorted, c->dDmap, g_d,
+                                  lambda_d, c->dXv, c->total_rows, st));
+    HIPCHK(c, solve_all(c, 2, st));
+    HIPCHK(c, launch_elem_adjoint(c->nelem_total, c->dElems, c->dEpos, c->dDK, c->dXv, dtheta_d, st));
+    HIPCHK(c, t6.stop());
+    return FETIF_OK;
 }
 
 // ======================================================================== inspection

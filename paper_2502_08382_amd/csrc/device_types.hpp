@@ -67,6 +67,22 @@ struct GatherEnt {
     int32_t pad;
 };
 
+// Implicit-apply gather entry: one (subdomain, local multiplier) term of a
+// global multiplier, read from the solved vector at `xpos` with `sign`.
+struct XGatherEnt {
+    int64_t xpos;
+    double sign;
+};
+
+// Element of the theta-adjoint: its subdomain and the offset of its
+// permuted DOF positions (edofs entries) in the element-position table.
+struct ElemRef {
+    int32_t sub;
+    int32_t edofs;
+    int64_t pos_off;  // into the element-position table (global x rows)
+    int64_t dk_off;   // into the dK table (edofs x edofs, row-major)
+};
+
 // Packed lower-triangle row offset with rows padded to multiples of V
 // elements: row r holds columns 0..r and starts at
 // V * (V*q*(q+1)/2 + s*(q+1)) where r = q*V + s.

@@ -206,6 +206,217 @@ __global__ void trsm_level_kernel(const TrsmItem* __restrict__ items, int32_t nb
     }
 }
 
+// ---------------------------------------------------------------- TRSV
+
+// x <- P B~^T D v for every subdomain (one work-group per subdomain).  The
+// subdomain's local multipliers are sorted by their permuted DOF, so equal
+// DOFs are adjacent: the first column of each run sums the run (fixed order).
+template <int NRHS>
+__global__ __launch_bounds__(NT) void scatter_dual_kernel(const int32_t* __restrict__ sub_rowbase,
+                                                          const int32_t* __restrict__ sub_mbase,
+                                                          const int32_t* __restrict__ start_rows,
+                                                          const int8_t* __restrict__ signs,
+                                                          const int32_t* __restrict__ dmap,
+                                                          const double* __restrict__ v0,
+                                                          const double* __restrict__ v1, double* __restrict__ x)
+{
+    const int i = blockIdx.x;
+    const int rb = sub_rowbase[i], r1 = sub_rowbase[i + 1];
+    const int m0 = sub_mbase[i], m1 = sub_mbase[i + 1];
+    for (int r = rb + threadIdx.x; r < r1; r += NT)
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) x[(int64_t)r * NRHS + k] = 0.0;
+    __syncthreads();
+    for (int a = m0 + threadIdx.x; a < m1; a += NT) {
+        const int row = start_rows[a];
+        if (a > m0 && start_rows[a - 1] == row) continue;
+        double acc0 = 0.0, acc1 = 0.0;
+        for (int b = a; b < m1 && start_rows[b] == row; ++b) {
+            const double sg = (double)signs[b];
+            acc0 += sg * v0[dmap[b]];
+            if (NRHS == 2) acc1 += sg * v1[dmap[b]];
+        }
+        x[(int64_t)(rb + row) * NRHS] = acc0;
+        if (NRHS == 2) x[(int64_t)(rb + row) * NRHS + 1] = acc1;
+    }
+}
+
+// Forward substitution of one supernode per work-group (multifrontal):
+//   front = [x_s ; 0] + extend-add of the children's update vectors
+//   x_s  = L_ss^{-1} front_s        (16-row blocks through inv(L_kk))
+//   u_s  = front_r - L_rs x_s       (update vector for the parent)
+// Children are added one after another, so sums have a fixed order.
+template <int NRHS>
+__global__ __launch_bounds__(NT) void trsv_forward_kernel(const int32_t* __restrict__ sn_list,
+                                                          const DevSN* __restrict__ sns,
+                                                          const double* __restrict__ L,
+                                                          const double* __restrict__ Linv,
+                                                          const int32_t* __restrict__ child_ptr,
+                                                          const int32_t* __restrict__ child_idx,
+                                                          const int32_t* __restrict__ relpos,
+                                                          double* __restrict__ u, double* __restrict__ x)
+{
+    extern __shared__ double fr[];
+    __shared__ double xb[16 * NRHS];
+    const int sid = sn_list[blockIdx.x];
+    const DevSN s = sns[sid];
+    const int tid = threadIdx.x;
+    const int ns = s.ncols, nr = s.nrows, d = ns + nr;
+    const double* __restrict__ P = L + s.lval;
+    double* __restrict__ xs = x + (int64_t)(s.rowbase + s.first) * NRHS;
+    for (int idx = tid; idx < d * NRHS; idx += NT) fr[idx] = idx < ns * NRHS ? xs[idx] : 0.0;
+    __syncthreads();
+    for (int ci = child_ptr[sid]; ci < child_ptr[sid + 1]; ++ci) {
+        const DevSN c = sns[child_idx[ci]];
+        for (int idx = tid; idx < c.nrows * NRHS; idx += NT) {
+            const int i = idx / NRHS, k = idx - i * NRHS;
+            fr[relpos[c.rowsoff + i] * NRHS + k] += u[c.rowsoff * NRHS + idx];
+        }
+        __syncthreads();
+    }
+    const int nb = (ns + 15) >> 4;
+    for (int rb = 0; rb < nb; ++rb) {
+        const int b0 = rb * 16, bn = min(16, ns - b0);
+        if (tid < 16 * NRHS) {
+            const int i = tid / NRHS, k = tid - i * NRHS;
+            double acc = 0.0;
+            if (i < bn) {
+                const double* li = Linv + s.linv + (int64_t)rb * 256 + i;  // Linv[i][kk] at kk*16 + i
+                for (int kk = 0; kk < bn; ++kk) acc += li[kk * 16] * fr[(b0 + kk) * NRHS + k];
+            }
+            xb[tid] = acc;
+        }
+        __syncthreads();
+        if (tid < 16 * NRHS && tid / NRHS < bn) fr[b0 * NRHS + tid] = xb[tid];
+        // update every later row (diagonal part and off-diagonal rows)
+        for (int i = b0 + bn + tid; i < d; i += NT) {
+            double a0 = 0.0, a1 = 0.0;
+            for (int kk = 0; kk < bn; ++kk) {
+                const double l = P[(int64_t)(b0 + kk) * d + i];
+                a0 += l * xb[kk * NRHS];
+                if (NRHS == 2) a1 += l * xb[kk * NRHS + 1];
+            }
+            fr[i * NRHS] -= a0;
+            if (NRHS == 2) fr[i * NRHS + 1] -= a1;
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < ns * NRHS; idx += NT) xs[idx] = fr[idx];
+    for (int idx = tid; idx < nr * NRHS; idx += NT) u[s.rowsoff * NRHS + idx] = fr[ns * NRHS + idx];
+}
+
+// Backward substitution of one supernode per work-group (ancestors first):
+//   x_s = L_ss^{-T} (y_s - L_rs^T x[rows(s)])
+template <int NRHS>
+__global__ __launch_bounds__(NT) void trsv_backward_kernel(const int32_t* __restrict__ sn_list,
+                                                           const DevSN* __restrict__ sns,
+                                                           const double* __restrict__ L,
+                                                           const double* __restrict__ Linv,
+                                                           const int32_t* __restrict__ rows,
+                                                           double* __restrict__ x)
+{
+    extern __shared__ double fr[];  // ns*NRHS solution part, then nr*NRHS ancestor values
+    __shared__ double xb[16 * NRHS];
+    const int sid = sn_list[blockIdx.x];
+    const DevSN s = sns[sid];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ns = s.ncols, nr = s.nrows, d = ns + nr;
+    const double* __restrict__ P = L + s.lval;
+    double* __restrict__ xs = x + (int64_t)(s.rowbase + s.first) * NRHS;
+    double* __restrict__ xr = fr + ns * NRHS;
+    for (int idx = tid; idx < ns * NRHS; idx += NT) fr[idx] = xs[idx];
+    for (int idx = tid; idx < nr * NRHS; idx += NT) {
+        const int i = idx / NRHS, k = idx - i * NRHS;
+        xr[idx] = x[(int64_t)(s.rowbase + rows[s.rowsoff + i]) * NRHS + k];
+    }
+    __syncthreads();
+    // y_s -= L_rs^T x_r: column k of the panel against the ancestor values
+    for (int k = wv; k < ns; k += NT / 64) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int i = lane; i < nr; i += 64) {
+            const double l = P[(int64_t)k * d + ns + i];
+            a0 += l * xr[i * NRHS];
+            if (NRHS == 2) a1 += l * xr[i * NRHS + 1];
+        }
+        a0 = wave_sum(a0);
+        if (NRHS == 2) a1 = wave_sum(a1);
+        if (lane == 0) {
+            fr[k * NRHS] -= a0;
+            if (NRHS == 2) fr[k * NRHS + 1] -= a1;
+        }
+    }
+    __syncthreads();
+    const int nb = (ns + 15) >> 4;
+    for (int rb = nb - 1; rb >= 0; --rb) {
+        const int b0 = rb * 16, bn = min(16, ns - b0);
+        if (tid < 16 * NRHS) {
+            const int i = tid / NRHS, k = tid - i * NRHS;
+            double acc = 0.0;
+            if (i < bn) {
+                const double* li = Linv + s.linv + (int64_t)rb * 256 + i * 16;  // Linv[kk][i] at i*16 + kk
+                for (int kk = 0; kk < bn; ++kk) acc += li[kk] * fr[(b0 + kk) * NRHS + k];
+            }
+            xb[tid] = acc;
+        }
+        __syncthreads();
+        if (tid < 16 * NRHS && tid / NRHS < bn) fr[b0 * NRHS + tid] = xb[tid];
+        // columns before the block: y_k -= sum_i L[b0+i][k] x_{b0+i}
+        for (int k = tid; k < b0; k += NT) {
+            double a0 = 0.0, a1 = 0.0;
+            const double* lk = P + (int64_t)k * d + b0;
+            for (int i = 0; i < bn; ++i) {
+                a0 += lk[i] * xb[i * NRHS];
+                if (NRHS == 2) a1 += lk[i] * xb[i * NRHS + 1];
+            }
+            fr[k * NRHS] -= a0;
+            if (NRHS == 2) fr[k * NRHS + 1] -= a1;
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < ns * NRHS; idx += NT) xs[idx] = fr[idx];
+}
+
+__global__ __launch_bounds__(NT) void xgather_kernel(int nrhs, int64_t n_lambda, const int32_t* __restrict__ gptr,
+                                                     const XGatherEnt* __restrict__ ents,
+                                                     const double* __restrict__ x, const double* __restrict__ c,
+                                                     double* __restrict__ q)
+{
+    const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (g >= n_lambda) return;
+    double acc = 0.0;
+    for (int32_t e = gptr[g]; e < gptr[g + 1]; ++e) acc += ents[e].sign * x[ents[e].xpos * nrhs];
+    q[g] = c ? acc - c[g] : acc;
+}
+
+// x[r] = f[xperm[r]]: a concatenated DOF vector into the permuted row order
+__global__ __launch_bounds__(NT) void permute_in_kernel(int64_t n, const int32_t* __restrict__ xperm,
+                                                        const double* __restrict__ f, double* __restrict__ x)
+{
+    const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (r < n) x[r] = f[xperm[r]];
+}
+
+__global__ __launch_bounds__(NT) void elem_adjoint_kernel(int64_t nelem, const ElemRef* __restrict__ elems,
+                                                          const int32_t* __restrict__ epos,
+                                                          const double* __restrict__ dk,
+                                                          const double* __restrict__ x,
+                                                          double* __restrict__ dtheta)
+{
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= nelem) return;
+    const ElemRef E = elems[e];
+    const int32_t* pos = epos + E.pos_off;
+    const double* K = dk + E.dk_off;
+    double acc = 0.0;
+    for (int a = 0; a < E.edofs; ++a) {
+        const double ga = x[(int64_t)pos[a] * 2];
+        double t = 0.0;
+        for (int b = 0; b < E.edofs; ++b) t += K[a * E.edofs + b] * x[(int64_t)pos[b] * 2 + 1];
+        acc += ga * t;
+    }
+    dtheta[e] = -acc;
+}
+
 // ---------------------------------------------------------------- SYRK
 
 constexpr int ST = 64;   // output tile edge
@@ -498,6 +709,75 @@ hipError_t launch_trsm_level(const TrsmItem* items, int32_t nitems, int32_t wave
     const int32_t nbmax = (max_ns + 15) / 16;
     hipLaunchKernelGGL(trsm_level_kernel, dim3(nitems), dim3(64 * waves), lds, st, items, nbmax, sns, L, Linv,
                        rows, xrows, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_dual(int nrhs, int32_t nsub, const int32_t* sub_rowbase, const int32_t* sub_mbase,
+                               const int32_t* start_rows, const int8_t* signs_sorted, const int32_t* dmap_sorted,
+                               const double* v0, const double* v1, double* x, int64_t nrows_total, hipStream_t st)
+{
+    (void)nrows_total;
+    if (nsub <= 0) return hipSuccess;
+    if (nrhs == 1)
+        hipLaunchKernelGGL(scatter_dual_kernel<1>, dim3(nsub), dim3(NT), 0, st, sub_rowbase, sub_mbase, start_rows,
+                           signs_sorted, dmap_sorted, v0, v1, x);
+    else
+        hipLaunchKernelGGL(scatter_dual_kernel<2>, dim3(nsub), dim3(NT), 0, st, sub_rowbase, sub_mbase, start_rows,
+                           signs_sorted, dmap_sorted, v0, v1, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_trsv_forward_level(int nrhs, const int32_t* sn_list, int32_t n, int32_t max_front,
+                                     const DevSN* sns, const double* L, const double* Linv,
+                                     const int32_t* child_ptr, const int32_t* child_idx, const int32_t* relpos,
+                                     double* u, double* x, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const size_t lds = sizeof(double) * (size_t)max_front * nrhs;
+    if (nrhs == 1)
+        hipLaunchKernelGGL(trsv_forward_kernel<1>, dim3(n), dim3(NT), lds, st, sn_list, sns, L, Linv, child_ptr,
+                           child_idx, relpos, u, x);
+    else
+        hipLaunchKernelGGL(trsv_forward_kernel<2>, dim3(n), dim3(NT), lds, st, sn_list, sns, L, Linv, child_ptr,
+                           child_idx, relpos, u, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_trsv_backward_level(int nrhs, const int32_t* sn_list, int32_t n, int32_t max_front,
+                                      const DevSN* sns, const double* L, const double* Linv, const int32_t* rows,
+                                      double* x, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const size_t lds = sizeof(double) * (size_t)max_front * nrhs;
+    if (nrhs == 1)
+        hipLaunchKernelGGL(trsv_backward_kernel<1>, dim3(n), dim3(NT), lds, st, sn_list, sns, L, Linv, rows, x);
+    else
+        hipLaunchKernelGGL(trsv_backward_kernel<2>, dim3(n), dim3(NT), lds, st, sn_list, sns, L, Linv, rows, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_xgather(int nrhs, int64_t n_lambda, const int32_t* gptr, const XGatherEnt* ents, const double* x,
+                          const double* c, double* q, hipStream_t st)
+{
+    if (n_lambda <= 0) return hipSuccess;
+    hipLaunchKernelGGL(xgather_kernel, dim3((unsigned)((n_lambda + NT - 1) / NT)), dim3(NT), 0, st, nrhs, n_lambda,
+                       gptr, ents, x, c, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_in(int64_t n, const int32_t* xperm, const double* f, double* x, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(permute_in_kernel, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, n, xperm, f, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_elem_adjoint(int64_t nelem, const ElemRef* elems, const int32_t* epos, const double* dk,
+                               const double* x, double* dtheta, hipStream_t st)
+{
+    if (nelem <= 0) return hipSuccess;
+    hipLaunchKernelGGL(elem_adjoint_kernel, dim3((unsigned)((nelem + NT - 1) / NT)), dim3(NT), 0, st, nelem, elems,
+                       epos, dk, x, dtheta);
     return hipGetLastError();
 }
 

@@ -25,6 +25,30 @@ hipError_t launch_trsm_level(const TrsmItem* items, int32_t nitems, int32_t wave
                              const XRow* xrows, double* X, hipStream_t st);
 // dynamic LDS bytes of a TRSM level launch
 inline size_t trsm_lds_bytes(int32_t waves, int32_t max_ns) { return (size_t)waves * ((max_ns + 15) / 16) * 2048; }
+// ---- batched supernodal solves with L (nrhs = 1 or 2, vectors interleaved:
+// x[row * nrhs + r]); x holds the right-hand side on entry, the solution on exit
+// scatter: x_i = P_i B~_i^T D_i v (for each rhs vector v_r), x zeroed first
+hipError_t launch_scatter_dual(int nrhs, int32_t nsub, const int32_t* sub_rowbase, const int32_t* sub_mbase,
+                               const int32_t* start_rows, const int8_t* signs_sorted, const int32_t* dmap_sorted,
+                               const double* v0, const double* v1, double* x, int64_t nrows_total,
+                               hipStream_t st);
+hipError_t launch_trsv_forward_level(int nrhs, const int32_t* sn_list, int32_t n, int32_t max_front,
+                                     const DevSN* sns, const double* L, const double* Linv,
+                                     const int32_t* child_ptr, const int32_t* child_idx, const int32_t* relpos,
+                                     double* u, double* x, hipStream_t st);
+hipError_t launch_trsv_backward_level(int nrhs, const int32_t* sn_list, int32_t n, int32_t max_front,
+                                      const DevSN* sns, const double* L, const double* Linv, const int32_t* rows,
+                                      double* x, hipStream_t st);
+// q[g] = sum of sign * x[xpos] over the entries of g (rhs slot 0 of an nrhs
+// layout), minus c[g] when c is not NULL
+hipError_t launch_xgather(int nrhs, int64_t n_lambda, const int32_t* gptr, const XGatherEnt* ents, const double* x,
+                          const double* c, double* q, hipStream_t st);
+// x[r] = f[xperm[r]] (one rhs)
+hipError_t launch_permute_in(int64_t n, const int32_t* xperm, const double* f, double* x, hipStream_t st);
+// dtheta_e = -x0|_e^T dK x1|_e (slots 0 and 1 of a 2-rhs layout)
+hipError_t launch_elem_adjoint(int64_t nelem, const ElemRef* elems, const int32_t* epos, const double* dk,
+                               const double* x, double* dtheta, hipStream_t st);
+
 // prec: 0 f64, 1 f32, 2 bf16
 hipError_t launch_syrk(int prec, const SyrkTile* tiles, int32_t ntiles, const int32_t* lists,
                        const DevSN* sns, const double* X, void* F, hipStream_t st);

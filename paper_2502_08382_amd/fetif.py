@@ -59,7 +59,7 @@ EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply
            "fetiF_apply_backward", "fetiF_download_F", "fetiF_query", "fetiF_destroy",
            "fetiF_last_error", "fetiF_host_factor", "fetiF_hfactor_info", "fetiF_hfactor_export",
            "fetiF_hfactor_supernodes", "fetiF_hfactor_free", "fetiF_profile_enable",
-           "fetiF_profile_read", "fetiF_set_apply"]
+           "fetiF_profile_read", "fetiF_set_apply", "fetiF_apply_implicit", "fetiF_dual_rhs"]
 
 PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "backward"]
 
@@ -95,6 +95,8 @@ def load_library(path=None):
     L.fetiF_profile_enable.argtypes = [vp, ctypes.c_int]
     L.fetiF_profile_read.argtypes = [vp, ctypes.c_int, vp, vp, i32]
     L.fetiF_set_apply.argtypes = [vp, i32, i32, i32]
+    L.fetiF_apply_implicit.argtypes = [vp, vp, vp, vp]
+    L.fetiF_dual_rhs.argtypes = [vp, vp, vp, vp, vp]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype if name == "fetiF_last_error" else ctypes.c_int
     _lib = L
@@ -198,6 +200,12 @@ class FetiContext:
     def apply_backward(self, g, lam, dlam, dtheta=None, stream=None):
         self._check(self.L.fetiF_apply_backward(self.h, _dptr(g), _dptr(lam), _dptr(dlam), _dptr(dtheta),
                                                 _stream(stream)))
+
+    def apply_implicit(self, lam, q, stream=None):
+        self._check(self.L.fetiF_apply_implicit(self.h, _dptr(lam), _dptr(q), _stream(stream)))
+
+    def dual_rhs(self, f, d, c=None, stream=None):
+        self._check(self.L.fetiF_dual_rhs(self.h, _dptr(f), _dptr(c), _dptr(d), _stream(stream)))
 
     def download_F(self, i):
         out = np.empty((self.m[i], self.m[i]))
