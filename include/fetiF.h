@@ -76,7 +76,10 @@ typedef enum { FETIF_F64 = 0, FETIF_F32 = 1, FETIF_BF16 = 2 } fetiF_prec;
  *               of fetiF_apply_backward: element e couples the local DOFs
  *               elem_dofs[e*edofs .. +edofs) and dK (edofs x edofs,
  *               row-major) is dK_reg,i/dtheta_e, the same for every element
- *               of the subdomain.  nelem=0 disables the adjoint. */
+ *               of the subdomain.  nelem=0 disables the adjoint.
+ *  nkernel,R    optional kernel basis R_i of K_i (n x nkernel, row-major,
+ *               nkernel <= 6; Sec. II) defining G = B R for the solver entry
+ *               points; nkernel=0 in any subdomain disables them. */
 typedef struct {
     int32_t n;
     int32_t dofs_per_node;
@@ -92,6 +95,8 @@ typedef struct {
     int32_t edofs;
     const int32_t* elem_dofs;
     const double* dK;
+    int32_t nkernel;
+    const double* R;
 } fetiF_subdomain;
 
 /* Options; zero-initialised fields select defaults. */
@@ -166,6 +171,54 @@ fetiF_status fetiF_apply_implicit(fetiF_ctx ctx, const double* lambda_d, double*
  * order, sum n_i entries), c_d the n_lambda constraint values (may be NULL
  * for c = 0).  Requires every subdomain factored.  Asynchronous. */
 fetiF_status fetiF_dual_rhs(fetiF_ctx ctx, const double* f_d, const double* c_d, double* d_d, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Dual solver (paper Sec. II and Alg. 1), all in FP64 on the device.
+ * Needs the kernel bases R_i at create.  G = B R, e = R^T f,
+ * P = I - G (G^T G)^{-1} G^T with (G^T G)^{-1} formed densely at create.
+ * --------------------------------------------------------------------- */
+
+/* e_d = R^T f: f_d concatenated subdomain loads (sum n_i), e_d one entry per
+ * kernel vector (subdomain order).  Asynchronous. */
+fetiF_status fetiF_coarse_rhs(fetiF_ctx ctx, const double* f_d, double* e_d, void* stream);
+
+typedef struct {
+    double tol;          /* stop when ||w_k|| <= tol ||w_0|| (default 1e-9) */
+    int32_t max_iters;   /* default 1000 */
+    int32_t fixed_iters; /* > 0: run exactly this many iterations */
+    int32_t implicit;    /* 1: apply F implicitly with the factors; 0: assembled F~ */
+    int32_t check_every; /* iterations between convergence checks (default 10) */
+    int32_t refine;      /* 1: FP64 iterative refinement around the assembled
+                            (FP32/BF16) operator: outer true residual
+                            P(d - F lambda) with the implicit FP64 operator,
+                            inner PCPG on the correction to inner_tol */
+    double inner_tol;    /* relative tolerance of each inner solve (default 1e-4) */
+    int32_t use_graph;   /* 1: replay captured iterations (needs a non-NULL stream) */
+} fetiF_pcpg_options;
+
+typedef struct {
+    int32_t iters;        /* operator applications in PCPG iterations (all inner solves) */
+    int32_t outer;        /* refinement steps (0 without refinement) */
+    double rel_residual;  /* ||w|| / ||w_0|| at exit: recursive (no refinement) or
+                             true FP64 projected residual (refinement) */
+    double w0;            /* ||w_0|| */
+} fetiF_pcpg_result;
+
+/* Solve the dual problem (eq. tfetidualproblem) for lambda by PCPG with
+ * M = I and lambda_0 = G (G^T G)^{-1} e (Alg. 1).  d_d (n_lambda) from
+ * fetiF_dual_rhs, e_d from fetiF_coarse_rhs; lambda_d receives the result.
+ * Enqueued on `stream`; the call waits for the stream to report the
+ * iteration count (every check_every iterations, and at the end). */
+fetiF_status fetiF_pcpg(fetiF_ctx ctx, const double* d_d, const double* e_d, double* lambda_d,
+                        const fetiF_pcpg_options* opt, fetiF_pcpg_result* res, void* stream);
+
+/* Primal recovery: alpha = -(G^T G)^{-1} G^T (d - F lambda) (eq.
+ * alphacompute, F applied implicitly in FP64) and u_i = K_reg,i^{-1} (f_i -
+ * B~_i^T lambda_i) + R_i alpha_i (eq. solutionUeval).  u_d has sum n_i
+ * entries (local DOF order per subdomain), alpha_d one per kernel vector.
+ * Asynchronous. */
+fetiF_status fetiF_primal(fetiF_ctx ctx, const double* f_d, const double* d_d, const double* lambda_d,
+                          double* alpha_d, double* u_d, void* stream);
 
 /* Copy F~_i of one subdomain to host_out as a full m_i x m_i row-major
  * matrix in the local multiplier order of create (test/debug hook).

@@ -1,262 +1,11 @@
 // The fetiF context: preparation (ordering, symbolic analysis, schedules,
 // device structures), per-step factorisation + upload, assembly and
 // application (paper Alg. 2 and Sec. IV-B).
-#include <hip/hip_runtime_api.h>
+#include "context.hpp"
 
-#include <algorithm>
-#include <atomic>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <mutex>
-#include <new>
-#include <string>
-#include <thread>
-#include <vector>
-
-#include "../../include/fetiF.h"
-#include "device_types.hpp"
-#include "host_sparse.hpp"
-#include "internal.hpp"
-#include "kernels.hpp"
-
-using namespace fetif;
+thread_local std::string fetif::g_create_error;
 
 namespace {
-
-thread_local std::string g_create_error;
-
-template <typename Fn>
-void parallel_for(int32_t n, int nthreads, Fn fn)
-{
-    if (nthreads <= 1 || n <= 1) {
-        for (int32_t i = 0; i < n; ++i) fn(i);
-        return;
-    }
-    std::atomic<int32_t> next(0);
-    std::vector<std::thread> th;
-    int nt = std::min<int>(nthreads, n);
-    th.reserve(nt);
-    for (int t = 0; t < nt; ++t)
-        th.emplace_back([&]() {
-            for (;;) {
-                int32_t i = next.fetch_add(1);
-                if (i >= n) break;
-                fn(i);
-            }
-        });
-    for (auto& t : th) t.join();
-}
-
-struct SubPlan {
-    int32_t n = 0, m = 0, dpn = 1;
-    int64_t nnzA = 0;
-    Symbolic sym;
-    std::vector<int32_t> sigma;   // sorted position -> caller's local multiplier
-    std::vector<int32_t> start;   // sorted start rows (permuted DOF of each column)
-    std::vector<int32_t> j0, w;   // per supernode
-    std::vector<int64_t> xoff;    // per supernode, local
-    int64_t nx = 0;
-    std::vector<int32_t> b_dof, dual_map;
-    std::vector<int8_t> b_sign;
-    int32_t nelem = 0, edofs = 0;
-    std::vector<int32_t> elem_dofs;
-    std::vector<double> dK;
-    // global placement
-    int64_t lbase = 0, xbase = 0, fbase = 0;
-    int32_t snbase = 0, rowbase = 0, dbase = 0, band0 = 0, nband = 0;
-    int32_t inv0 = 0, ninv = 0;
-    std::string err;
-};
-
-template <typename T>
-struct DevBuf {
-    T* p = nullptr;
-    size_t n = 0;
-};
-
-}  // namespace
-
-struct fetiF_ctx_s {
-    int device = 0;
-    int64_t n_lambda = 0;
-    int32_t nsub = 0;
-    fetiF_options opt{};
-    int prec = 0;
-    int nthreads = 1;
-    std::vector<SubPlan> subs;
-    // schedules
-    std::vector<std::vector<TrsmItem>> level_items;
-    std::vector<int32_t> level_waves, level_maxns;
-    int32_t ninv = 0;
-    int64_t total_linv = 0;
-    // batched solves with L: levels of all supernodes, tree tables
-    std::vector<std::vector<int32_t>> solve_levels;
-    std::vector<int32_t> solve_maxfront;
-    std::vector<int64_t> solve_off;
-    int64_t total_u = 0;
-    int64_t nelem_total = 0;
-    bool has_elems = false;
-    std::vector<int64_t> level_off;
-    int32_t apply_nch = 1;
-    int32_t nbands = 0;
-    int32_t nsyrk = 0;
-    int64_t total_L = 0, total_X = 0, total_F = 0, total_z = 0, total_rows = 0, sum_m = 0;
-    double trsm_flops = 0, syrk_flops = 0, factor_flops = 0;
-    // device buffers
-    double* dL = nullptr;
-    double* dX = nullptr;
-    double* dLinv = nullptr;
-    InvItem* dInv = nullptr;
-    int32_t* dSolveSn = nullptr;    // supernode ids per solve level
-    int32_t* dChildPtr = nullptr;
-    int32_t* dChildIdx = nullptr;
-    int32_t* dRelpos = nullptr;
-    double* dU = nullptr;           // update vectors (2 rhs)
-    double* dXv = nullptr;          // solve vectors (2 rhs, permuted rows)
-    int32_t* dSubRow = nullptr;     // nsub+1 row bases
-    int32_t* dSubM = nullptr;       // nsub+1 multiplier bases
-    int32_t* dStartRows = nullptr;  // sorted start rows per subdomain
-    int8_t* dSignsSorted = nullptr;
-    int32_t* dXGptr = nullptr;
-    XGatherEnt* dXGent = nullptr;
-    int32_t* dXperm = nullptr;      // x row -> position in the concatenated DOF vector
-    ElemRef* dElems = nullptr;
-    int32_t* dEpos = nullptr;
-    double* dDK = nullptr;
-    void* dF = nullptr;
-    void* dZ = nullptr;
-    DevSN* dSN = nullptr;
-    int32_t* dRows = nullptr;
-    XRow* dXRows = nullptr;
-    RhsUnit* dUnits = nullptr;
-    TrsmItem* dItems = nullptr;
-    SyrkTile* dTiles = nullptr;
-    int32_t* dLists = nullptr;
-    Band* dBands = nullptr;
-    int64_t* dBandZ = nullptr;
-    int32_t* dGptr = nullptr;
-    GatherEnt* dGent = nullptr;
-    int32_t* dDmap = nullptr;
-    double* hStage = nullptr;  // pinned staging of factor values
-    hipEvent_t upload_done = nullptr;
-    bool upload_pending = false;
-    std::vector<void*> allocations;
-    std::vector<void*> apply_allocs;  // buffers of the current apply plan
-    // phase timing
-    struct Rec {
-        int phase;
-        hipEvent_t a, b;
-    };
-    bool profiling = false;
-    std::vector<Rec> recs;
-    std::vector<hipEvent_t> ev_pool;
-    double prof_ms[FETIF_NPHASES] = {0};
-    int64_t prof_cnt[FETIF_NPHASES] = {0};
-    // state
-    std::vector<uint8_t> uploaded;
-    int32_t n_uploaded = 0;
-    bool assembled = false;
-    bool sticky = false;
-    std::string last_error;
-};
-
-namespace {
-
-fetiF_status fail(fetiF_ctx c, fetiF_status st, const std::string& msg)
-{
-    if (c) c->last_error = msg;
-    else g_create_error = msg;
-    return st;
-}
-
-fetiF_status hip_fail(fetiF_ctx c, hipError_t e, const char* what)
-{
-    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
-    if (c) {
-        c->sticky = true;
-        c->last_error = msg;
-    } else {
-        g_create_error = msg;
-    }
-    return FETIF_EDEVICE;
-}
-
-// Event pair around one device phase when profiling is on.
-struct PhaseTimer {
-    fetiF_ctx c;
-    hipStream_t st;
-    int phase;
-    hipEvent_t b = nullptr;
-    hipError_t err = hipSuccess;
-    hipEvent_t get()
-    {
-        if (!c->ev_pool.empty()) {
-            hipEvent_t e = c->ev_pool.back();
-            c->ev_pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        err = hipEventCreate(&e);
-        return e;
-    }
-    PhaseTimer(fetiF_ctx c_, hipStream_t s_, int ph) : c(c_), st(s_), phase(ph)
-    {
-        if (!c->profiling) return;
-        hipEvent_t a = get();
-        b = get();
-        if (err == hipSuccess) err = hipEventRecord(a, st);
-        c->recs.push_back({phase, a, b});
-    }
-    hipError_t stop()
-    {
-        if (!c->profiling || !b) return err;
-        if (err == hipSuccess) err = hipEventRecord(b, st);
-        return err;
-    }
-};
-
-#define HIPCHK(ctx, call)                                         \
-    do {                                                          \
-        hipError_t e_ = (call);                                   \
-        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);  \
-    } while (0)
-
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-template <typename T>
-hipError_t dalloc(fetiF_ctx c, T** p, size_t count)
-{
-    *p = nullptr;
-    if (count == 0) count = 1;
-    void* q = nullptr;
-    hipError_t e = hipMalloc(&q, sizeof(T) * count);
-    if (e == hipSuccess) {
-        c->allocations.push_back(q);
-        *p = (T*)q;
-    }
-    return e;
-}
-
-template <typename T>
-hipError_t upload(T* d, const std::vector<T>& h)
-{
-    if (h.empty()) return hipSuccess;
-    return hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
-}
 
 bool plan_subdomain(const fetiF_subdomain& in, const fetiF_options& opt, int64_t n_lambda, SubPlan& P)
 {
@@ -287,6 +36,11 @@ bool plan_subdomain(const fetiF_subdomain& in, const fetiF_options& opt, int64_t
         P.dK.assign(in.dK, in.dK + (size_t)in.edofs * in.edofs);
         for (int32_t v : P.elem_dofs)
             if (v < 0 || v >= in.n) { P.err = "elem_dofs out of range"; return false; }
+    }
+    if (in.nkernel > 0) {
+        if (in.nkernel > COARSE_MAXK || !in.R) { P.err = "nkernel must be <= 6 with R given"; return false; }
+        P.nk = in.nkernel;
+        P.R.assign(in.R, in.R + (size_t)in.n * in.nkernel);
     }
     SymbolicOptions so;
     so.leaf_nodes = opt.leaf_nodes;
@@ -773,6 +527,77 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         c->nelem_total = (int64_t)elems.size();
     }
 
+    // coarse space G = B R (sorted multiplier order) and G^T G
+    std::vector<CoarseSub> csub;
+    std::vector<double> gvals, Rcat, GtG;
+    std::vector<int32_t> g2ptr;
+    std::vector<GEnt> g2ent;
+    c->has_coarse = true;
+    for (int32_t i = 0; i < nsub; ++i)
+        if (c->subs[i].nk <= 0) c->has_coarse = false;
+    if (c->has_coarse) {
+        int32_t koff = 0;
+        int64_t rbs = 0;
+        for (int32_t i = 0; i < nsub; ++i) {
+            SubPlan& P = c->subs[i];
+            P.koff = koff;
+            CoarseSub cs;
+            cs.mbase = P.dbase;
+            cs.gvbase = 0;
+            cs.rbase = rbs;
+            cs.m = P.m;
+            cs.nk = P.nk;
+            cs.koff = koff;
+            cs.n = P.n;
+            cs.rowbase = P.rowbase;
+            cs.pad = 0;
+            csub.push_back(cs);
+            for (int32_t a = 0; a < P.m; ++a) {
+                const int32_t j = P.sigma[a];
+                for (int32_t k = 0; k < P.nk; ++k)
+                    gvals.push_back((double)P.b_sign[j] * P.R[(size_t)P.b_dof[j] * P.nk + k]);
+            }
+            Rcat.insert(Rcat.end(), P.R.begin(), P.R.end());
+            koff += P.nk;
+            rbs += P.n;
+        }
+        c->ncoarse = koff;
+        // rows of G per global multiplier, ascending subdomain; gvals rows are
+        // laid out with each subdomain's own nk, so keep explicit offsets
+        std::vector<int64_t> gvoff(nsub + 1, 0);
+        for (int32_t i = 0; i < nsub; ++i) gvoff[i + 1] = gvoff[i] + (int64_t)c->subs[i].m * c->subs[i].nk;
+        g2ptr.assign(n_lambda + 1, 0);
+        for (int32_t i = 0; i < nsub; ++i)
+            for (int32_t g : c->subs[i].dual_map) g2ptr[g + 1]++;
+        for (int64_t g = 0; g < n_lambda; ++g) g2ptr[g + 1] += g2ptr[g];
+        g2ent.resize(g2ptr[n_lambda]);
+        {
+            std::vector<int32_t> fill(g2ptr.begin(), g2ptr.end() - 1);
+            for (int32_t i = 0; i < nsub; ++i) {
+                const SubPlan& P = c->subs[i];
+                for (int32_t a = 0; a < P.m; ++a) {
+                    GEnt e;
+                    e.gv = gvoff[i] + (int64_t)a * P.nk;
+                    e.koff = P.koff;
+                    e.nk = P.nk;
+                    g2ent[fill[P.dual_map[P.sigma[a]]]++] = e;
+                }
+            }
+        }
+        for (int32_t i = 0; i < nsub; ++i) csub[i].gvbase = gvoff[i];
+        const int64_t nc = c->ncoarse;
+        GtG.assign((size_t)nc * nc, 0.0);
+        for (int64_t g = 0; g < n_lambda; ++g)
+            for (int32_t e1 = g2ptr[g]; e1 < g2ptr[g + 1]; ++e1)
+                for (int32_t e2 = g2ptr[g]; e2 < g2ptr[g + 1]; ++e2) {
+                    const GEnt& A1 = g2ent[e1];
+                    const GEnt& A2 = g2ent[e2];
+                    for (int32_t k1 = 0; k1 < A1.nk; ++k1)
+                        for (int32_t k2 = 0; k2 < A2.nk; ++k2)
+                            GtG[(size_t)(A1.koff + k1) * nc + A2.koff + k2] += gvals[A1.gv + k1] * gvals[A2.gv + k2];
+                }
+    }
+
     // ---- device memory
     {
         int ndev = 0;
@@ -848,6 +673,28 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         CK(upload(c->dEpos, epos));
         CK(dalloc(c, &c->dDK, dks.size()));
         CK(upload(c->dDK, dks));
+    }
+    if (c->has_coarse) {
+        const int64_t nc = c->ncoarse;
+        CK(dalloc(c, &c->dCoarse, csub.size()));
+        CK(upload(c->dCoarse, csub));
+        CK(dalloc(c, &c->dGv, gvals.size()));
+        CK(upload(c->dGv, gvals));
+        CK(dalloc(c, &c->dGptr2, g2ptr.size()));
+        CK(upload(c->dGptr2, g2ptr));
+        CK(dalloc(c, &c->dGent2, g2ent.size()));
+        CK(upload(c->dGent2, g2ent));
+        CK(dalloc(c, &c->dR, Rcat.size()));
+        CK(upload(c->dR, Rcat));
+        CK(dalloc(c, &c->dAinv, (size_t)(nc * nc)));
+        CK(upload(c->dAinv, GtG));
+        CK(dalloc(c, &c->dVec, (size_t)(7 * n_lambda)));
+        CK(dalloc(c, &c->dCvec, (size_t)(3 * nc + 2 * nc)));
+        CK(dalloc(c, &c->dPart, (size_t)(2 * DOT_PARTS)));
+        CK(dalloc(c, &c->dSc, (size_t)SC_COUNT + 8));
+        // (G^T G)^{-1} in place by Gauss-Jordan steps on the device; the two
+        // trailing coarse vectors serve as the pivot row/column buffers
+        CK(launch_gauss_jordan_inverse((int32_t)nc, c->dAinv, c->dCvec + 3 * nc, c->dCvec + 4 * nc, nullptr));
     }
     CK(dalloc(c, &c->dSN, sns.size()));
     CK(dalloc(c, &c->dRows, rows.size()));
@@ -986,6 +833,12 @@ extern "C" fetiF_status fetiF_set_apply(fetiF_ctx c, int32_t band_elems, int32_t
         return fail(c, FETIF_EINVAL, "band_elems >= 0, rows in {0,1,2}, nontemporal in {-1,0,1}");
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    if (c->pcpg_graph) {
+        HIPCHK(c, hipDeviceSynchronize());
+        (void)hipGraphExecDestroy(c->pcpg_graph);
+        c->pcpg_graph = nullptr;
+        c->pcpg_graph_key = -1;
+    }
     if (rows) c->opt.apply_rows = rows;
     if (nontemporal >= 0) c->opt.apply_nontemporal = nontemporal;
     if (band_elems > 0 && band_elems != c->opt.apply_band) {
@@ -998,11 +851,9 @@ extern "C" fetiF_status fetiF_set_apply(fetiF_ctx c, int32_t band_elems, int32_t
     return FETIF_OK;
 }
 
-namespace {
-
 // Forward and backward substitution with every L_i on the nrhs vectors held
-// in c->dXv (permuted rows, interleaved); phase 6 of the timers.
-hipError_t solve_all(fetiF_ctx c, int nrhs, hipStream_t st)
+// in c->dXv (permuted rows, interleaved).
+hipError_t fetif::solve_all(fetiF_ctx c, int nrhs, hipStream_t st)
 {
     hipError_t e;
     const int32_t nl = (int32_t)c->solve_levels.size();
@@ -1022,13 +873,11 @@ hipError_t solve_all(fetiF_ctx c, int nrhs, hipStream_t st)
     return hipSuccess;
 }
 
-fetiF_status need_factors(fetiF_ctx c)
+fetiF_status fetif::need_factors(fetiF_ctx c)
 {
     if (c->n_uploaded != c->nsub) return fail(c, FETIF_ESTATE, "solve before every subdomain was factored");
     return FETIF_OK;
 }
-
-}  // namespace
 
 extern "C" fetiF_status fetiF_apply_implicit(fetiF_ctx c, const double* lambda_d, double* q_d, void* stream)
 {
@@ -1200,6 +1049,9 @@ extern "C" fetiF_status fetiF_destroy(fetiF_ctx c)
             (void)hipEventDestroy(r.b);
         }
         for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+        if (c->pcpg_graph) (void)hipGraphExecDestroy(c->pcpg_graph);
+        if (c->hHist) (void)hipHostFree(c->hHist);
+        if (c->dHist) (void)hipFree(c->dHist);
         for (void* p : c->allocations) (void)hipFree(p);
         free_apply(c);
         if (c->hStage) (void)hipHostFree(c->hStage);

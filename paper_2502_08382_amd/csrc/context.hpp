@@ -1,0 +1,287 @@
+// The fetiF context and the helpers shared by the library's host files.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/fetiF.h"
+#include "device_types.hpp"
+#include "host_sparse.hpp"
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "solver_kernels.hpp"
+
+
+namespace fetif {
+
+// message of the last failed create (per host thread)
+extern thread_local std::string g_create_error;
+
+template <typename Fn>
+void parallel_for(int32_t n, int nthreads, Fn fn)
+{
+    if (nthreads <= 1 || n <= 1) {
+        for (int32_t i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    std::atomic<int32_t> next(0);
+    std::vector<std::thread> th;
+    int nt = std::min<int>(nthreads, n);
+    th.reserve(nt);
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&]() {
+            for (;;) {
+                int32_t i = next.fetch_add(1);
+                if (i >= n) break;
+                fn(i);
+            }
+        });
+    for (auto& t : th) t.join();
+}
+
+struct SubPlan {
+    int32_t n = 0, m = 0, dpn = 1;
+    int64_t nnzA = 0;
+    Symbolic sym;
+    std::vector<int32_t> sigma;   // sorted position -> caller's local multiplier
+    std::vector<int32_t> start;   // sorted start rows (permuted DOF of each column)
+    std::vector<int32_t> j0, w;   // per supernode
+    std::vector<int64_t> xoff;    // per supernode, local
+    int64_t nx = 0;
+    std::vector<int32_t> b_dof, dual_map;
+    std::vector<int8_t> b_sign;
+    int32_t nelem = 0, edofs = 0;
+    std::vector<int32_t> elem_dofs;
+    std::vector<double> dK;
+    // global placement
+    int64_t lbase = 0, xbase = 0, fbase = 0;
+    int32_t snbase = 0, rowbase = 0, dbase = 0, band0 = 0, nband = 0;
+    int32_t inv0 = 0, ninv = 0;
+    int32_t nk = 0;              // kernel dimension (0: none given)
+    std::vector<double> R;       // n x nk row-major
+    int32_t koff = 0;            // first coarse unknown
+    std::string err;
+};
+
+}  // namespace fetif
+
+using namespace fetif;
+
+struct fetiF_ctx_s {
+    int device = 0;
+    int64_t n_lambda = 0;
+    int32_t nsub = 0;
+    fetiF_options opt{};
+    int prec = 0;
+    int nthreads = 1;
+    std::vector<SubPlan> subs;
+    // schedules
+    std::vector<std::vector<TrsmItem>> level_items;
+    std::vector<int32_t> level_waves, level_maxns;
+    int32_t ninv = 0;
+    int64_t total_linv = 0;
+    // batched solves with L: levels of all supernodes, tree tables
+    std::vector<std::vector<int32_t>> solve_levels;
+    std::vector<int32_t> solve_maxfront;
+    std::vector<int64_t> solve_off;
+    int64_t total_u = 0;
+    int64_t nelem_total = 0;
+    bool has_elems = false;
+    std::vector<int64_t> level_off;
+    int32_t apply_nch = 1;
+    int32_t nbands = 0;
+    int32_t nsyrk = 0;
+    int64_t total_L = 0, total_X = 0, total_F = 0, total_z = 0, total_rows = 0, sum_m = 0;
+    double trsm_flops = 0, syrk_flops = 0, factor_flops = 0;
+    // device buffers
+    double* dL = nullptr;
+    double* dX = nullptr;
+    double* dLinv = nullptr;
+    InvItem* dInv = nullptr;
+    int32_t* dSolveSn = nullptr;    // supernode ids per solve level
+    int32_t* dChildPtr = nullptr;
+    int32_t* dChildIdx = nullptr;
+    int32_t* dRelpos = nullptr;
+    double* dU = nullptr;           // update vectors (2 rhs)
+    double* dXv = nullptr;          // solve vectors (2 rhs, permuted rows)
+    int32_t* dSubRow = nullptr;     // nsub+1 row bases
+    int32_t* dSubM = nullptr;       // nsub+1 multiplier bases
+    int32_t* dStartRows = nullptr;  // sorted start rows per subdomain
+    int8_t* dSignsSorted = nullptr;
+    int32_t* dXGptr = nullptr;
+    XGatherEnt* dXGent = nullptr;
+    int32_t* dXperm = nullptr;      // x row -> position in the concatenated DOF vector
+    ElemRef* dElems = nullptr;
+    int32_t* dEpos = nullptr;
+    double* dDK = nullptr;
+    void* dF = nullptr;
+    void* dZ = nullptr;
+    DevSN* dSN = nullptr;
+    int32_t* dRows = nullptr;
+    XRow* dXRows = nullptr;
+    RhsUnit* dUnits = nullptr;
+    TrsmItem* dItems = nullptr;
+    SyrkTile* dTiles = nullptr;
+    int32_t* dLists = nullptr;
+    Band* dBands = nullptr;
+    int64_t* dBandZ = nullptr;
+    int32_t* dGptr = nullptr;
+    GatherEnt* dGent = nullptr;
+    int32_t* dDmap = nullptr;
+    double* hStage = nullptr;  // pinned staging of factor values
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+    std::vector<void*> allocations;
+    std::vector<void*> apply_allocs;  // buffers of the current apply plan
+    // phase timing
+    struct Rec {
+        int phase;
+        hipEvent_t a, b;
+    };
+    bool profiling = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> ev_pool;
+    double prof_ms[FETIF_NPHASES] = {0};
+    int64_t prof_cnt[FETIF_NPHASES] = {0};
+    // coarse space and solver (present when every subdomain gave R_i)
+    bool has_coarse = false;
+    int32_t ncoarse = 0;
+    CoarseSub* dCoarse = nullptr;
+    double* dGv = nullptr;
+    int32_t* dGptr2 = nullptr;
+    GEnt* dGent2 = nullptr;
+    double* dAinv = nullptr;   // (G^T G)^{-1}, dense ncoarse x ncoarse
+    double* dR = nullptr;      // concatenated R_i (sum n_i x nk_i)
+    double* dVec = nullptr;    // solver work vectors, 7 x n_lambda
+    double* dCvec = nullptr;   // 3 x ncoarse
+    double* dPart = nullptr;   // 2 x DOT_PARTS
+    double* dSc = nullptr;     // SC_COUNT scalars
+    double* dHist = nullptr;   // ||w_k||^2 history
+    double* hHist = nullptr;   // pinned copy
+    int32_t hist_cap = 0;
+    // captured solver iterations (rebuilt when the apply plan changes)
+    hipGraphExec_t pcpg_graph = nullptr;
+    hipStream_t pcpg_graph_stream = nullptr;
+    int32_t pcpg_graph_key = -1;
+    const double* pcpg_lam = nullptr;
+    // state
+    std::vector<uint8_t> uploaded;
+    int32_t n_uploaded = 0;
+    bool assembled = false;
+    bool sticky = false;
+    std::string last_error;
+};
+
+namespace fetif {
+
+inline fetiF_status fail(fetiF_ctx c, fetiF_status st, const std::string& msg)
+{
+    if (c) c->last_error = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+inline fetiF_status hip_fail(fetiF_ctx c, hipError_t e, const char* what)
+{
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    if (c) {
+        c->sticky = true;
+        c->last_error = msg;
+    } else {
+        g_create_error = msg;
+    }
+    return FETIF_EDEVICE;
+}
+
+// Event pair around one device phase when profiling is on.
+struct PhaseTimer {
+    fetiF_ctx c;
+    hipStream_t st;
+    int phase;
+    hipEvent_t b = nullptr;
+    hipError_t err = hipSuccess;
+    hipEvent_t get()
+    {
+        if (!c->ev_pool.empty()) {
+            hipEvent_t e = c->ev_pool.back();
+            c->ev_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        err = hipEventCreate(&e);
+        return e;
+    }
+    PhaseTimer(fetiF_ctx c_, hipStream_t s_, int ph) : c(c_), st(s_), phase(ph)
+    {
+        if (!c->profiling) return;
+        hipEvent_t a = get();
+        b = get();
+        if (err == hipSuccess) err = hipEventRecord(a, st);
+        c->recs.push_back({phase, a, b});
+    }
+    hipError_t stop()
+    {
+        if (!c->profiling || !b) return err;
+        if (err == hipSuccess) err = hipEventRecord(b, st);
+        return err;
+    }
+};
+
+#define HIPCHK(ctx, call)                                         \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);  \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+hipError_t dalloc(fetiF_ctx c, T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(T) * count);
+    if (e == hipSuccess) {
+        c->allocations.push_back(q);
+        *p = (T*)q;
+    }
+    return e;
+}
+
+template <typename T>
+hipError_t upload(T* d, const std::vector<T>& h)
+{
+    if (h.empty()) return hipSuccess;
+    return hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
+}
+
+
+// batched forward + backward solves with every L_i on c->dXv (context.cpp)
+hipError_t solve_all(fetiF_ctx c, int nrhs, hipStream_t st);
+// FETIF_ESTATE unless every subdomain has been factored
+fetiF_status need_factors(fetiF_ctx c);
+
+}  // namespace fetif

@@ -1,0 +1,296 @@
+// Dual solver on the device: projected conjugate gradients (paper Alg. 1,
+// M = I), FP64 iterative refinement around a reduced-precision operator, and
+// the primal recovery of alpha and u (Sec. II).
+#include "context.hpp"
+
+namespace {
+
+struct Work {
+    double *r, *w, *y, *p, *q, *rt, *dl;
+    double *t, *s;
+};
+
+Work work_of(fetiF_ctx c)
+{
+    const int64_t n = c->n_lambda;
+    Work W;
+    W.r = c->dVec;
+    W.w = c->dVec + n;
+    W.y = c->dVec + 2 * n;
+    W.p = c->dVec + 3 * n;
+    W.q = c->dVec + 4 * n;
+    W.rt = c->dVec + 5 * n;
+    W.dl = c->dVec + 6 * n;
+    W.t = c->dCvec;
+    W.s = c->dCvec + c->ncoarse;
+    return W;
+}
+
+hipError_t apply_op(fetiF_ctx c, int implicit, const double* x, double* out, hipStream_t st)
+{
+    fetiF_status s = implicit ? fetiF_apply_implicit(c, x, out, st) : fetiF_apply(c, x, out, st);
+    return s == FETIF_OK ? hipSuccess : hipErrorUnknown;
+}
+
+// out = P in = in - G (G^T G)^{-1} G^T in
+hipError_t project(fetiF_ctx c, const Work& W, const double* in, double* out, hipStream_t st)
+{
+    hipError_t e;
+    if ((e = launch_gt(c->nsub, c->dCoarse, c->dGv, c->dDmap, in, W.t, st)) != hipSuccess) return e;
+    if ((e = launch_gemv(c->ncoarse, c->dAinv, W.t, W.s, st)) != hipSuccess) return e;
+    return launch_gs(c->n_lambda, 1.0, -1.0, c->dGptr2, c->dGent2, c->dGv, W.s, in, out, st);
+}
+
+// one iteration of Alg. 1 (the loop body), all scalars on the device
+hipError_t iteration(fetiF_ctx c, const Work& W, int implicit, double* lam, hipStream_t st)
+{
+    hipError_t e;
+    const int64_t n = c->n_lambda;
+    if ((e = apply_op(c, implicit, W.p, W.q, st)) != hipSuccess) return e;
+    if ((e = launch_dot(n, W.p, W.q, nullptr, 1, c->dPart, c->dSc, c->dHist, c->hist_cap, st)) != hipSuccess)
+        return e;
+    if ((e = launch_update_lr(n, c->dSc, W.p, W.q, lam, W.r, st)) != hipSuccess) return e;
+    if ((e = project(c, W, W.r, W.w, st)) != hipSuccess) return e;
+    if ((e = project(c, W, W.w, W.y, st)) != hipSuccess) return e;  // y = P M w, M = I
+    if ((e = launch_dot(n, W.w, W.y, W.w, 2, c->dPart, c->dSc, c->dHist, c->hist_cap, st)) != hipSuccess) return e;
+    return launch_update_p(n, 1, c->dSc, W.y, W.p, st);
+}
+
+hipError_t ensure_hist(fetiF_ctx c, int32_t cap)
+{
+    if (cap <= c->hist_cap) return hipSuccess;
+    if (c->dHist) (void)hipFree(c->dHist);
+    if (c->hHist) (void)hipHostFree(c->hHist);
+    c->dHist = nullptr;
+    c->hHist = nullptr;
+    c->hist_cap = 0;
+    hipError_t e = hipMalloc((void**)&c->dHist, sizeof(double) * (size_t)cap);
+    if (e != hipSuccess) return e;
+    e = hipHostMalloc((void**)&c->hHist, sizeof(double) * (size_t)cap, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    c->hist_cap = cap;
+    // captured iterations refer to the old history buffer
+    if (c->pcpg_graph) {
+        (void)hipGraphExecDestroy(c->pcpg_graph);
+        c->pcpg_graph = nullptr;
+        c->pcpg_graph_key = -1;
+    }
+    return hipSuccess;
+}
+
+// run `count` iterations, replaying a captured chunk when allowed
+hipError_t run_iters(fetiF_ctx c, const Work& W, int implicit, double* lam, int32_t count, int32_t chunk,
+                     bool graph, hipStream_t st)
+{
+    hipError_t e;
+    if (graph && st != nullptr && count >= chunk) {
+        const int32_t key = (implicit ? 1 : 0) | (chunk << 1);
+        const bool reuse = c->pcpg_graph && c->pcpg_graph_key == key && c->pcpg_graph_stream == st &&
+                           c->pcpg_lam == lam;
+        if (!reuse) {
+            if (c->pcpg_graph) {
+                (void)hipGraphExecDestroy(c->pcpg_graph);
+                c->pcpg_graph = nullptr;
+            }
+            const bool prof = c->profiling;
+            c->profiling = false;  // no event records inside the capture
+            if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+                c->profiling = prof;
+                return e;
+            }
+            hipError_t ie = hipSuccess;
+            for (int32_t k = 0; k < chunk && ie == hipSuccess; ++k) ie = iteration(c, W, implicit, lam, st);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(st, &g);
+            c->profiling = prof;
+            if (ie != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return ie;
+            }
+            if (e != hipSuccess) return e;
+            e = hipGraphInstantiate(&c->pcpg_graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return e;
+            c->pcpg_graph_key = key;
+            c->pcpg_graph_stream = st;
+            c->pcpg_lam = lam;
+        }
+        int32_t done = 0;
+        for (; done + chunk <= count; done += chunk)
+            if ((e = hipGraphLaunch(c->pcpg_graph, st)) != hipSuccess) return e;
+        for (; done < count; ++done)
+            if ((e = iteration(c, W, implicit, lam, st)) != hipSuccess) return e;
+        return hipSuccess;
+    }
+    for (int32_t k = 0; k < count; ++k)
+        if ((e = iteration(c, W, implicit, lam, st)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// PCPG on P F P lambda = P d from lambda_0 = G (G^T G)^{-1} e (e != NULL)
+// or lambda_0 = 0 (e == NULL).  Returns the iterations and ||w_k||/||w_0||.
+fetiF_status pcpg_core(fetiF_ctx c, const double* d, const double* e, double* lam, double tol, int32_t maxit,
+                       int32_t fixed, int implicit, int32_t check_every, bool graph, hipStream_t st,
+                       int32_t* iters_out, double* rel_out, double* w0_out)
+{
+    const int64_t n = c->n_lambda;
+    const Work W = work_of(c);
+    const int32_t cap = std::max(fixed, maxit) + 2;
+    HIPCHK(c, ensure_hist(c, cap));
+    if (e) {
+        HIPCHK(c, launch_gemv(c->ncoarse, c->dAinv, e, W.s, st));
+        HIPCHK(c, launch_gs(n, 0.0, 1.0, c->dGptr2, c->dGent2, c->dGv, W.s, nullptr, lam, st));
+    } else {
+        HIPCHK(c, launch_axpby(n, 0.0, d, 0.0, d, lam, st));
+    }
+    HIPCHK(c, apply_op(c, implicit, lam, W.q, st));
+    HIPCHK(c, launch_axpby(n, 1.0, d, -1.0, W.q, W.r, st));
+    HIPCHK(c, project(c, W, W.r, W.w, st));
+    HIPCHK(c, project(c, W, W.w, W.y, st));
+    HIPCHK(c, launch_update_p(n, 0, c->dSc, W.y, W.p, st));
+    HIPCHK(c, launch_dot(n, W.w, W.y, W.w, 0, c->dPart, c->dSc, c->dHist, c->hist_cap, st));
+    int32_t it = 0;
+    double h0 = 0.0, hk = 0.0;
+    if (fixed > 0) {
+        HIPCHK(c, run_iters(c, W, implicit, lam, fixed, std::max(1, check_every), graph, st));
+        it = fixed;
+        HIPCHK(c, hipMemcpyAsync(c->hHist, c->dHist, sizeof(double) * (size_t)(it + 1), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        h0 = c->hHist[0];
+        hk = c->hHist[it];
+    } else {
+        HIPCHK(c, hipMemcpyAsync(c->hHist, c->dHist, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        h0 = hk = c->hHist[0];
+        const double goal = tol * tol * h0;
+        bool done = !(h0 > 0.0) || hk <= goal;
+        while (!done && it < maxit) {
+            const int32_t chunk = std::min(std::max(1, check_every), maxit - it);
+            HIPCHK(c, run_iters(c, W, implicit, lam, chunk, std::max(1, check_every), graph, st));
+            HIPCHK(c, hipMemcpyAsync(c->hHist + it + 1, c->dHist + it + 1, sizeof(double) * (size_t)chunk,
+                                     hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            it += chunk;
+            hk = c->hHist[it];
+            for (int32_t k = it - chunk + 1; k <= it; ++k)
+                if (c->hHist[k] <= goal) done = true;
+        }
+    }
+    if (iters_out) *iters_out = it;
+    if (w0_out) *w0_out = std::sqrt(std::max(0.0, h0));
+    if (rel_out) *rel_out = h0 > 0.0 ? std::sqrt(std::max(0.0, hk) / h0) : 0.0;
+    return FETIF_OK;
+}
+
+fetiF_status need_coarse(fetiF_ctx c)
+{
+    if (!c->has_coarse) return fail(c, FETIF_ESTATE, "solver entry points need R_i for every subdomain at create");
+    return FETIF_OK;
+}
+
+}  // namespace
+
+extern "C" fetiF_status fetiF_coarse_rhs(fetiF_ctx c, const double* f_d, double* e_d, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (fetiF_status s0 = need_coarse(c)) return s0;
+    if (!f_d || !e_d) return fail(c, FETIF_EINVAL, "f or e is NULL");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    HIPCHK(c, launch_rtf(c->nsub, c->dCoarse, c->dR, f_d, e_d, (hipStream_t)stream));
+    return FETIF_OK;
+}
+
+extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double* e_d, double* lambda_d,
+                                   const fetiF_pcpg_options* opt_in, fetiF_pcpg_result* res, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (fetiF_status s0 = need_coarse(c)) return s0;
+    if (!d_d || !e_d || !lambda_d) return fail(c, FETIF_EINVAL, "d, e and lambda are required");
+    fetiF_pcpg_options o;
+    std::memset(&o, 0, sizeof(o));
+    if (opt_in) o = *opt_in;
+    if (!(o.tol > 0.0)) o.tol = 1e-9;
+    if (o.max_iters <= 0) o.max_iters = 1000;
+    if (o.check_every <= 0) o.check_every = 10;
+    if (!(o.inner_tol > 0.0)) o.inner_tol = 1e-4;
+    if (o.fixed_iters < 0) return fail(c, FETIF_EINVAL, "fixed_iters < 0");
+    if (o.implicit || o.refine) {
+        if (fetiF_status s1 = need_factors(c)) return s1;
+    }
+    if (!o.implicit && !c->assembled) return fail(c, FETIF_ESTATE, "explicit PCPG before assemble");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    fetiF_pcpg_result R;
+    std::memset(&R, 0, sizeof(R));
+    const bool graph = o.use_graph != 0;
+    if (!o.refine) {
+        fetiF_status s = pcpg_core(c, d_d, e_d, lambda_d, o.tol, o.max_iters, o.fixed_iters, o.implicit,
+                                   o.check_every, graph, st, &R.iters, &R.rel_residual, &R.w0);
+        if (s != FETIF_OK) return s;
+    } else {
+        // outer FP64 refinement: true projected residual with the implicit
+        // FP64 operator, inner PCPG on the correction with the stored F~
+        const int64_t n = c->n_lambda;
+        const Work W = work_of(c);
+        HIPCHK(c, launch_gemv(c->ncoarse, c->dAinv, e_d, W.s, st));
+        HIPCHK(c, launch_gs(n, 0.0, 1.0, c->dGptr2, c->dGent2, c->dGv, W.s, nullptr, lambda_d, st));
+        double w0 = 0.0, wk = 0.0;
+        int32_t total = 0;
+        for (int32_t outer = 0; outer < 50; ++outer) {
+            HIPCHK(c, apply_op(c, 1, lambda_d, W.q, st));
+            HIPCHK(c, launch_axpby(n, 1.0, d_d, -1.0, W.q, W.rt, st));
+            HIPCHK(c, project(c, W, W.rt, W.w, st));
+            HIPCHK(c, launch_dot(n, W.w, W.w, nullptr, 3, c->dPart, c->dSc, nullptr, 0, st));
+            double ww = 0.0;
+            HIPCHK(c, hipMemcpyAsync(&ww, c->dSc + SC_TMP, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            wk = std::sqrt(std::max(0.0, ww));
+            if (outer == 0) w0 = wk;
+            R.outer = outer;
+            if (!(w0 > 0.0) || wk <= o.tol * w0 || total >= o.max_iters) break;
+            int32_t it = 0;
+            fetiF_status s = pcpg_core(c, W.rt, nullptr, W.dl, o.inner_tol, o.max_iters - total, 0, 0, o.check_every,
+                                       graph, st, &it, nullptr, nullptr);
+            if (s != FETIF_OK) return s;
+            total += it;
+            HIPCHK(c, launch_axpby(n, 1.0, lambda_d, 1.0, W.dl, lambda_d, st));
+        }
+        R.iters = total;
+        R.w0 = w0;
+        R.rel_residual = w0 > 0.0 ? wk / w0 : 0.0;
+    }
+    if (res) *res = R;
+    return FETIF_OK;
+}
+
+extern "C" fetiF_status fetiF_primal(fetiF_ctx c, const double* f_d, const double* d_d, const double* lambda_d,
+                                     double* alpha_d, double* u_d, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (fetiF_status s0 = need_coarse(c)) return s0;
+    if (fetiF_status s1 = need_factors(c)) return s1;
+    if (!f_d || !d_d || !lambda_d || !alpha_d || !u_d) return fail(c, FETIF_EINVAL, "NULL argument");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = c->n_lambda;
+    const Work W = work_of(c);
+    // alpha = -(G^T G)^{-1} G^T (d - F lambda)
+    if (fetiF_apply_implicit(c, lambda_d, W.q, st) != FETIF_OK) return FETIF_EDEVICE;
+    HIPCHK(c, launch_axpby(n, 1.0, d_d, -1.0, W.q, W.rt, st));
+    HIPCHK(c, launch_gt(c->nsub, c->dCoarse, c->dGv, c->dDmap, W.rt, W.t, st));
+    HIPCHK(c, launch_gemv(c->ncoarse, c->dAinv, W.t, W.s, st));
+    HIPCHK(c, launch_axpby(c->ncoarse, -1.0, W.s, 0.0, W.s, alpha_d, st));
+    // u = K^+ (f - B~^T lambda) + R alpha
+    HIPCHK(c, launch_load_primal_rhs(c->nsub, c->dSubRow, c->dSubM, c->dXperm, c->dStartRows, c->dSignsSorted,
+                                     c->dDmap, f_d, lambda_d, c->dXv, st));
+    HIPCHK(c, solve_all(c, 1, st));
+    HIPCHK(c, launch_permute_out(c->total_rows, c->dXperm, c->dXv, u_d, st));
+    HIPCHK(c, launch_add_kernel_part(c->nsub, c->dCoarse, c->dR, alpha_d, u_d, st));
+    return FETIF_OK;
+}

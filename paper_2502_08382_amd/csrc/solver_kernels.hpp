@@ -1,0 +1,58 @@
+// Records and launchers of the solver kernels (solver.hip).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace fetif {
+
+constexpr int COARSE_MAXK = 6;  // kernel dimension per subdomain (3D elasticity: 6)
+constexpr int DOT_PARTS = 256;  // fixed partial count of the deterministic dot
+
+// solver scalars in device memory
+enum { SC_WY = 0, SC_PQ, SC_DELTA, SC_BETA, SC_WW, SC_TMP, SC_TMP2, SC_K, SC_COUNT };
+
+// coarse-space block of one subdomain: G_i = D_i^T B~_i R_i
+struct CoarseSub {
+    int64_t mbase;   // first sorted local multiplier (into the sorted dual map)
+    int64_t gvbase;  // first value of its G rows (m x nk, sorted multiplier order)
+    int64_t rbase;   // first row of R_i in the concatenated R (n rows of nk)
+    int32_t m;
+    int32_t nk;
+    int32_t koff;    // first coarse unknown (alpha index)
+    int32_t n;
+    int32_t rowbase; // first entry of the subdomain in the concatenated DOF vector
+    int32_t pad;
+};
+
+// one term of row g of G: Gv[gv .. gv+nk) against s[koff .. koff+nk)
+struct GEnt {
+    int64_t gv;
+    int32_t koff;
+    int32_t nk;
+};
+
+hipError_t launch_gt(int32_t nsub, const CoarseSub* cs, const double* gv, const int32_t* dmap, const double* w,
+                     double* t, hipStream_t st);
+hipError_t launch_rtf(int32_t nsub, const CoarseSub* cs, const double* R, const double* f, double* e, hipStream_t st);
+hipError_t launch_gemv(int32_t nc, const double* A, const double* x, double* y, hipStream_t st);
+hipError_t launch_gs(int64_t n, double alpha, double sgn, const int32_t* gptr, const GEnt* ents, const double* gv,
+                     const double* s, const double* w, double* out, hipStream_t st);
+// deterministic dot(s) x.y (and x.z if z) followed by the scalar update
+// `mode`; the history index is a device counter (graph-replay safe)
+hipError_t launch_dot(int64_t n, const double* x, const double* y, const double* z, int mode, double* part,
+                      double* sc, double* hist, int32_t hist_cap, hipStream_t st);
+hipError_t launch_update_lr(int64_t n, const double* sc, const double* p, const double* q, double* lam, double* r,
+                            hipStream_t st);
+hipError_t launch_update_p(int64_t n, int use_beta, const double* sc, const double* y, double* p, hipStream_t st);
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
+                        hipStream_t st);
+hipError_t launch_gauss_jordan_inverse(int32_t n, double* A, double* rowk, double* colk, hipStream_t st);
+hipError_t launch_permute_out(int64_t n, const int32_t* xperm, const double* x, double* u, hipStream_t st);
+hipError_t launch_add_kernel_part(int32_t nsub, const CoarseSub* cs, const double* R, const double* alpha, double* u,
+                                  hipStream_t st);
+hipError_t launch_load_primal_rhs(int32_t nsub, const int32_t* sub_rowbase, const int32_t* sub_mbase,
+                                  const int32_t* xperm, const int32_t* start_rows, const int8_t* signs,
+                                  const int32_t* dmap, const double* f, const double* lam, double* x, hipStream_t st);
+
+}  // namespace fetif

@@ -36,7 +36,8 @@ class _Sub(ctypes.Structure):
                 ("dim", ctypes.c_int32), ("coords", ctypes.c_void_p),
                 ("m", ctypes.c_int32), ("b_dof", ctypes.c_void_p), ("b_sign", ctypes.c_void_p),
                 ("dual_map", ctypes.c_void_p), ("nelem", ctypes.c_int32), ("edofs", ctypes.c_int32),
-                ("elem_dofs", ctypes.c_void_p), ("dK", ctypes.c_void_p)]
+                ("elem_dofs", ctypes.c_void_p), ("dK", ctypes.c_void_p),
+                ("nkernel", ctypes.c_int32), ("R", ctypes.c_void_p)]
 
 
 class _Opt(ctypes.Structure):
@@ -44,6 +45,17 @@ class _Opt(ctypes.Structure):
                 ("nthreads", ctypes.c_int32), ("apply_band", ctypes.c_int32),
                 ("trsm_chunk", ctypes.c_int32), ("apply_rows", ctypes.c_int32),
                 ("apply_nontemporal", ctypes.c_int32)]
+
+
+class _PcpgOpt(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
+                ("implicit", ctypes.c_int32), ("check_every", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("use_graph", ctypes.c_int32)]
+
+
+class _PcpgRes(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("w0", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -59,7 +71,8 @@ EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply
            "fetiF_apply_backward", "fetiF_download_F", "fetiF_query", "fetiF_destroy",
            "fetiF_last_error", "fetiF_host_factor", "fetiF_hfactor_info", "fetiF_hfactor_export",
            "fetiF_hfactor_supernodes", "fetiF_hfactor_free", "fetiF_profile_enable",
-           "fetiF_profile_read", "fetiF_set_apply", "fetiF_apply_implicit", "fetiF_dual_rhs"]
+           "fetiF_profile_read", "fetiF_set_apply", "fetiF_apply_implicit", "fetiF_dual_rhs",
+           "fetiF_coarse_rhs", "fetiF_pcpg", "fetiF_primal"]
 
 PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "backward"]
 
@@ -97,6 +110,9 @@ def load_library(path=None):
     L.fetiF_set_apply.argtypes = [vp, i32, i32, i32]
     L.fetiF_apply_implicit.argtypes = [vp, vp, vp, vp]
     L.fetiF_dual_rhs.argtypes = [vp, vp, vp, vp, vp]
+    L.fetiF_coarse_rhs.argtypes = [vp, vp, vp, vp]
+    L.fetiF_pcpg.argtypes = [vp, vp, vp, vp, ctypes.POINTER(_PcpgOpt), ctypes.POINTER(_PcpgRes), vp]
+    L.fetiF_primal.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype if name == "fetiF_last_error" else ctypes.c_int
     _lib = L
@@ -146,13 +162,16 @@ class _SubArrays:
         self.elem_dofs = None if ed is None else np.ascontiguousarray(ed, dtype=np.int32)
         dk = d.get("dK")
         self.dK = None if dk is None else np.ascontiguousarray(dk, dtype=np.float64)
+        R = d.get("R")
+        self.R = None if R is None else np.ascontiguousarray(R, dtype=np.float64)
 
     def record(self):
         ne = 0 if self.elem_dofs is None else self.elem_dofs.shape[0]
         ed = 0 if self.elem_dofs is None else self.elem_dofs.shape[1]
         return _Sub(self.n, self.dpn, _ptr(self.k_ptr), _ptr(self.k_idx), self.dim, _ptr(self.coords),
                     len(self.b_dof), _ptr(self.b_dof), _ptr(self.b_sign), _ptr(self.dual_map), ne, ed,
-                    _ptr(self.elem_dofs), _ptr(self.dK))
+                    _ptr(self.elem_dofs), _ptr(self.dK), 0 if self.R is None else self.R.shape[1],
+                    _ptr(self.R))
 
 
 def _options(f_storage="f64", leaf_nodes=0, nthreads=0, apply_band=0, trsm_chunk=0, apply_rows=0,
@@ -206,6 +225,23 @@ class FetiContext:
 
     def dual_rhs(self, f, d, c=None, stream=None):
         self._check(self.L.fetiF_dual_rhs(self.h, _dptr(f), _dptr(c), _dptr(d), _stream(stream)))
+
+    def coarse_rhs(self, f, e, stream=None):
+        self._check(self.L.fetiF_coarse_rhs(self.h, _dptr(f), _dptr(e), _stream(stream)))
+
+    def pcpg(self, d, e, lam, tol=1e-9, max_iters=1000, fixed_iters=0, implicit=False, check_every=10,
+             refine=False, inner_tol=1e-4, use_graph=True, stream=None):
+        """PCPG (Alg. 1) on the device; returns dict(iters, outer, rel_residual, w0)."""
+        o = _PcpgOpt(tol, max_iters, fixed_iters, int(implicit), check_every, int(refine), inner_tol,
+                     int(use_graph))
+        r = _PcpgRes()
+        self._check(self.L.fetiF_pcpg(self.h, _dptr(d), _dptr(e), _dptr(lam), ctypes.byref(o), ctypes.byref(r),
+                                      _stream(stream)))
+        return {k: getattr(r, k) for k, _ in _PcpgRes._fields_}
+
+    def primal(self, f, d, lam, alpha, u, stream=None):
+        self._check(self.L.fetiF_primal(self.h, _dptr(f), _dptr(d), _dptr(lam), _dptr(alpha), _dptr(u),
+                                        _stream(stream)))
 
     def download_F(self, i):
         out = np.empty((self.m[i], self.m[i]))

@@ -1,0 +1,150 @@
+"""GPU parity of the dual solver (Alg. 1) and the primal recovery.
+
+Pins: a fixed number of PCPG iterations reproduces the oracle's iterates of
+the same algorithm; the converged lambda equals the oracle's; u equals the
+global FEM direct solve (the torn system is equivalent to the FEM system);
+graph replay is bitwise identical to direct launches; FP32/BF16 operators
+with FP64 refinement reach the FP64 solution."""
+import numpy as np
+import pytest
+
+from synth import config_problem, make_problem
+from oracle import feti
+from tests.gpu_common import say, make_context
+from tests.test_oracle_pins import global_fem_solve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _dev(t, a):
+    return t.tensor(np.ascontiguousarray(a), dtype=t.float64, device="cuda")
+
+
+def _cases():
+    return {
+        "C1": lambda: config_problem(1),
+        "heat3d": lambda: make_problem(3, "heat", [[3, 4], [4, 3], [3, 3]], 0.5, dirichlet_axis=2, seed=4),
+        "elast3d": lambda: make_problem(3, "elasticity", [[3, 3], [3, 4], [4, 3]], 0.2, dirichlet_axis=2, seed=6),
+    }
+
+
+def _oracle(prob):
+    invs = [feti.RegInverse(s.Kreg) for s in prob.subs]
+    Fs = [feti.local_dual_operator(s.Kreg, s.b_dof, s.b_sign, i) for s, i in zip(prob.subs, invs)]
+    Ds = [s.dual_map for s in prob.subs]
+    applyF = lambda x: feti.apply_explicit(Fs, Ds, x, prob.n_lambda)
+    return invs, applyF, feti.G_matrix(prob), feti.e_vector(prob), feti.d_vector(prob, invs)
+
+
+@pytest.mark.parametrize("case", list(_cases().keys()))
+def test_pcpg_and_primal_match_oracle_and_fem(torch_cuda, case):
+    t = torch_cuda
+    prob = _cases()[case]()
+    say("pcpg", case, "n_lambda", prob.n_lambda)
+    invs, applyF, G, e_o, d_o = _oracle(prob)
+    ctx = make_context(prob)
+    ctx.factor_upload([s.Kreg.data for s in prob.subs])
+    ctx.assemble()
+    f = _dev(t, np.concatenate([s.f for s in prob.subs]))
+    nk = G.shape[1]
+    e = t.empty(nk, dtype=t.float64, device="cuda")
+    d = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+    ctx.coarse_rhs(f, e)
+    ctx.dual_rhs(f, d)
+    t.cuda.synchronize()
+    assert np.abs(e.cpu().numpy() - e_o).max() <= 1e-12 * max(1.0, np.abs(e_o).max())
+    assert np.linalg.norm(d.cpu().numpy() - d_o) <= 1e-12 * np.linalg.norm(d_o)
+    # a fixed number of iterations reproduces the oracle's iterates
+    lam = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+    stream = t.cuda.Stream()
+    with t.cuda.stream(stream):
+        r5 = ctx.pcpg(d, e, lam, fixed_iters=5, stream=stream)
+    stream.synchronize()
+    lam5_o, it5, _ = feti.pcpg(applyF, d_o, G, e_o, fixed_iters=5)
+    err5 = np.linalg.norm(lam.cpu().numpy() - lam5_o) / np.linalg.norm(lam5_o)
+    say("5 iterations: rel diff", err5, r5)
+    assert r5["iters"] == 5 and err5 <= 1e-10
+    # converged solution
+    with t.cuda.stream(stream):
+        r = ctx.pcpg(d, e, lam, tol=1e-12, max_iters=3000, stream=stream)
+    stream.synchronize()
+    lam_o, it_o, _ = feti.pcpg(applyF, d_o, G, e_o, tol=1e-12, maxit=3000)
+    err = np.linalg.norm(lam.cpu().numpy() - lam_o) / np.linalg.norm(lam_o)
+    say(f"converged: gpu iters {r['iters']} oracle iters {it_o} rel err {err:.2e} res {r['rel_residual']:.2e}")
+    assert r["rel_residual"] <= 1e-12 and err <= 1e-8
+    assert abs(r["iters"] - it_o) <= 10
+    # primal recovery against the global FEM solve
+    alpha = t.empty(nk, dtype=t.float64, device="cuda")
+    u = t.empty(sum(s.n for s in prob.subs), dtype=t.float64, device="cuda")
+    ctx.primal(f, d, lam, alpha, u)
+    t.cuda.synchronize()
+    ug = global_fem_solve(prob)
+    uu = u.cpu().numpy()
+    off, worst = 0, 0.0
+    for s in prob.subs:
+        gd = (s.gnode[:, None] * prob.dpn + np.arange(prob.dpn)[None, :]).ravel()
+        worst = max(worst, np.abs(uu[off:off + s.n] - ug[gd]).max())
+        off += s.n
+    say("u vs FEM max abs err", worst, "scale", np.abs(ug).max())
+    assert worst <= 1e-8 * np.abs(ug).max()
+    ctx.close()
+
+
+def test_pcpg_graph_replay_is_bitwise_identical(torch_cuda):
+    t = torch_cuda
+    prob = config_problem(5, scale=(2, 5))
+    ctx = make_context(prob)
+    ctx.factor_upload([s.Kreg.data for s in prob.subs])
+    ctx.assemble()
+    f = _dev(t, np.concatenate([s.f for s in prob.subs]))
+    e = t.empty(prob.nsub, dtype=t.float64, device="cuda")
+    d = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+    ctx.coarse_rhs(f, e)
+    ctx.dual_rhs(f, d)
+    stream = t.cuda.Stream()
+    outs = []
+    for graph in (False, True, True):
+        lam = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+        with t.cuda.stream(stream):
+            r = ctx.pcpg(d, e, lam, fixed_iters=40, check_every=10, use_graph=graph, stream=stream)
+        stream.synchronize()
+        # eager work between replays
+        _ = (lam * 2).sum().item()
+        outs.append(lam.cpu().numpy())
+        say("graph" if graph else "direct", r)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_pcpg_refinement_reaches_fp64_solution(torch_cuda, prec):
+    t = torch_cuda
+    prob = config_problem(4, scale=(2, 8))
+    invs, applyF, G, e_o, d_o = _oracle(prob)
+    lam_o, it_o, _ = feti.pcpg(applyF, d_o, G, e_o, tol=1e-12, maxit=3000)
+    ctx = make_context(prob, f_storage=prec)
+    ctx.factor_upload([s.Kreg.data for s in prob.subs])
+    ctx.assemble()
+    f = _dev(t, np.concatenate([s.f for s in prob.subs]))
+    e = t.empty(prob.nsub, dtype=t.float64, device="cuda")
+    d = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+    ctx.coarse_rhs(f, e)
+    ctx.dual_rhs(f, d)
+    lam = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+    stream = t.cuda.Stream()
+    with t.cuda.stream(stream):
+        r = ctx.pcpg(d, e, lam, tol=1e-9, refine=True, inner_tol=1e-4 if prec == "f32" else 1e-2,
+                     max_iters=5000, stream=stream)
+    stream.synchronize()
+    err = np.linalg.norm(lam.cpu().numpy() - lam_o) / np.linalg.norm(lam_o)
+    say(prec, "refined:", r, "lambda rel err", err, "fp64 oracle iters", it_o)
+    assert r["rel_residual"] <= 1e-9
+    assert err <= 1e-6
+    ctx.close()
