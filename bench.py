@@ -6,8 +6,11 @@ subdomains of 12^3 elements (2197 DOFs each), lognormal(0, 0.5)
 conductivity, Dirichlet on z=0; seeded synthetic data.  One step follows
 the paper's multi-step skeleton (Alg. 2): numeric factorisation of every
 K_reg,i on host threads + copy of the factor values, assembly of every F~_i
-on the GPU (RHS init, supernodal TRSM, SYRK), then 200 applications of
-F = sum_i D_i^T F~_i D_i (the operator products of 200 solver iterations).
+on the GPU (RHS init, supernodal TRSM, SYRK), the dual right-hand sides
+d = B K^+ f - c and e = R^T f, then 200 iterations of the projected
+conjugate gradient solver (Alg. 1), each applying F = sum_i D_i^T F~_i D_i.
+With --prec f32/bf16 the solver instead runs to tol 1e-9 with FP64
+iterative refinement (true residual through the factors).
 
 Printed: one JSON line with the apply bandwidth as `value`, the assembly
 time per 1000 subdomains, the break-even iteration count against the CPU
@@ -43,7 +46,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2, help="workload 1..5")
-    ap.add_argument("--iters", type=int, default=200, help="applies per step")
+    ap.add_argument("--iters", type=int, default=200, help="solver iterations per step (FP64)")
+    ap.add_argument("--tol", type=float, default=1e-9, help="solver tolerance with --prec f32/bf16")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--cpu-sample", type=int, default=128, help="subdomains timed by the CPU oracle")
     ap.add_argument("--no-cpu", action="store_true")
@@ -77,9 +81,15 @@ def main():
     kvals = [s.Kreg.data for s in prob.subs]
     lam = torch.tensor(prob.lam, dtype=torch.float64, device=dev)
     q = torch.empty_like(lam)
-    stream = torch.cuda.current_stream()
+    f = torch.tensor(np.concatenate([s.f for s in prob.subs]), dtype=torch.float64, device=dev)
+    e = torch.empty(sum(s.R.shape[1] for s in prob.subs), dtype=torch.float64, device=dev)
+    d = torch.empty_like(lam)
+    sol = torch.empty_like(lam)
+    stream = torch.cuda.Stream()
+    refine = args.prec != "f64"
 
     host_factor_s = []
+    solver = []
     tune = None
 
     def step():
@@ -87,32 +97,39 @@ def main():
         ctx.factor_upload(kvals, stream=stream)
         host_factor_s.append(time.time() - th)
         ctx.assemble(stream=stream)
-        x, y = lam, q
-        for _ in range(args.iters):
-            ctx.apply(x, y, stream=stream)
+        ctx.coarse_rhs(f, e, stream=stream)
+        ctx.dual_rhs(f, d, stream=stream)
+        if refine:
+            r = ctx.pcpg(d, e, sol, tol=args.tol, refine=True, inner_tol=1e-4 if args.prec == "f32" else 1e-2,
+                         max_iters=20000, use_graph=False, stream=stream)
+        else:
+            r = ctx.pcpg(d, e, sol, fixed_iters=args.iters, use_graph=False, stream=stream)
+        solver.append(r)
 
-    for w in range(args.warmup):
-        step()
+    with torch.cuda.stream(stream):
+        for w in range(args.warmup):
+            step()
+            torch.cuda.synchronize()
+            log(f"warmup step {w} done: solver {solver[-1]}")
+            if w == 0 and not args.no_tune:
+                from paper_2502_08382_amd.autotune import tune_apply
+                tt = time.time()
+                tune = tune_apply(ctx, lam, q, stream=stream)
+                log(f"apply autotune {time.time() - tt:.1f}s: band={tune['band']} rows={tune['rows']} "
+                    f"nontemporal={tune['nontemporal']} ({tune['ms'] * 1e3:.1f} us)")
+        host_factor_s.clear()
+        solver.clear()
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
         torch.cuda.synchronize()
-        log(f"warmup step {w} done")
-        if w == 0 and not args.no_tune:
-            from paper_2502_08382_amd.autotune import tune_apply
-            tt = time.time()
-            tune = tune_apply(ctx, lam, q, stream=stream)
-            log(f"apply autotune {time.time() - tt:.1f}s: band={tune['band']} rows={tune['rows']} "
-                f"nontemporal={tune['nontemporal']} ({tune['ms'] * 1e3:.1f} us)")
-    host_factor_s.clear()
-    ctx.profile(True)
-    ctx.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    ctx.profile(False)
-    prof = ctx.profile_read(reset=True)
-    log(f"timed {args.steps} steps in {elapsed:.3f}s; phases {prof}")
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        ctx.profile(False)
+        prof = ctx.profile_read(reset=True)
+    log(f"timed {args.steps} steps in {elapsed:.3f}s; phases {prof}; solver {solver[-1]}")
 
     K = args.steps
     ms = {p: v[0] for p, v in prof.items()}
@@ -153,6 +170,10 @@ def main():
                               "syrk": round(ms["syrk"] / K, 4)},
         "assembly_tflops": round(asm_flops / (t_asm * 1e-3) / 1e12, 3),
         "assembly_mfma_frac": round(asm_flops / (t_asm * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
+        "solver": {"kind": "PCPG (Alg. 1), M = I" + (", FP64 refinement" if refine else ""),
+                   "iters": solver[-1]["iters"], "outer": solver[-1]["outer"],
+                   "rel_residual": solver[-1]["rel_residual"],
+                   "ms_per_iter": None},
         "apply_ms": round(t_apply, 4),
         "apply_band_ms": round(t_band, 4),
         "apply_gather_ms": round(t_gather, 4),
@@ -163,6 +184,12 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(band_gbs / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_launch": int(band_bytes)},
     }
+
+    # solver time per iteration: the step minus factor copy, assembly, solves with
+    # the factors and the host factorisation (the PCPG dominates what remains)
+    t_solve_ms = elapsed / K * 1e3 - t_upload - t_asm - ms["solves"] / K - float(np.mean(host_factor_s)) * 1e3
+    result["solver"]["ms_per_iter"] = round(t_solve_ms / max(1, solver[-1]["iters"]), 4)
+    result["solves_with_factors_ms"] = round(ms["solves"] / K, 3)
 
     # ---- CPU oracle: implicit apply on host threads, bounded sample
     if not args.no_cpu:

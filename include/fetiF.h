@@ -246,7 +246,7 @@ fetiF_status fetiF_query(fetiF_ctx ctx, fetiF_info* info);
 /* Phase timing with HIP events recorded on the caller's stream around each
  * device phase: 0 factor copy (H2D), 1 RHS initialisation, 2 forward TRSM
  * (all levels), 3 SYRK, 4 apply band kernel, 5 apply gather kernel,
- * 6 backward solves and adjoint.  fetiF_profile_enable(ctx, 1) starts
+ * 6 solves with the factors (implicit apply, dual RHS, adjoint).  fetiF_profile_enable(ctx, 1) starts
  * recording (it inserts event records, so keep it off inside captured
  * graphs); fetiF_profile_read waits for the recorded events and adds their
  * elapsed times into ms[phase] / counts[phase] for phase < nphases, then

@@ -74,7 +74,7 @@ EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply
            "fetiF_profile_read", "fetiF_set_apply", "fetiF_apply_implicit", "fetiF_dual_rhs",
            "fetiF_coarse_rhs", "fetiF_pcpg", "fetiF_primal"]
 
-PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "backward"]
+PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "solves"]
 
 _lib = None
 
