@@ -106,8 +106,10 @@ typedef struct {
     int32_t nthreads;     /* host threads for analysis/factorisation (default: all) */
     int32_t apply_band;   /* stored elements of F~ per apply work-group (default 131072) */
     int32_t trsm_chunk;   /* most RHS columns per TRSM work-group: 16, 32 or 64 (default 64) */
-    int32_t apply_rows;   /* rows of F~ per wavefront pass in apply, 1 or 2 (default 2) */
+    int32_t apply_rows;   /* rows of F~ per pass of a wavefront pair in apply, 2 or 4 (default 4) */
     int32_t apply_nontemporal; /* 1: stream F~ with non-temporal loads (default), 0: cached */
+    int32_t apply_split;  /* apply work split: 0 bands per triangle, largest first (default);
+                             1 equal shares of all stored elements, one per work-group */
 } fetiF_options;
 
 /* Preparation (Alg. 2, "preparation"; Sec. IV-B "Preparation"): nested
@@ -145,10 +147,12 @@ fetiF_status fetiF_apply(fetiF_ctx ctx, const double* lambda_d, double* q_d, voi
 
 /* Re-plan the application (tuning hook): band_elems > 0 sets the stored
  * elements of F~ per work-group (the band/gather tables are rebuilt, which
- * synchronises the device), rows (1 or 2; 0 keeps) the rows per wavefront
- * pass, nontemporal (0/1; -1 keeps) the load policy for F~.  The result of
+ * synchronises the device), rows (2 or 4; 0 keeps) the rows per pass of a
+ * wavefront pair, nontemporal (0/1; -1 keeps) the load policy for F~, split
+ * (0/1; -1 keeps) the work split of fetiF_options.apply_split.  The result of
  * fetiF_apply does not depend on these up to summation order. */
-fetiF_status fetiF_set_apply(fetiF_ctx ctx, int32_t band_elems, int32_t rows, int32_t nontemporal);
+fetiF_status fetiF_set_apply(fetiF_ctx ctx, int32_t band_elems, int32_t rows, int32_t nontemporal,
+                             int32_t split);
 
 /* Reverse mode of J = g^T F(theta) lambda for the applied operator:
  *   dlambda_d = F g_d   (F is symmetric),
@@ -239,6 +243,7 @@ typedef struct {
     double factor_flops;    /* host numeric factorisation flops */
     int32_t trsm_levels;    /* launches of the level-scheduled TRSM */
     int32_t apply_groups;   /* work-groups of one apply */
+    int64_t apply_elements; /* stored elements the apply streams (sum of packed triangles) */
 } fetiF_info;
 
 fetiF_status fetiF_query(fetiF_ctx ctx, fetiF_info* info);

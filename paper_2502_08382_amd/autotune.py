@@ -12,8 +12,6 @@ import itertools
 import json
 import os
 
-DEFAULT_BANDS = (8192, 16384, 32768, 65536, 131072)
-
 
 def signature(ctx):
     ms = sorted(ctx.m)
@@ -35,33 +33,46 @@ def _time_apply(ctx, lam, q, reps, stream):
     return band + gath, band
 
 
-def tune_apply(ctx, lam, q, bands=DEFAULT_BANDS, rows=(1, 2), nontemporal=(0, 1), reps=20,
-               stream=None, cache=None, verbose=False):
-    """Try every (band, rows, nontemporal) shape; install and return the best.
+def group_candidates(ctx, per_cu=(2, 3, 4, 6, 8, 12)):
+    """Elements per work-group that give about k work-groups per compute
+    unit for the whole apply (exactly k with the equal-share split)."""
+    import torch
+    ncu = torch.cuda.get_device_properties(ctx.device).multi_processor_count
+    total = ctx.info()["apply_elements"]
+    return tuple(max(1, -(-total // (ncu * k))) for k in per_cu)
 
-    Returns dict(band=..., rows=..., nontemporal=..., ms=..., trials=[...])."""
+
+def tune_apply(ctx, lam, q, bands=None, rows=(2, 4), nontemporal=(1,), splits=(0, 1), reps=20,
+               stream=None, cache=None, verbose=False):
+    """Try every (split, band, rows, nontemporal) shape; install and return
+    the best.  bands: candidate elements per work-group (default:
+    group_candidates).
+
+    Returns dict(band=..., rows=..., nontemporal=..., split=..., ms=..., trials=[...])."""
+    if bands is None:
+        bands = group_candidates(ctx)
     sig = signature(ctx)
     if cache and os.path.exists(cache):
         try:
             with open(cache) as f:
                 hit = json.load(f).get(sig)
             if hit:
-                ctx.set_apply(hit["band"], hit["rows"], hit["nontemporal"])
+                ctx.set_apply(hit["band"], hit["rows"], hit["nontemporal"], hit.get("split", 0))
                 return dict(hit, cached=True)
         except (OSError, ValueError):
             pass
     trials = []
-    for b, r, n in itertools.product(bands, rows, nontemporal):
-        ctx.set_apply(b, r, n)
+    for sp, b, r, n in itertools.product(splits, bands, rows, nontemporal):
+        ctx.set_apply(b, r, n, sp)
         t, tb = _time_apply(ctx, lam, q, reps, stream)
-        trials.append(dict(band=b, rows=r, nontemporal=n, ms=t, band_ms=tb))
+        trials.append(dict(band=b, rows=r, nontemporal=n, split=sp, ms=t, band_ms=tb))
         if verbose:
-            print(f"[autotune] band={b} rows={r} nt={n}: apply {t * 1e3:.1f} us (band kernel {tb * 1e3:.1f} us)",
-                  flush=True)
+            print(f"[autotune] split={sp} band={b} rows={r} nt={n}: apply {t * 1e3:.1f} us "
+                  f"(band kernel {tb * 1e3:.1f} us)", flush=True)
     best = min(trials, key=lambda d: d["ms"])
-    ctx.set_apply(best["band"], best["rows"], best["nontemporal"])
-    out = dict(band=best["band"], rows=best["rows"], nontemporal=best["nontemporal"], ms=best["ms"],
-               trials=trials, cached=False)
+    ctx.set_apply(best["band"], best["rows"], best["nontemporal"], best["split"])
+    out = dict(band=best["band"], rows=best["rows"], nontemporal=best["nontemporal"], split=best["split"],
+               ms=best["ms"], trials=trials, cached=False)
     if cache:
         data = {}
         if os.path.exists(cache):
@@ -70,7 +81,7 @@ def tune_apply(ctx, lam, q, bands=DEFAULT_BANDS, rows=(1, 2), nontemporal=(0, 1)
                     data = json.load(f)
             except (OSError, ValueError):
                 data = {}
-        data[sig] = {k: out[k] for k in ("band", "rows", "nontemporal", "ms")}
+        data[sig] = {k: out[k] for k in ("band", "rows", "nontemporal", "split", "ms")}
         with open(cache, "w") as f:
             json.dump(data, f, indent=1)
     return out

@@ -86,41 +86,71 @@ bool plan_subdomain(const fetiF_subdomain& in, const fetiF_options& opt, int64_t
 namespace {
 
 struct ApplyPlan {
-    std::vector<Band> bands;
+    std::vector<Band> bands;      // bands of rows, in subdomain order (indexed by the gather map)
+    std::vector<Band> launch;     // the same bands in launch order
+    std::vector<int32_t> seg_ptr; // work-group g handles launch[seg_ptr[g] .. seg_ptr[g+1])
     std::vector<int64_t> band_z;
     std::vector<int32_t> gptr;
     std::vector<GatherEnt> gent;
     int64_t total_z = 0;
 };
 
-// Bands of about band_elems stored elements per subdomain triangle (whole
-// rows, boundaries at equal shares of the packed storage) and the gather map:
-// for every global multiplier, the (subdomain, row) entries in ascending
-// subdomain order with the bands whose partials hold that row.
-void plan_apply(fetiF_ctx c, int32_t band_elems, ApplyPlan& A)
+// Work decomposition of the apply.  split 0: every triangle is cut into
+// ceil(E_i / band_elems) bands of whole rows with about equal stored
+// elements, one band per work-group, launched largest first so the short
+// bands fill the tail.  split 1: the stored elements of all triangles,
+// concatenated in subdomain order, are cut into G = total / band_elems equal
+// shares (rows kept whole), one per work-group; a share is cut at subdomain
+// boundaries into bands that its work-group handles in turn.  The gather map
+// lists, for every global multiplier, its (subdomain, row) entries in
+// ascending subdomain order with the bands whose partials hold that row.
+void plan_apply(fetiF_ctx c, int32_t band_elems, int32_t split, ApplyPlan& A)
 {
     const int V = prec_vec(c->prec);
-    int64_t zb = 0;
+    band_elems = std::max(1, band_elems);
+    int64_t total = 0;
+    for (int32_t i = 0; i < c->nsub; ++i) total += packed_row_offset(c->subs[i].m, V);
+    // first row of subdomain plan P starting at or after local element offset t
+    auto cut_row = [&](const SubPlan& P, int64_t t) {
+        int32_t lo = 0, hi = P.m;
+        while (lo < hi) {
+            int32_t mid = (lo + hi) / 2;
+            if (packed_row_offset(mid, V) >= t) hi = mid;
+            else lo = mid + 1;
+        }
+        return lo;
+    };
+    const int64_t G = split ? std::max<int64_t>(1, (total + band_elems / 2) / band_elems) : 0;
+    // share g covers global element offsets [S(g), S(g+1))
+    auto S = [&](int64_t g) { return (int64_t)((__int128)total * g / G); };
+    auto share_of = [&](int64_t x) {
+        int64_t g = std::min<int64_t>(G - 1, (int64_t)((__int128)x * G / std::max<int64_t>(1, total)));
+        while (g + 1 < G && S(g + 1) <= x) ++g;
+        while (g > 0 && S(g) > x) --g;
+        return g;
+    };
+    int64_t zb = 0, off = 0;
+    std::vector<int64_t> band_group;
     for (int32_t i = 0; i < c->nsub; ++i) {
         SubPlan& P = c->subs[i];
-        const int64_t fel = packed_row_offset(P.m, V);
+        const int64_t E = packed_row_offset(P.m, V);
         P.band0 = (int32_t)A.bands.size();
-        int64_t nb = std::max<int64_t>(1, (fel + band_elems - 1) / band_elems);
-        int32_t r0 = 0;
-        for (int64_t k = 1; k <= nb && r0 < P.m; ++k) {
-            int32_t r1;
-            if (k == nb) {
-                r1 = P.m;
-            } else {
-                int64_t target = fel * k / nb;
-                int32_t lo = r0 + 1, hi = P.m;
-                while (lo < hi) {
-                    int32_t mid = (lo + hi) / 2;
-                    if (packed_row_offset(mid, V) >= target) hi = mid;
-                    else lo = mid + 1;
-                }
-                r1 = lo;
+        std::vector<int32_t> cuts{0};
+        if (split) {
+            for (int64_t g = share_of(off) + 1; g < G && S(g) < off + E; ++g) {
+                const int32_t r = cut_row(P, S(g) - off);
+                if (r > cuts.back() && r < P.m) cuts.push_back(r);
             }
+        } else {
+            const int64_t nb = std::max<int64_t>(1, (E + band_elems - 1) / band_elems);
+            for (int64_t k = 1; k < nb; ++k) {
+                const int32_t r = cut_row(P, E * k / nb);
+                if (r > cuts.back() && r < P.m) cuts.push_back(r);
+            }
+        }
+        cuts.push_back(P.m);
+        for (size_t k = 0; k + 1 < cuts.size(); ++k) {
+            const int32_t r0 = cuts[k], r1 = cuts[k + 1];
             if (r1 <= r0) continue;
             Band bd;
             bd.fbase = P.fbase;
@@ -131,12 +161,30 @@ void plan_apply(fetiF_ctx c, int32_t band_elems, ApplyPlan& A)
             bd.pad = 0;
             A.bands.push_back(bd);
             A.band_z.push_back(zb);
+            if (split) band_group.push_back(share_of(off + packed_row_offset(r0, V)));
             zb += r1;
-            r0 = r1;
         }
         P.nband = (int32_t)A.bands.size() - P.band0;
+        off += E;
     }
     A.total_z = zb;
+    const int64_t nb = (int64_t)A.bands.size();
+    if (split) {
+        A.launch = A.bands;
+        A.seg_ptr.assign(G + 1, 0);
+        for (int64_t grp : band_group) A.seg_ptr[grp + 1]++;
+        for (int64_t g = 0; g < G; ++g) A.seg_ptr[g + 1] += A.seg_ptr[g];
+    } else {
+        auto elems = [&](const Band& bd) { return packed_row_offset(bd.r1, V) - packed_row_offset(bd.r0, V); };
+        std::vector<int64_t> order(nb);
+        for (int64_t k = 0; k < nb; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t x, int64_t y) { return elems(A.bands[x]) > elems(A.bands[y]); });
+        A.launch.resize(nb);
+        for (int64_t k = 0; k < nb; ++k) A.launch[k] = A.bands[order[k]];
+        A.seg_ptr.resize(nb + 1);
+        for (int64_t k = 0; k <= nb; ++k) A.seg_ptr[k] = (int32_t)k;
+    }
     const int64_t nl = c->n_lambda;
     A.gptr.assign(nl + 1, 0);
     for (int32_t i = 0; i < c->nsub; ++i)
@@ -165,6 +213,8 @@ void free_apply(fetiF_ctx c)
     c->apply_allocs.clear();
     c->dZ = nullptr;
     c->dBands = nullptr;
+    c->dSegPtr = nullptr;
+    c->ngroups = 0;
     c->dBandZ = nullptr;
     c->dGptr = nullptr;
     c->dGent = nullptr;
@@ -191,11 +241,14 @@ hipError_t install_apply(fetiF_ctx c, const ApplyPlan& A)
     char* z = nullptr;
     if ((e = aalloc(c, &z, (size_t)A.total_z * (c->prec == 0 ? 8 : 4) + 64)) != hipSuccess) return e;
     c->dZ = z;
-    if ((e = aalloc(c, &c->dBands, A.bands.size())) != hipSuccess) return e;
+    if ((e = aalloc(c, &c->dBands, A.launch.size())) != hipSuccess) return e;
+    if ((e = aalloc(c, &c->dSegPtr, A.seg_ptr.size())) != hipSuccess) return e;
+    if ((e = upload(c->dSegPtr, A.seg_ptr)) != hipSuccess) return e;
+    c->ngroups = (int32_t)A.seg_ptr.size() - 1;
     if ((e = aalloc(c, &c->dBandZ, A.band_z.size())) != hipSuccess) return e;
     if ((e = aalloc(c, &c->dGptr, A.gptr.size())) != hipSuccess) return e;
     if ((e = aalloc(c, &c->dGent, A.gent.size())) != hipSuccess) return e;
-    if ((e = upload(c->dBands, A.bands)) != hipSuccess) return e;
+    if ((e = upload(c->dBands, A.launch)) != hipSuccess) return e;
     if ((e = upload(c->dBandZ, A.band_z)) != hipSuccess) return e;
     if ((e = upload(c->dGptr, A.gptr)) != hipSuccess) return e;
     if ((e = upload(c->dGent, A.gent)) != hipSuccess) return e;
@@ -427,7 +480,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         tiles.swap(t2);
     }
     ApplyPlan aplan;
-    plan_apply(c, opt.apply_band, aplan);
+    plan_apply(c, opt.apply_band, opt.apply_split, aplan);
 
     // ---- tables of the batched solves with L
     std::vector<int32_t> relpos(rows.size(), -1), child_ptr(sns.size() + 1, 0), child_idx;
@@ -817,7 +870,7 @@ extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double*
     hipStream_t st = (hipStream_t)stream;
     PhaseTimer t4(c, st, 4);
     HIPCHK(c, launch_apply_band(c->prec, c->apply_nch, c->opt.apply_rows, c->opt.apply_nontemporal != 0, c->dBands,
-                                c->nbands, c->dF, lambda_d, c->dDmap, c->dZ, st));
+                                c->dSegPtr, c->ngroups, c->dF, lambda_d, c->dDmap, c->dZ, st));
     HIPCHK(c, t4.stop());
     PhaseTimer t5(c, st, 5);
     HIPCHK(c, launch_gather(c->prec, c->n_lambda, c->dGptr, c->dGent, c->dBandZ, c->dZ, q_d, st));
@@ -825,12 +878,15 @@ extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double*
     return FETIF_OK;
 }
 
-extern "C" fetiF_status fetiF_set_apply(fetiF_ctx c, int32_t band_elems, int32_t rows, int32_t nontemporal)
+extern "C" fetiF_status fetiF_set_apply(fetiF_ctx c, int32_t band_elems, int32_t rows, int32_t nontemporal,
+                                        int32_t split)
 {
     if (!c) return FETIF_EINVAL;
     if (c->sticky) return FETIF_EDEVICE;
-    if (band_elems < 0 || (rows != 0 && rows != 1 && rows != 2) || nontemporal < -1 || nontemporal > 1)
-        return fail(c, FETIF_EINVAL, "band_elems >= 0, rows in {0,1,2}, nontemporal in {-1,0,1}");
+    if (band_elems < 0 || (rows != 0 && rows != 2 && rows != 4) || nontemporal < -1 || nontemporal > 1 ||
+        split < -1 || split > 1)
+        return fail(c, FETIF_EINVAL,
+                    "band_elems >= 0, rows in {0,2,4}, nontemporal in {-1,0,1}, split in {-1,0,1}");
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     if (c->pcpg_graph) {
@@ -841,12 +897,15 @@ extern "C" fetiF_status fetiF_set_apply(fetiF_ctx c, int32_t band_elems, int32_t
     }
     if (rows) c->opt.apply_rows = rows;
     if (nontemporal >= 0) c->opt.apply_nontemporal = nontemporal;
-    if (band_elems > 0 && band_elems != c->opt.apply_band) {
+    const int32_t nb = band_elems > 0 ? band_elems : c->opt.apply_band;
+    const int32_t ns = split >= 0 ? split : c->opt.apply_split;
+    if (nb != c->opt.apply_band || ns != c->opt.apply_split) {
         HIPCHK(c, hipDeviceSynchronize());
         ApplyPlan A;
-        plan_apply(c, band_elems, A);
+        plan_apply(c, nb, ns, A);
         HIPCHK(c, install_apply(c, A));
-        c->opt.apply_band = band_elems;
+        c->opt.apply_band = nb;
+        c->opt.apply_split = ns;
     }
     return FETIF_OK;
 }
@@ -1000,7 +1059,13 @@ extern "C" fetiF_status fetiF_query(fetiF_ctx c, fetiF_info* info)
     info->syrk_flops = c->syrk_flops;
     info->factor_flops = c->factor_flops;
     info->trsm_levels = (int32_t)c->level_items.size();
-    info->apply_groups = c->nbands;
+    info->apply_groups = c->ngroups;
+    {
+        const int V = prec_vec(c->prec);
+        int64_t tot = 0;
+        for (const auto& P : c->subs) tot += packed_row_offset(P.m, V);
+        info->apply_elements = tot;
+    }
     return FETIF_OK;
 }
 

@@ -133,6 +133,8 @@ struct fetiF_ctx_s {
     SyrkTile* dTiles = nullptr;
     int32_t* dLists = nullptr;
     Band* dBands = nullptr;
+    int32_t* dSegPtr = nullptr;
+    int32_t ngroups = 0;
     int64_t* dBandZ = nullptr;
     int32_t* dGptr = nullptr;
     GatherEnt* dGent = nullptr;

@@ -46,8 +46,9 @@ void options_defaults(const fetiF_options* in, fetiF_options& o)
     if (o.leaf_nodes <= 0) o.leaf_nodes = 24;
     if (o.apply_band <= 0) o.apply_band = 131072;
     if (o.trsm_chunk <= 0) o.trsm_chunk = 64;
-    if (o.apply_rows != 1 && o.apply_rows != 2) o.apply_rows = 2;
+    if (o.apply_rows != 2 && o.apply_rows != 4) o.apply_rows = 4;
     if (o.apply_nontemporal < 0 || o.apply_nontemporal > 1) o.apply_nontemporal = 1;
+    if (o.apply_split < 0 || o.apply_split > 1) o.apply_split = 0;
 }
 
 }  // namespace fetif

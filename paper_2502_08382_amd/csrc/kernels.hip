@@ -536,6 +536,20 @@ __device__ __forceinline__ void unpack<bf16_t, 8>(const uint4& raw, float (&v)[8
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// 16 bytes per lane from a buffer descriptor covering [base, base + nbytes):
+// lanes whose 16 bytes fall outside read zero (hardware range check), so the
+// base and range can be wavefront-uniform (scalar registers) and one lane
+// offset register serves every load.  Descriptor word 3 is the gfx9-family
+// raw-buffer format.
+template <bool NTL>
+__device__ __forceinline__ uint4 load16_range(const void* base, uint32_t nbytes, int lane_off)
+{
+    __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nbytes, 0x00020000);
+    u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, 0, NTL ? 2 : 0);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 template <bool NTL>
 __device__ __forceinline__ uint4 load16(const void* p)
 {
@@ -547,15 +561,23 @@ __device__ __forceinline__ uint4 load16(const void* p)
     }
 }
 
-// One work-group handles one band of rows [r0, r1) of a packed lower
-// triangle: every stored element F[r][c] (c <= r) contributes F[r][c] p[c] to
-// row r (a dot product, reduced across the wavefront) and, for c < r,
-// F[r][c] p[r] to row c (kept in per-lane registers).  The band writes its
-// partial vector z[0..r1).  Lanes read 16-byte vectors of consecutive
-// columns, so a wavefront streams 1 KiB of a row per load; a wavefront
-// takes ROWS consecutive rows per pass (their loads are in flight together).
+// One work-group handles an equal share of all stored elements: a short list
+// of segments, each a band of rows [r0, r1) of one packed lower triangle.
+// Every stored element F[r][c] (c <= r) contributes F[r][c] p[c] to row r (a
+// dot product) and, for c < r, F[r][c] p[r] to row c (kept in per-lane
+// registers).  A segment writes its partial vector z[0..r1).
+// The four wavefronts form two pairs; a pair takes ROWS consecutive rows per
+// pass and its two wavefronts split every row's 16-byte column chunks
+// round-robin (chunk ch belongs to wavefront ch % 2 of the pair), so each
+// lane keeps the column partials of only half the chunks and more rows'
+// loads are in flight at once.  Row dots are the sum of the two wavefronts'
+// partials, added in a fixed order at the end.  Row padding is zero (F is
+// cleared at creation and only c <= r is ever stored) and so is p beyond r1,
+// so the inner loop needs no per-element test except keeping the diagonal
+// out of the column partials.
 template <typename T, int NCH, int ROWS, bool NTL>
 __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__ bands,
+                                                        const int32_t* __restrict__ seg_ptr,
                                                         const T* __restrict__ F,
                                                         const double* __restrict__ lam,
                                                         const int32_t* __restrict__ dmap,
@@ -563,36 +585,51 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
 {
     using A = typename Acc<T>::type;
     constexpr int VEC = 16 / sizeof(T);
-    constexpr int CH = 64 * VEC;  // columns per chunk
+    constexpr int CH = 64 * VEC;          // columns per chunk
     constexpr int CAP = NCH * CH;
-    __shared__ A sp[CAP];   // p = lambda[D_i] (sorted order); later the partial sums
-    __shared__ A srow[CAP]; // row dot products of the band
-    const Band b = bands[blockIdx.x];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int cidx = tid; cidx < b.r1; cidx += NT) sp[cidx] = (A)lam[dmap[b.dbase + cidx]];
+    constexpr int NH = (NCH + 1) / 2;     // chunks per wavefront of a pair
+    __shared__ A sp[CAP];                 // p = lambda[D_i] (sorted order), zero beyond r1; later partial sums
+    __shared__ A srow[2][CAP];            // row-dot partials of the two wavefronts of a pair
+    const int tid = threadIdx.x, lane = tid & 63;
+    // wavefront-uniform values in scalar registers: row indices, row
+    // addresses and loop control then stay out of the vector registers
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int pair = wv >> 1, half = wv & 1;
+    for (int seg = seg_ptr[blockIdx.x]; seg < seg_ptr[blockIdx.x + 1]; ++seg) {
+    const Band b = bands[seg];
+    for (int cidx = tid; cidx < CAP; cidx += NT) sp[cidx] = cidx < b.r1 ? (A)lam[dmap[b.dbase + cidx]] : (A)0;
     __syncthreads();
-    A y[NCH][VEC];
+    A y[NH][VEC];
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
+    for (int c2 = 0; c2 < NH; ++c2)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) y[ch][e] = (A)0;
-    for (int r = b.r0 + ROWS * wv; r < b.r1; r += 4 * ROWS) {
-        const T* __restrict__ rowp = F + b.fbase + packed_row_offset(r, VEC);
-        uint4 raw[ROWS][NCH];
+        for (int e = 0; e < VEC; ++e) y[c2][e] = (A)0;
+    const char* __restrict__ tri = reinterpret_cast<const char*>(F + b.fbase);
+    for (int r = b.r0 + ROWS * pair; r < b.r1; r += 2 * ROWS) {
+        uint4 raw[ROWS][NH];
         int rr[ROWS];
-        const T* rp[ROWS];
+        int rmax = r;
 #pragma unroll
         for (int k = 0; k < ROWS; ++k) {
-            rr[k] = (r + k < b.r1) ? r + k : -1;   // -1: no such row, loads masked off
-            rp[k] = k == 0 ? rowp : rp[k - 1] + VEC * ((r + k - 1) / VEC + 1);
+            rr[k] = (r + k < b.r1) ? r + k : -1;   // -1: no such row, its loads read zero
+            rmax = rr[k] > rmax ? rr[k] : rmax;
         }
+        const int nchunk = rmax / CH + 1;   // chunks holding a column of the pass's longest row
 #pragma unroll
-        for (int k = 0; k < ROWS; ++k)
+        for (int k = 0; k < ROWS; ++k) {
+            // padded row r + k: bytes [row_start, row_start + row_bytes)
+            const int64_t row_start = packed_row_offset(r + k, VEC) * (int64_t)sizeof(T);
+            const int row_bytes = rr[k] >= 0 ? (int)(VEC * (rr[k] / VEC + 1) * sizeof(T)) : 0;
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-                const int col = ch * CH + lane * VEC;
-                raw[k][ch] = col <= rr[k] ? load16<NTL>(rp[k] + col) : make_uint4(0, 0, 0, 0);
+            for (int c2 = 0; c2 < NH; ++c2) {
+                const int ch = 2 * c2 + half;
+                const int cbyte = ch * CH * (int)sizeof(T);
+                const int nbytes = (ch < NCH && row_bytes > cbyte) ? row_bytes - cbyte : 0;
+                // wavefront-uniform: chunks past the longest row are not issued
+                raw[k][c2] = ch < nchunk ? load16_range<NTL>(tri + row_start + cbyte, (uint32_t)nbytes, lane * 16)
+                                         : make_uint4(0, 0, 0, 0);
             }
+        }
         A pr[ROWS], dot[ROWS];
 #pragma unroll
         for (int k = 0; k < ROWS; ++k) {
@@ -600,26 +637,21 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
             dot[k] = (A)0;
         }
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
+        for (int c2 = 0; c2 < NH; ++c2) {
+            const int ch = 2 * c2 + half;
+            if (ch >= NCH || ch * CH > rmax) break;  // wavefront-uniform
             const int col = ch * CH + lane * VEC;
-            if (col <= rr[ROWS - 1] || col <= rr[0]) {
-                A pc[VEC];
+            A pc[VEC];
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) pc[e] = sp[col + e];
+            for (int e = 0; e < VEC; ++e) pc[e] = sp[col + e];
 #pragma unroll
-                for (int k = 0; k < ROWS; ++k) {
-                    if (col <= rr[k]) {
-                        A v[VEC];
-                        unpack<T, VEC>(raw[k][ch], v);
+            for (int k = 0; k < ROWS; ++k) {
+                A v[VEC];
+                unpack<T, VEC>(raw[k][c2], v);
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) {
-                            const int cc = col + e;
-                            if (cc <= rr[k]) {
-                                dot[k] += v[e] * pc[e];
-                                if (cc < rr[k]) y[ch][e] += v[e] * pr[k];
-                            }
-                        }
-                    }
+                for (int e = 0; e < VEC; ++e) {
+                    dot[k] += v[e] * pc[e];
+                    y[c2][e] += (col + e == rr[k] ? (A)0 : v[e]) * pr[k];
                 }
             }
         }
@@ -628,25 +660,29 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < ROWS; ++k)
-                if (rr[k] >= 0) srow[rr[k] - b.r0] = dot[k];
+                if (rr[k] >= 0) srow[half][rr[k] - b.r0] = dot[k];
         }
     }
     __syncthreads();
-    // sp is free now: sum the four wavefronts' column partials in order
+    // sp is free now: sum the column partials in a fixed order (pair 0, then pair 1)
     for (int w = 0; w < 4; ++w) {
-        if (wv == w) {
+        const int wp = w >> 1, wh = w & 1;   // pair-major order: waves 0,1 (pair 0) then 2,3 (pair 1)
+        if (pair == wp && half == wh) {
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
+            for (int c2 = 0; c2 < NH; ++c2)
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
+                    const int ch = 2 * c2 + half;
                     const int cc = ch * CH + lane * VEC + e;
-                    if (cc < b.r1) sp[cc] = (w == 0 ? (A)0 : sp[cc]) + y[ch][e];
+                    if (ch < NCH && cc < b.r1) sp[cc] = (wp == 0 ? (A)0 : sp[cc]) + y[c2][e];
                 }
         }
         __syncthreads();
     }
     for (int cidx = tid; cidx < b.r1; cidx += NT)
-        z[b.zoff + cidx] = sp[cidx] + (cidx >= b.r0 ? srow[cidx - b.r0] : (A)0);
+        z[b.zoff + cidx] = sp[cidx] + (cidx >= b.r0 ? srow[0][cidx - b.r0] + srow[1][cidx - b.r0] : (A)0);
+    __syncthreads();  // sp and srow are reused by the next segment
+    }
 }
 
 template <typename A>
@@ -798,56 +834,58 @@ hipError_t launch_syrk(int prec, const SyrkTile* tiles, int32_t ntiles, const in
 }
 
 template <typename T, int NCH, int ROWS, bool NTL>
-static void apply_launch(const Band* bands, int32_t nbands, const T* f, const double* lam, const int32_t* dmap,
-                         typename Acc<T>::type* z, hipStream_t st)
+static void apply_launch(const Band* bands, const int32_t* seg_ptr, int32_t ngroups, const T* f, const double* lam,
+                         const int32_t* dmap, typename Acc<T>::type* z, hipStream_t st)
 {
     // a band keeps NCH * 64 * VEC columns of p and of the row sums in LDS;
     // only instantiate shapes whose capacity stays within 4096 columns
     if constexpr (NCH * 64 * (16 / (int)sizeof(T)) <= 4096)
-        hipLaunchKernelGGL((apply_band_kernel<T, NCH, ROWS, NTL>), dim3(nbands), dim3(NT), 0, st, bands, f, lam,
-                           dmap, z);
+        hipLaunchKernelGGL((apply_band_kernel<T, NCH, ROWS, NTL>), dim3(ngroups), dim3(NT), 0, st, bands, seg_ptr,
+                           f, lam, dmap, z);
 }
 
 template <typename T, int ROWS, bool NTL>
-static hipError_t apply_dispatch_nch(int nch, const Band* bands, int32_t nbands, const void* F, const double* lam,
-                                     const int32_t* dmap, void* z, hipStream_t st)
+static hipError_t apply_dispatch_nch(int nch, const Band* bands, const int32_t* seg_ptr, int32_t ngroups,
+                                     const void* F, const double* lam, const int32_t* dmap, void* z, hipStream_t st)
 {
     using A = typename Acc<T>::type;
     const T* f = (const T*)F;
     A* zz = (A*)z;
     if (nch * 64 * (16 / (int)sizeof(T)) > 4096) return hipErrorInvalidValue;
     switch (nch) {
-    case 1: apply_launch<T, 1, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
-    case 2: apply_launch<T, 2, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
-    case 4: apply_launch<T, 4, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
-    case 8: apply_launch<T, 8, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
-    case 16: apply_launch<T, 16, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
-    case 32: apply_launch<T, 32, ROWS, NTL>(bands, nbands, f, lam, dmap, zz, st); break;
+    case 1: apply_launch<T, 1, ROWS, NTL>(bands, seg_ptr, ngroups, f, lam, dmap, zz, st); break;
+    case 2: apply_launch<T, 2, ROWS, NTL>(bands, seg_ptr, ngroups, f, lam, dmap, zz, st); break;
+    case 4: apply_launch<T, 4, ROWS, NTL>(bands, seg_ptr, ngroups, f, lam, dmap, zz, st); break;
+    case 8: apply_launch<T, 8, ROWS, NTL>(bands, seg_ptr, ngroups, f, lam, dmap, zz, st); break;
+    case 16: apply_launch<T, 16, ROWS, NTL>(bands, seg_ptr, ngroups, f, lam, dmap, zz, st); break;
+    case 32: apply_launch<T, 32, ROWS, NTL>(bands, seg_ptr, ngroups, f, lam, dmap, zz, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t apply_dispatch(int nch, int rows, bool ntl, const Band* bands, int32_t nbands, const void* F,
-                                 const double* lam, const int32_t* dmap, void* z, hipStream_t st)
+static hipError_t apply_dispatch(int nch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
+                                 int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
+                                 hipStream_t st)
 {
-    if (rows == 1)
-        return ntl ? apply_dispatch_nch<T, 1, true>(nch, bands, nbands, F, lam, dmap, z, st)
-                   : apply_dispatch_nch<T, 1, false>(nch, bands, nbands, F, lam, dmap, z, st);
     if (rows == 2)
-        return ntl ? apply_dispatch_nch<T, 2, true>(nch, bands, nbands, F, lam, dmap, z, st)
-                   : apply_dispatch_nch<T, 2, false>(nch, bands, nbands, F, lam, dmap, z, st);
+        return ntl ? apply_dispatch_nch<T, 2, true>(nch, bands, seg_ptr, ngroups, F, lam, dmap, z, st)
+                   : apply_dispatch_nch<T, 2, false>(nch, bands, seg_ptr, ngroups, F, lam, dmap, z, st);
+    if (rows == 4)
+        return ntl ? apply_dispatch_nch<T, 4, true>(nch, bands, seg_ptr, ngroups, F, lam, dmap, z, st)
+                   : apply_dispatch_nch<T, 4, false>(nch, bands, seg_ptr, ngroups, F, lam, dmap, z, st);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* bands, int32_t nbands,
-                             const void* F, const double* lam, const int32_t* dmap, void* z, hipStream_t st)
+hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
+                             int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
+                             hipStream_t st)
 {
-    if (nbands <= 0) return hipSuccess;
-    if (prec == 0) return apply_dispatch<double>(nch, rows, ntl, bands, nbands, F, lam, dmap, z, st);
-    if (prec == 1) return apply_dispatch<float>(nch, rows, ntl, bands, nbands, F, lam, dmap, z, st);
-    return apply_dispatch<bf16_t>(nch, rows, ntl, bands, nbands, F, lam, dmap, z, st);
+    if (ngroups <= 0) return hipSuccess;
+    if (prec == 0) return apply_dispatch<double>(nch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, st);
+    if (prec == 1) return apply_dispatch<float>(nch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, st);
+    return apply_dispatch<bf16_t>(nch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, st);
 }
 
 hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* gptr, const GatherEnt* ents,

@@ -52,9 +52,11 @@ hipError_t launch_elem_adjoint(int64_t nelem, const ElemRef* elems, const int32_
 // prec: 0 f64, 1 f32, 2 bf16
 hipError_t launch_syrk(int prec, const SyrkTile* tiles, int32_t ntiles, const int32_t* lists,
                        const DevSN* sns, const double* X, void* F, hipStream_t st);
-// rows: rows per wavefront pass (1 or 2); ntl: non-temporal loads of F
-hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* bands, int32_t nbands,
-                             const void* F, const double* lam, const int32_t* dmap, void* z, hipStream_t st);
+// rows: rows per pass of a wavefront pair (2 or 4); ntl: non-temporal loads
+// of F; work-group g handles the segments bands[seg_ptr[g] .. seg_ptr[g+1])
+hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
+                             int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
+                             hipStream_t st);
 hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* gptr, const GatherEnt* ents,
                          const int64_t* band_zoff, const void* z, double* q, hipStream_t st);
 

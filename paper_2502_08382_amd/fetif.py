@@ -44,7 +44,7 @@ class _Opt(ctypes.Structure):
     _fields_ = [("f_storage", ctypes.c_int), ("leaf_nodes", ctypes.c_int32),
                 ("nthreads", ctypes.c_int32), ("apply_band", ctypes.c_int32),
                 ("trsm_chunk", ctypes.c_int32), ("apply_rows", ctypes.c_int32),
-                ("apply_nontemporal", ctypes.c_int32)]
+                ("apply_nontemporal", ctypes.c_int32), ("apply_split", ctypes.c_int32)]
 
 
 class _PcpgOpt(ctypes.Structure):
@@ -64,7 +64,7 @@ class _Info(ctypes.Structure):
                 ("f_elements", ctypes.c_int64), ("f_tri_elements", ctypes.c_int64),
                 ("trsm_flops", ctypes.c_double), ("syrk_flops", ctypes.c_double),
                 ("factor_flops", ctypes.c_double), ("trsm_levels", ctypes.c_int32),
-                ("apply_groups", ctypes.c_int32)]
+                ("apply_groups", ctypes.c_int32), ("apply_elements", ctypes.c_int64)]
 
 
 EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply",
@@ -107,7 +107,7 @@ def load_library(path=None):
     L.fetiF_hfactor_free.argtypes = [vp]
     L.fetiF_profile_enable.argtypes = [vp, ctypes.c_int]
     L.fetiF_profile_read.argtypes = [vp, ctypes.c_int, vp, vp, i32]
-    L.fetiF_set_apply.argtypes = [vp, i32, i32, i32]
+    L.fetiF_set_apply.argtypes = [vp, i32, i32, i32, i32]
     L.fetiF_apply_implicit.argtypes = [vp, vp, vp, vp]
     L.fetiF_dual_rhs.argtypes = [vp, vp, vp, vp, vp]
     L.fetiF_coarse_rhs.argtypes = [vp, vp, vp, vp]
@@ -175,9 +175,9 @@ class _SubArrays:
 
 
 def _options(f_storage="f64", leaf_nodes=0, nthreads=0, apply_band=0, trsm_chunk=0, apply_rows=0,
-             apply_nontemporal=-1):
+             apply_nontemporal=-1, apply_split=-1):
     prec = _PREC[f_storage] if isinstance(f_storage, str) else int(f_storage)
-    return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk, apply_rows, apply_nontemporal)
+    return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk, apply_rows, apply_nontemporal, apply_split)
 
 
 class FetiContext:
@@ -253,9 +253,10 @@ class FetiContext:
         self._check(self.L.fetiF_query(self.h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
 
-    def set_apply(self, band_elems=0, rows=0, nontemporal=-1):
-        """Re-plan the apply (band size in stored elements, rows per pass, load policy)."""
-        self._check(self.L.fetiF_set_apply(self.h, int(band_elems), int(rows), int(nontemporal)))
+    def set_apply(self, band_elems=0, rows=0, nontemporal=-1, split=-1):
+        """Re-plan the apply (band size in stored elements, rows per pass,
+        load policy, work split: 0 bands per triangle, 1 equal shares)."""
+        self._check(self.L.fetiF_set_apply(self.h, int(band_elems), int(rows), int(nontemporal), int(split)))
 
     def profile(self, on=True):
         """Record HIP events around every device phase (see PHASES)."""

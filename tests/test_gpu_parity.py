@@ -128,3 +128,72 @@ def test_apply_reduced_precision(torch_cuda, prec, tol):
     else:
         assert rel_fro(Fg, Fs[0]) <= 2 ** -8
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5), ("bf16", 2e-2)])
+def test_apply_every_launch_shape(torch_cuda, prec, tol):
+    """Every work split, band size, rows per pass and load policy the tuner
+    may pick gives the same operator: against the oracle to the storage
+    precision's bound, and between shapes to summation-order rounding."""
+    prob = config_problem(2, scale=(2, 12))
+    say("apply shapes", prec, "m", min(s.m for s in prob.subs), max(s.m for s in prob.subs))
+    ctx = make_context(prob, f_storage=prec)
+    upload_and_assemble(ctx, prob)
+    Fs = [oracle_F(prob, i) for i in range(prob.nsub)]
+    q_o = feti.apply_explicit(Fs, [s.dual_map for s in prob.subs], prob.lam, prob.n_lambda)
+    total = ctx.info()["apply_elements"]
+    ref = None
+    for split in (0, 1):
+        for band in (1, 3000, total // 5, total):
+            for rows in (2, 4):
+                for nt in (0, 1):
+                    ctx.set_apply(band, rows, nt, split)
+                    q_g = gpu_apply(ctx, prob.lam)
+                    err = np.linalg.norm(q_g - q_o) / np.linalg.norm(q_o)
+                    say(f"split {split} band {band} rows {rows} nt {nt}: groups {ctx.info()['apply_groups']}"
+                        f" rel err {err:.2e}")
+                    assert err <= tol
+                    if ref is None:
+                        ref = q_g
+                    else:
+                        d = np.linalg.norm(q_g - ref) / np.linalg.norm(ref)
+                        assert d <= (1e-14 if prec == "f64" else 1e-6)
+    ctx.close()
+
+
+def test_full_size_heat_sampled(torch_cuda):
+    """The 512-subdomain heat workload (8^3 subdomains of 12^3 elements,
+    lognormal conductivity) at full size in the default launch
+    configuration: F~_i of sampled subdomains against the oracle, and sampled
+    entries of the applied operator against the oracle's row sums over the
+    subdomains holding them."""
+    prob = config_problem(2)
+    say("full size heat", "nsub", prob.nsub, "n_lambda", prob.n_lambda)
+    ctx = make_context(prob)
+    upload_and_assemble(ctx, prob)
+    for i in (0, 137, prob.nsub - 1):
+        Fg = ctx.download_F(i)
+        e = rel_fro(Fg, oracle_F(prob, i))
+        tol = max(1e-12, _kappa(prob.subs[i].Kreg) * np.finfo(float).eps) if e > 1e-12 else 1e-12
+        say(f"sub {i} m {prob.subs[i].m}: F vs oracle {e:.2e} (tol {tol:.2e})")
+        assert e <= tol
+    q_g = gpu_apply(ctx, prob.lam)
+    rng = np.random.default_rng(7)
+    owners = {}
+    for i, s in enumerate(prob.subs):
+        for a, g in enumerate(s.dual_map):
+            owners.setdefault(int(g), []).append((i, a))
+    Fcache, tolF = {}, {}
+    for g in rng.choice(prob.n_lambda, 6, replace=False):
+        acc, bound = 0.0, 0.0
+        for i, a in owners[int(g)]:
+            if i not in Fcache:
+                Fcache[i] = oracle_F(prob, i)
+                tolF[i] = max(1e-12, _kappa(prob.subs[i].Kreg) * np.finfo(float).eps)
+            li = prob.lam[prob.subs[i].dual_map]
+            acc += Fcache[i][a] @ li
+            # |dq| <= |dF row| |lambda_i|, the row error at most the operator's
+            bound += tolF[i] * np.linalg.norm(Fcache[i], 2) * np.linalg.norm(li)
+        say(f"q[{g}]: gpu {q_g[g]:.15e} oracle {acc:.15e} bound {bound:.2e}")
+        assert abs(q_g[g] - acc) <= bound
+    ctx.close()

@@ -124,3 +124,29 @@ def test_backward_central_differences(torch_cuda):
             say(f"sub {si} elem {e}: fd {fd:.10e} gpu {gpu:.10e}")
             assert abs(fd - gpu) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(dth).max())
     ctx.close()
+
+
+def test_autograd_function_gradients(torch_cuda):
+    """J = mu^T F(theta) lambda through torch.autograd: dJ/dlambda = F mu and
+    dJ/dtheta equal the oracle's adjoint (workload C5 law, small mesh)."""
+    t = torch_cuda
+    from paper_2502_08382_amd.autograd import feti_apply
+    prob = config_problem(5, scale=(2, 5))
+    ctx = make_context(prob, with_elements=True)
+    ctx.factor_upload([s.Kreg.data for s in prob.subs])
+    ctx.assemble()
+    theta = t.tensor(np.concatenate([s.theta for s in prob.subs]), dtype=t.float64, device="cuda",
+                     requires_grad=True)
+    lam = _dev(t, prob.lam).requires_grad_(True)
+    mu = _dev(t, prob.mu)
+    J = (mu * feti_apply(lam, theta, ctx)).sum()
+    J.backward()
+    Fs = [feti.local_dual_operator(s.Kreg, s.b_dof, s.b_sign) for s in prob.subs]
+    Ds = [s.dual_map for s in prob.subs]
+    J_o = prob.mu @ feti.apply_explicit(Fs, Ds, prob.lam, prob.n_lambda)
+    dl_o = feti.apply_explicit(Fs, Ds, prob.mu, prob.n_lambda)
+    dt_o = np.concatenate([feti.grad_theta(feti.RegInverse(s.Kreg), s, prob.mu, prob.lam) for s in prob.subs])
+    assert abs(J.item() - J_o) <= 1e-12 * abs(J_o)
+    assert np.linalg.norm(lam.grad.cpu().numpy() - dl_o) <= 1e-12 * np.linalg.norm(dl_o)
+    assert np.linalg.norm(theta.grad.cpu().numpy() - dt_o) <= 1e-12 * np.linalg.norm(dt_o)
+    ctx.close()
