@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, vendor figure
+COPY_CAL_BYTES = 1 << 30     # size of the counter-calibration copy
 FP64_PEAK_TFS = 78.6         # MI355X dense FP64 (vector and matrix)
 METRIC = "F assembly ms/1k subdomains; F·λ apply GB/s; break-even iters vs implicit"
 
@@ -53,6 +54,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--apply-band", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="skip the apply autotuner")
+    ap.add_argument("--retune", action="store_true",
+                    help="tune the apply shape even if the stored tuning has this workload")
+    ap.add_argument("--backward", action="store_true",
+                    help="also time fetiF_apply_backward (dlambda and the element adjoint dtheta)")
+    ap.add_argument("--pmc-apply", type=int, default=0, metavar="N",
+                    help="profiling mode: assemble, run N applies in the tuned shape, then copy a 1 GiB "
+                         "buffer three times (the counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -71,8 +79,8 @@ def main():
     log(f"problem C{args.config}: {prob.nsub} subdomains, n_lambda={prob.n_lambda}, "
         f"gen {time.time() - t0:.1f}s")
     t0 = time.time()
-    ctx = FetiContext([subdomain_dict(s) for s in prob.subs], prob.n_lambda, device=0,
-                      f_storage=args.prec, apply_band=args.apply_band)
+    ctx = FetiContext([subdomain_dict(s, with_elements=args.backward) for s in prob.subs], prob.n_lambda,
+                      device=0, f_storage=args.prec, apply_band=args.apply_band)
     info = ctx.info()
     log(f"create (ordering + symbolic + plan + device structures) {time.time() - t0:.1f}s; "
         f"L values {info['factor_values']:.3g}, X values {info['x_values']:.3g}, "
@@ -87,9 +95,35 @@ def main():
     sol = torch.empty_like(lam)
     stream = torch.cuda.Stream()
     refine = args.prec != "f64"
+    tune_cache = os.path.join(ROOT, "paper_2502_08382_amd", "tuned_apply.json")
+
+    def shape_key(t):
+        return (f"{CONFIGS[args.config]}|{args.prec}|split{t['split']}-band{t['band']}-rows{t['rows']}"
+                f"-nt{t['nontemporal']}")
+
+    if args.pmc_apply:
+        from paper_2502_08382_amd.autotune import tune_apply
+        with torch.cuda.stream(stream):
+            ctx.factor_upload(kvals, stream=stream)
+            ctx.assemble(stream=stream)
+            tune = tune_apply(ctx, lam, q, stream=stream, cache=tune_cache, reps=5)
+            for _ in range(args.pmc_apply):
+                ctx.apply(lam, q, stream=stream)
+            torch.cuda.synchronize()
+        log(f"{args.pmc_apply} applies done; key {shape_key(tune)}")
+        a = torch.empty(COPY_CAL_BYTES // 8, dtype=torch.float64, device=dev)
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copies done")
+        ctx.close()
+        return
 
     host_factor_s = []
     solver = []
+    pcpg_events = []
     tune = None
 
     def step():
@@ -99,11 +133,15 @@ def main():
         ctx.assemble(stream=stream)
         ctx.coarse_rhs(f, e, stream=stream)
         ctx.dual_rhs(f, d, stream=stream)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
         if refine:
             r = ctx.pcpg(d, e, sol, tol=args.tol, refine=True, inner_tol=1e-4 if args.prec == "f32" else 1e-2,
                          max_iters=20000, use_graph=False, stream=stream)
         else:
             r = ctx.pcpg(d, e, sol, fixed_iters=args.iters, use_graph=False, stream=stream)
+        ev1.record(stream)
+        pcpg_events.append((ev0, ev1))
         solver.append(r)
 
     with torch.cuda.stream(stream):
@@ -114,11 +152,13 @@ def main():
             if w == 0 and not args.no_tune:
                 from paper_2502_08382_amd.autotune import tune_apply
                 tt = time.time()
-                tune = tune_apply(ctx, lam, q, stream=stream)
-                log(f"apply autotune {time.time() - tt:.1f}s: band={tune['band']} rows={tune['rows']} "
+                tune = tune_apply(ctx, lam, q, stream=stream, cache=None if args.retune else tune_cache)
+                log(f"apply autotune {time.time() - tt:.1f}s{' (stored)' if tune.get('cached') else ''}: "
+                    f"split={tune['split']} band={tune['band']} rows={tune['rows']} "
                     f"nontemporal={tune['nontemporal']} ({tune['ms'] * 1e3:.1f} us)")
         host_factor_s.clear()
         solver.clear()
+        pcpg_events.clear()
         ctx.profile(True)
         ctx.profile_read(reset=True)
         torch.cuda.synchronize()
@@ -131,10 +171,45 @@ def main():
         prof = ctx.profile_read(reset=True)
     log(f"timed {args.steps} steps in {elapsed:.3f}s; phases {prof}; solver {solver[-1]}")
 
+    # ---- the apply alone, eager and replayed from a captured HIP graph
+    # (HIP events on the launching stream; outside the timed steps)
+    def event_time(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            fn()
+            e0.record(stream)
+            for _ in range(n):
+                fn()
+            e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    with torch.cuda.stream(stream):
+        ctx.apply(lam, q, stream=stream)
+    torch.cuda.synchronize()
+    q_eager = q.clone()
+    t_apply_eager = event_time(lambda: ctx.apply(lam, q, stream=stream), 50)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ctx.apply(lam, q)
+    t_apply_graph = event_time(graph.replay, 50)
+    torch.cuda.synchronize()
+    graph_same = bool(torch.equal(q, q_eager))
+    log(f"apply alone: eager {t_apply_eager * 1e3:.1f} us, graph replay {t_apply_graph * 1e3:.1f} us, "
+        f"graph result bitwise equal to eager: {graph_same}")
+    del graph
+    t_backward = None
+    if args.backward:
+        g_d = torch.tensor(prob.mu, dtype=torch.float64, device=dev)
+        dl = torch.empty_like(lam)
+        dth = torch.empty(sum(len(s.theta) for s in prob.subs), dtype=torch.float64, device=dev)
+        t_backward = event_time(lambda: ctx.apply_backward(g_d, lam, dl, dth, stream=stream), 10)
+        log(f"apply_backward (dlambda + dtheta) {t_backward:.3f} ms")
+
     K = args.steps
     ms = {p: v[0] for p, v in prof.items()}
     cnt = {p: max(1, v[1]) for p, v in prof.items()}
-    t_upload = ms["factor_copy"] / cnt["factor_copy"]
+    t_upload = ms["factor_copy"] / K     # all chunks of one step's copy
     t_asm = (ms["rhs_init"] + ms["trsm"] + ms["syrk"]) / K
     t_band = ms["apply_band"] / cnt["apply_band"]
     t_gather = ms["apply_gather"] / cnt["apply_gather"]
@@ -142,8 +217,11 @@ def main():
     bytes_el = {"f64": 8, "f32": 4, "bf16": 2}[args.prec]
     sum_m = info["sum_m"]
     tri_bytes = bytes_el * info["f_tri_elements"]
-    band_bytes = tri_bytes + 12 * sum_m            # triangle + lambda[D_i] gather (value + index)
-    apply_bytes = band_bytes + 8 * prob.n_lambda   # + the q write of the gather kernel
+    # algorithmic bytes of one apply: each stored element of every triangle
+    # once, plus per local multiplier the lambda value (8), its index (4) and
+    # the partial q~ write (8); all of them move in the band kernel
+    apply_bytes = tri_bytes + 20 * sum_m
+    band_bytes = apply_bytes
     apply_gbs = apply_bytes / (t_apply * 1e-3) / 1e9
     band_gbs = band_bytes / (t_band * 1e-3) / 1e9
     asm_flops = info["trsm_flops"] + info["syrk_flops"]
@@ -175,19 +253,30 @@ def main():
                    "rel_residual": solver[-1]["rel_residual"],
                    "ms_per_iter": None},
         "apply_ms": round(t_apply, 4),
+        "apply_alone_us": {"eager": round(t_apply_eager * 1e3, 2), "hip_graph": round(t_apply_graph * 1e3, 2),
+                           "graph_bitwise_equal": graph_same},
+        "backward_ms": None if t_backward is None else round(t_backward, 4),
         "apply_band_ms": round(t_band, 4),
         "apply_gather_ms": round(t_gather, 4),
         "factor_copy_ms": round(t_upload, 3),
-        "apply_shape": None if tune is None else {k: tune[k] for k in ("band", "rows", "nontemporal")},
+        "apply_shape": None if tune is None else {k: tune[k] for k in ("split", "band", "rows", "nontemporal")},
         "host_factor_s": round(float(np.mean(host_factor_s)), 3) if host_factor_s else None,
         "roofline": {"bound": "hbm", "kernel": "apply_band_kernel", "achieved": round(band_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(band_gbs / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_launch": int(band_bytes)},
     }
 
-    # solver time per iteration: the step minus factor copy, assembly, solves with
-    # the factors and the host factorisation (the PCPG dominates what remains)
-    t_solve_ms = elapsed / K * 1e3 - t_upload - t_asm - ms["solves"] / K - float(np.mean(host_factor_s)) * 1e3
+    if tune is not None:
+        from paper_2502_08382_amd.traffic import lookup
+        rec = lookup(shape_key(tune))
+        if rec is not None:
+            result["roofline"]["traffic"] = int(rec["traffic_bytes"])
+            result["roofline"]["traffic_source"] = (f"rocprofv3 FETCH_SIZE x {rec['fetch_factor']} + WRITE_SIZE x "
+                                                    f"{rec['write_factor']} (1 GiB copy calibration)")
+
+    # solver time: HIP events around the PCPG call on its stream
+    t_solve_ms = float(np.mean([a.elapsed_time(b) for a, b in pcpg_events]))
+    result["solver"]["ms"] = round(t_solve_ms, 3)
     result["solver"]["ms_per_iter"] = round(t_solve_ms / max(1, solver[-1]["iters"]), 4)
     result["solves_with_factors_ms"] = round(ms["solves"] / K, 3)
 

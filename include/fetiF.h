@@ -110,6 +110,7 @@ typedef struct {
     int32_t apply_nontemporal; /* 1: stream F~ with non-temporal loads (default), 0: cached */
     int32_t apply_split;  /* apply work split: 0 bands per triangle, largest first (default);
                              1 equal shares of all stored elements, one per work-group */
+    int32_t trsm_panel;   /* most supernode columns per TRSM panel, a multiple of 16 (default 48) */
 } fetiF_options;
 
 /* Preparation (Alg. 2, "preparation"; Sec. IV-B "Preparation"): nested

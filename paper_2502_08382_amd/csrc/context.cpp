@@ -337,6 +337,8 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
             d.nrows = x.nrows;
             d.j0 = P.j0[s];
             d.w = P.w[s];
+            d.ld = x.ncols + x.nrows;
+            d.pad = 0;
             sns.push_back(d);
             rows.insert(rows.end(), S.rows.begin() + x.row_off, S.rows.begin() + x.row_off + x.nrows);
             maxlev = std::max(maxlev, x.level);
@@ -409,61 +411,96 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         }
         c->apply_nch = nch;
     }
-    // TRSM levels: items per height level.  A work-group has W wavefronts of
-    // 16 RHS columns each; W shrinks for large supernodes so that the solved
-    // blocks (W * ceil(ns/16) * 2 KiB of LDS) fit.
-    c->level_items.assign(maxlev + 1, {});
-    c->level_maxns.assign(maxlev + 1, 0);
-    c->level_waves.assign(maxlev + 1, 4);
-    for (int32_t i = 0; i < nsub; ++i) {
-        const SubPlan& P = c->subs[i];
-        for (size_t s = 0; s < P.sym.sn.size(); ++s)
-            if (P.w[s] > 0) {
-                int32_t L = P.sym.sn[s].level;
-                c->level_maxns[L] = std::max(c->level_maxns[L], P.sym.sn[s].ncols);
+    // TRSM schedule.  Every supernode with RHS columns is cut into column
+    // panels of at most trsm_panel columns (a multiple of 16): panel k starts
+    // at diagonal offset o = k * trsm_panel of the same storage, and the
+    // supernode's columns after the panel count among its below rows, so the
+    // panel's update of them is an ordinary below-row update.  Panel levels:
+    // panel k of a supernode runs one level after panel k - 1, and its first
+    // panel one level after the last panel of every child.  Two panels of one
+    // level then never belong to an ancestor and a descendant, so they own
+    // disjoint RHS column ranges and write disjoint entries of X.  A
+    // work-group has W wavefronts of 16 RHS columns each; W shrinks when the
+    // solved blocks (W * ceil(ncols/16) * 2 KiB of LDS) would not fit.
+    std::vector<DevSN> tsns;
+    std::vector<int32_t> trows;
+    std::vector<int32_t> tlevel;
+    int32_t tmaxlev = 0;
+    {
+        const int32_t PW = opt.trsm_panel;
+        for (int32_t i = 0; i < nsub; ++i) {
+            const SubPlan& P = c->subs[i];
+            const Symbolic& S = P.sym;
+            const int32_t nsn = (int32_t)S.sn.size();
+            std::vector<int32_t> next_level(nsn, 0);   // first level free above each supernode's panels
+            for (int32_t s = 0; s < nsn; ++s) {        // postorder: children before parents
+                const Supernode& x = S.sn[s];
+                const DevSN& d = sns[P.snbase + s];
+                int32_t L = next_level[s];
+                if (P.w[s] > 0) {
+                    for (int32_t o = 0; o < x.ncols; o += PW) {
+                        const int32_t cw = std::min(PW, x.ncols - o);
+                        DevSN t = d;
+                        t.lval = d.lval + (int64_t)o * d.ld + o;
+                        t.linv = d.linv + (int64_t)(o / 16) * 256;
+                        t.xoff = d.xoff + (int64_t)o * P.w[s];
+                        t.rowsoff = (int64_t)trows.size();
+                        t.first = x.first + o;
+                        t.ncols = cw;
+                        t.nrows = x.ncols - o - cw + x.nrows;
+                        for (int32_t k = o + cw; k < x.ncols; ++k) trows.push_back(x.first + k);
+                        trows.insert(trows.end(), S.rows.begin() + x.row_off, S.rows.begin() + x.row_off + x.nrows);
+                        tsns.push_back(t);
+                        tlevel.push_back(L++);
+                    }
+                }
+                if (x.parent >= 0) next_level[x.parent] = std::max(next_level[x.parent], L);
+                tmaxlev = std::max(tmaxlev, L - 1);
             }
+        }
     }
+    c->level_items.assign(tmaxlev + 1, {});
+    c->level_maxns.assign(tmaxlev + 1, 0);
+    c->level_waves.assign(tmaxlev + 1, 4);
+    for (size_t t = 0; t < tsns.size(); ++t)
+        c->level_maxns[tlevel[t]] = std::max(c->level_maxns[tlevel[t]], tsns[t].ncols);
     const int32_t wmax = std::max(1, std::min(4, opt.trsm_chunk / 16));
-    for (int32_t L = 0; L <= maxlev; ++L) {
+    for (int32_t L = 0; L <= tmaxlev; ++L) {
         int32_t mx = std::max(1, c->level_maxns[L]);
         int32_t W = wmax;
         while (W > 1 && trsm_lds_bytes(W, mx) > 65536) W /= 2;
         if (trsm_lds_bytes(W, mx) > 160 * 1024) {
             delete c;
-            return fail(nullptr, FETIF_ENOTSUP, "a supernode has more than 1280 columns");
+            return fail(nullptr, FETIF_ENOTSUP, "a TRSM panel has more than 1280 columns");
         }
         c->level_waves[L] = W;
     }
-    for (int32_t i = 0; i < nsub; ++i) {
-        const SubPlan& P = c->subs[i];
-        for (size_t s = 0; s < P.sym.sn.size(); ++s) {
-            if (P.w[s] <= 0) continue;
-            int32_t L = P.sym.sn[s].level;
-            int32_t slot = 16 * c->level_waves[L];
-            for (int32_t c0 = 0; c0 < P.w[s]; c0 += slot) {
-                TrsmItem it;
-                it.sn = P.snbase + (int32_t)s;
-                it.c0 = c0;
-                it.cw = std::min(slot, P.w[s] - c0);
-                it.pad = 0;
-                c->level_items[L].push_back(it);
-            }
+    for (size_t t = 0; t < tsns.size(); ++t) {
+        const int32_t L = tlevel[t];
+        const int32_t slot = 16 * c->level_waves[L];
+        for (int32_t c0 = 0; c0 < tsns[t].w; c0 += slot) {
+            TrsmItem it;
+            it.sn = (int32_t)t;
+            it.c0 = c0;
+            it.cw = std::min(slot, tsns[t].w - c0);
+            it.pad = 0;
+            c->level_items[L].push_back(it);
         }
     }
     std::vector<TrsmItem> all_items;
-    c->level_off.assign(maxlev + 2, 0);
-    for (int32_t L = 0; L <= maxlev; ++L) {
+    c->level_off.assign(tmaxlev + 2, 0);
+    for (int32_t L = 0; L <= tmaxlev; ++L) {
         auto& v = c->level_items[L];
-        // larger supernodes first
+        // larger panels first
         std::stable_sort(v.begin(), v.end(), [&](const TrsmItem& a, const TrsmItem& b) {
-            const DevSN& x = sns[a.sn];
-            const DevSN& y = sns[b.sn];
+            const DevSN& x = tsns[a.sn];
+            const DevSN& y = tsns[b.sn];
             return (int64_t)x.ncols * (x.ncols + 2 * x.nrows) > (int64_t)y.ncols * (y.ncols + 2 * y.nrows);
         });
         c->level_off[L] = (int64_t)all_items.size();
         all_items.insert(all_items.end(), v.begin(), v.end());
     }
-    c->level_off[maxlev + 1] = (int64_t)all_items.size();
+    c->level_off[tmaxlev + 1] = (int64_t)all_items.size();
     // SYRK tiles: most expensive first
     {
         std::vector<int64_t> cost(tiles.size());
@@ -751,6 +788,8 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     }
     CK(dalloc(c, &c->dSN, sns.size()));
     CK(dalloc(c, &c->dRows, rows.size()));
+    CK(dalloc(c, &c->dTSN, tsns.size()));
+    CK(dalloc(c, &c->dTRows, trows.size()));
     CK(dalloc(c, &c->dXRows, xrows.size()));
     CK(dalloc(c, &c->dUnits, units.size()));
     CK(dalloc(c, &c->dItems, all_items.size()));
@@ -759,6 +798,8 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     CK(dalloc(c, &c->dDmap, dmap.size()));
     CK(upload(c->dSN, sns));
     CK(upload(c->dRows, rows));
+    CK(upload(c->dTSN, tsns));
+    CK(upload(c->dTRows, trows));
     CK(upload(c->dXRows, xrows));
     CK(upload(c->dUnits, units));
     CK(upload(c->dItems, all_items));
@@ -795,36 +836,57 @@ extern "C" fetiF_status fetiF_factor_upload(fetiF_ctx c, int32_t first, int32_t 
         HIPCHK(c, hipEventSynchronize(c->upload_done));
         c->upload_pending = false;
     }
-    std::vector<int32_t> bad(count, -1);
-    parallel_for(count, c->nthreads, [&](int32_t k) {
-        const SubPlan& P = c->subs[first + k];
-        bad[k] = numeric_cholesky(P.sym, k_vals[k], c->hStage + P.lbase);
-    });
-    for (int32_t k = 0; k < count; ++k)
-        if (bad[k] >= 0) {
-            const SubPlan& P = c->subs[first + k];
-            return fail(c, FETIF_ENOTSPD,
-                        "subdomain " + std::to_string(first + k) + ": non-positive pivot at permuted column " +
-                            std::to_string(bad[k]) + " (original dof " + std::to_string(P.sym.perm[bad[k]]) + ")");
-        }
-    const SubPlan& P0 = c->subs[first];
-    const SubPlan& P1 = c->subs[first + count - 1];
-    const int64_t n = P1.lbase + P1.sym.nvals - P0.lbase;
-    PhaseTimer t0(c, st, 0);
-    HIPCHK(c, hipMemcpyAsync(c->dL + P0.lbase, c->hStage + P0.lbase, sizeof(double) * (size_t)n,
-                             hipMemcpyHostToDevice, st));
+    // any upload replaces factor values: F~ must be assembled again, and on
+    // failure the whole range counts as not uploaded
+    c->assembled = false;
+    // chunks of about 64 MiB of factor values: the copy of a chunk and its
+    // diagonal-block inverses run on the stream while the host factors the
+    // next chunk (each subdomain has its own staging area)
+    constexpr int64_t kChunkVals = int64_t(8) << 20;
+    for (int32_t k0 = 0; k0 < count;) {
+        int32_t k1 = k0;
+        int64_t vals = 0;
+        while (k1 < count && (k1 == k0 || vals < kChunkVals)) vals += c->subs[first + k1++].sym.nvals;
+        std::vector<int32_t> bad(k1 - k0, -1);
+        parallel_for(k1 - k0, c->nthreads, [&](int32_t k) {
+            const SubPlan& P = c->subs[first + k0 + k];
+            bad[k] = numeric_cholesky(P.sym, k_vals[k0 + k], c->hStage + P.lbase);
+        });
+        for (int32_t k = 0; k < k1 - k0; ++k)
+            if (bad[k] >= 0) {
+                const SubPlan& P = c->subs[first + k0 + k];
+                for (int32_t t = 0; t < count; ++t)
+                    if (c->uploaded[first + t]) {
+                        c->uploaded[first + t] = 0;
+                        c->n_uploaded--;
+                    }
+                if (k0 > 0) {   // earlier chunks' copies may still read the staging area
+                    HIPCHK(c, hipEventRecord(c->upload_done, st));
+                    c->upload_pending = true;
+                }
+                return fail(c, FETIF_ENOTSPD,
+                            "subdomain " + std::to_string(first + k0 + k) + ": non-positive pivot at permuted column " +
+                                std::to_string(bad[k]) + " (original dof " + std::to_string(P.sym.perm[bad[k]]) + ")");
+            }
+        const SubPlan& P0 = c->subs[first + k0];
+        const SubPlan& P1 = c->subs[first + k1 - 1];
+        const int64_t n = P1.lbase + P1.sym.nvals - P0.lbase;
+        PhaseTimer t0(c, st, 0);
+        HIPCHK(c, hipMemcpyAsync(c->dL + P0.lbase, c->hStage + P0.lbase, sizeof(double) * (size_t)n,
+                                 hipMemcpyHostToDevice, st));
+        // inverses of the 16x16 diagonal blocks of the uploaded supernodes,
+        // used by the assembly TRSM and by the solves
+        HIPCHK(c, launch_diag_inverse(c->dInv + P0.inv0, P1.inv0 + P1.ninv - P0.inv0, c->dSN, c->dL, c->dLinv, st));
+        HIPCHK(c, t0.stop());
+        k0 = k1;
+    }
     HIPCHK(c, hipEventRecord(c->upload_done, st));
     c->upload_pending = true;
-    // inverses of the 16x16 diagonal blocks of the uploaded supernodes, used
-    // by the assembly TRSM and by the solves
-    HIPCHK(c, launch_diag_inverse(c->dInv + P0.inv0, P1.inv0 + P1.ninv - P0.inv0, c->dSN, c->dL, c->dLinv, st));
-    HIPCHK(c, t0.stop());
     for (int32_t k = 0; k < count; ++k)
         if (!c->uploaded[first + k]) {
             c->uploaded[first + k] = 1;
             c->n_uploaded++;
         }
-    c->assembled = false;
     return FETIF_OK;
 }
 
@@ -845,8 +907,8 @@ extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
     PhaseTimer t2(c, st, 2);
     for (size_t L = 0; L < c->level_items.size(); ++L) {
         int32_t cnt = (int32_t)(c->level_off[L + 1] - c->level_off[L]);
-        HIPCHK(c, launch_trsm_level(c->dItems + c->level_off[L], cnt, c->level_waves[L], c->level_maxns[L], c->dSN,
-                                    c->dL, c->dLinv, c->dRows, c->dXRows, c->dX, st));
+        HIPCHK(c, launch_trsm_level(c->dItems + c->level_off[L], cnt, c->level_waves[L], c->level_maxns[L], c->dTSN,
+                                    c->dL, c->dLinv, c->dTRows, c->dXRows, c->dX, st));
     }
     HIPCHK(c, t2.stop());
     PhaseTimer t3(c, st, 3);

@@ -127,6 +127,8 @@ struct fetiF_ctx_s {
     void* dZ = nullptr;
     DevSN* dSN = nullptr;
     int32_t* dRows = nullptr;
+    DevSN* dTSN = nullptr;     // TRSM column panels
+    int32_t* dTRows = nullptr; // their below-row lists
     XRow* dXRows = nullptr;
     RhsUnit* dUnits = nullptr;
     TrsmItem* dItems = nullptr;

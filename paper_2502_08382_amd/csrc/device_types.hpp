@@ -4,9 +4,12 @@
 
 namespace fetif {
 
-// One supernode of one subdomain, in device form.
+// One supernode of one subdomain, in device form.  The TRSM also uses
+// records of column panels of a supernode (a view of the same storage at
+// diagonal offset o: ncols <= the panel width, the supernode's later columns
+// counted among its below rows, ld the supernode's leading dimension).
 struct DevSN {
-    int64_t lval;    // offset of its (ncols+nrows) x ncols column-major panel in the factor buffer
+    int64_t lval;    // offset of its column-major panel (ncols columns, ld rows) in the factor buffer
     int64_t linv;    // offset of the inverses of its 16x16 diagonal blocks (-1: none)
     int64_t xoff;    // offset of its ncols x w row-major block of X
     int64_t rowsoff; // offset of its below-diagonal row list (subdomain-local rows)
@@ -16,6 +19,8 @@ struct DevSN {
     int32_t nrows;
     int32_t j0;      // first RHS column of its range (sorted local multiplier order)
     int32_t w;       // width of its RHS column range
+    int32_t ld;      // leading dimension of the panel (ncols + nrows for a whole supernode)
+    int32_t pad;
 };
 
 // Diagonal-block inversion item: block rb of supernode sn.

@@ -34,6 +34,55 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+// v from the lane selected by a DPP pattern within each row of 16 lanes
+template <int CTRL>
+__device__ __forceinline__ float dpp_get(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_get(double v)
+{
+    const int64_t b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Sums of R per-lane partials d[0..R) over the 64 lanes of a wavefront
+// (R = 1, 2 or 4).  The first log2(R) butterfly steps (lane distance 32,
+// then 16) each hand half of the still-separate sums to the partner lane,
+// so lane l ends with the sum of d[(l >> (6 - log2 R))], i.e. sum k sits in
+// lanes [k * 64 / R, (k + 1) * 64 / R).  The steps inside a row of 16 lanes
+// use DPP (quad swaps, then half-row and row mirrors) instead of LDS
+// permutes.  Fixed order: the result is bitwise reproducible.
+template <int R, typename A>
+__device__ __forceinline__ A rows_wave_sum(const A (&d)[R], int lane)
+{
+    static_assert(R == 1 || R == 2 || R == 4, "R in {1,2,4}");
+    A v;
+    if constexpr (R == 1) {
+        v = d[0];
+        v += __shfl_xor(v, 32, 64);
+        v += __shfl_xor(v, 16, 64);
+    } else if constexpr (R == 2) {
+        const bool hi = (lane & 32) != 0;
+        v = (hi ? d[1] : d[0]) + __shfl_xor(hi ? d[0] : d[1], 32, 64);
+        v += __shfl_xor(v, 16, 64);
+    } else {
+        const bool hi = (lane & 32) != 0;
+        A k0 = (hi ? d[2] : d[0]) + __shfl_xor(hi ? d[0] : d[2], 32, 64);
+        A k1 = (hi ? d[3] : d[1]) + __shfl_xor(hi ? d[1] : d[3], 32, 64);
+        const bool h16 = (lane & 16) != 0;
+        v = (h16 ? k1 : k0) + __shfl_xor(h16 ? k0 : k1, 16, 64);
+    }
+    v += dpp_get<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_get<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp_get<0x141>(v);  // row_half_mirror: quads 0<->1, 2<->3
+    v += dpp_get<0x140>(v);  // row_mirror: half-rows swapped
+    return v;
+}
+
 // ---------------------------------------------------------------- storage conversions
 
 struct bf16_t {
@@ -147,7 +196,7 @@ __global__ void trsm_level_kernel(const TrsmItem* __restrict__ items, int32_t nb
     const int cbeg = wv * 16;
     if (cbeg >= it.cw) return;  // this wavefront has no columns
     const DevSN s = sns[it.sn];
-    const int ns = s.ncols, nr = s.nrows, d = ns + nr;
+    const int ns = s.ncols, nr = s.nrows, d = s.ld;
     const int nb = (ns + 15) >> 4;
     const int col = it.c0 + cbeg + j;             // column relative to j0
     const bool cv = (cbeg + j) < it.cw;
@@ -186,7 +235,7 @@ __global__ void trsm_level_kernel(const TrsmItem* __restrict__ items, int32_t nb
     for (int rb = 0; rb * 16 < nr; ++rb) {
         d4 acc = {0.0, 0.0, 0.0, 0.0};
         const int arow = ns + rb * 16 + j;
-        const bool av = arow < d;
+        const bool av = arow < ns + nr;
         for (int kb = 0; kb < nb; ++kb) {
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
@@ -426,52 +475,77 @@ constexpr int SP = ST + 2;
 // One work-group forms one 64x64 tile (rows ta, columns tb) of the lower
 // triangle of F~_i = X_i^T X_i, summing over the supernodes whose RHS range
 // meets both column ranges (only their rows of X are non-zero there).
-// Wavefront w computes the 32x32 quadrant (w/2, w%2) as 2x2 MFMA blocks; X
-// rows are staged 16 at a time through LDS, zero outside the range.
+// Wavefront w computes the 32x32 quadrant (w/2, w%2) as 2x2 MFMA blocks.  X
+// rows go through LDS 16 at a time, zero outside the range, in a software
+// pipeline: the global loads of the next 16-row stage are in flight (in
+// registers) while the current stage is multiplied, and the two LDS buffers
+// alternate, so each stage needs one barrier.  On diagonal tiles the two
+// column ranges coincide and one buffer serves both operands.
 template <typename T>
 __global__ __launch_bounds__(NT) void syrk_kernel(const SyrkTile* __restrict__ tiles,
                                                   const int32_t* __restrict__ lists,
                                                   const DevSN* __restrict__ sns,
                                                   const double* __restrict__ X, T* __restrict__ F)
 {
-    __shared__ double sa[SK][SP];
-    __shared__ double sb[SK][SP];
+    __shared__ double sa[2][SK][SP];
+    __shared__ double sb[2][SK][SP];
+    constexpr int U = (SK * ST) / NT;   // staged values per thread and operand
     const SyrkTile t = tiles[blockIdx.x];
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int q = lane >> 4, j = lane & 15;
     const int wi = wv >> 1, wj = wv & 1;
     const int ca0 = t.ta * ST, cb0 = t.tb * ST;
+    const bool diag = t.ta == t.tb;
     d4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int li = t.list0; li < t.list1; ++li) {
-        const DevSN s = sns[lists[li]];
-        for (int k0 = 0; k0 < s.ncols; k0 += SK) {
+    // stage cursor: supernode li of the list, its rows k0 .. k0 + SK
+    int li = t.list0, k0 = 0;
+    double ra[U], rb[U];
+    auto fetch = [&](int l, int kb) {
+        const DevSN s = sns[lists[l]];
 #pragma unroll
-            for (int u = 0; u < (SK * ST) / NT; ++u) {
-                const int idx = tid + u * NT;
-                const int kk = idx / ST, cc = idx - kk * ST;
-                const int k = k0 + kk;
-                const int ja = ca0 + cc - s.j0, jb = cb0 + cc - s.j0;
-                const bool kin = k < s.ncols;
-                const double* xr = X + s.xoff + (int64_t)k * s.w;
-                sa[kk][cc] = (kin && ja >= 0 && ja < s.w) ? xr[ja] : 0.0;
-                sb[kk][cc] = (kin && jb >= 0 && jb < s.w) ? xr[jb] : 0.0;
-            }
-            __syncthreads();
+        for (int u = 0; u < U; ++u) {
+            const int idx = tid + u * NT;
+            const int kk = idx / ST, cc = idx - kk * ST;
+            const int k = kb + kk;
+            const int ja = ca0 + cc - s.j0, jb = cb0 + cc - s.j0;
+            const bool kin = k < s.ncols;
+            const double* xr = X + s.xoff + (int64_t)k * s.w;
+            ra[u] = (kin && ja >= 0 && ja < s.w) ? xr[ja] : 0.0;
+            rb[u] = (!diag && kin && jb >= 0 && jb < s.w) ? xr[jb] : 0.0;
+        }
+    };
+    if (li < t.list1) fetch(li, 0);
+    for (int stage = 0; li < t.list1; ++stage) {
+        const int buf = stage & 1;
 #pragma unroll
-            for (int k4 = 0; k4 < SK / 4; ++k4) {
-                const int kr = 4 * k4 + q;
-                const double a0 = sa[kr][32 * wi + j], a1 = sa[kr][32 * wi + 16 + j];
-                const double b0 = sb[kr][32 * wj + j], b1 = sb[kr][32 * wj + 16 + j];
-                acc[0][0] = mfma16(a0, b0, acc[0][0]);
-                acc[0][1] = mfma16(a0, b1, acc[0][1]);
-                acc[1][0] = mfma16(a1, b0, acc[1][0]);
-                acc[1][1] = mfma16(a1, b1, acc[1][1]);
-            }
-            __syncthreads();
+        for (int u = 0; u < U; ++u) {
+            const int idx = tid + u * NT;
+            const int kk = idx / ST, cc = idx - kk * ST;
+            sa[buf][kk][cc] = ra[u];
+            if (!diag) sb[buf][kk][cc] = rb[u];
+        }
+        __syncthreads();
+        // advance the cursor and start the next stage's loads
+        k0 += SK;
+        if (k0 >= sns[lists[li]].ncols) {
+            ++li;
+            k0 = 0;
+        }
+        if (li < t.list1) fetch(li, k0);
+        const double(*pb)[SP] = diag ? sa[buf] : sb[buf];
+#pragma unroll
+        for (int k4 = 0; k4 < SK / 4; ++k4) {
+            const int kr = 4 * k4 + q;
+            const double a0 = sa[buf][kr][32 * wi + j], a1 = sa[buf][kr][32 * wi + 16 + j];
+            const double b0 = pb[kr][32 * wj + j], b1 = pb[kr][32 * wj + 16 + j];
+            acc[0][0] = mfma16(a0, b0, acc[0][0]);
+            acc[0][1] = mfma16(a0, b1, acc[0][1]);
+            acc[1][0] = mfma16(a1, b0, acc[1][0]);
+            acc[1][1] = mfma16(a1, b1, acc[1][1]);
         }
     }
     constexpr int64_t V = 16 / sizeof(T);
@@ -605,34 +679,30 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
 #pragma unroll
         for (int e = 0; e < VEC; ++e) y[c2][e] = (A)0;
     const char* __restrict__ tri = reinterpret_cast<const char*>(F + b.fbase);
-    for (int r = b.r0 + ROWS * pair; r < b.r1; r += 2 * ROWS) {
-        uint4 raw[ROWS][NH];
-        int rr[ROWS];
-        int rmax = r;
-#pragma unroll
-        for (int k = 0; k < ROWS; ++k) {
-            rr[k] = (r + k < b.r1) ? r + k : -1;   // -1: no such row, its loads read zero
-            rmax = rr[k] > rmax ? rr[k] : rmax;
-        }
-        const int nchunk = rmax / CH + 1;   // chunks holding a column of the pass's longest row
+    // loads of the ROWS rows from r on; rows at or past r1 read zero (empty range)
+    auto issue = [&](int r, uint4 (&raw)[ROWS][NH]) {
 #pragma unroll
         for (int k = 0; k < ROWS; ++k) {
             // padded row r + k: bytes [row_start, row_start + row_bytes)
             const int64_t row_start = packed_row_offset(r + k, VEC) * (int64_t)sizeof(T);
-            const int row_bytes = rr[k] >= 0 ? (int)(VEC * (rr[k] / VEC + 1) * sizeof(T)) : 0;
+            const int row_bytes = r + k < b.r1 ? (int)(VEC * ((r + k) / VEC + 1) * sizeof(T)) : 0;
 #pragma unroll
             for (int c2 = 0; c2 < NH; ++c2) {
                 const int ch = 2 * c2 + half;
                 const int cbyte = ch * CH * (int)sizeof(T);
                 const int nbytes = (ch < NCH && row_bytes > cbyte) ? row_bytes - cbyte : 0;
-                // wavefront-uniform: chunks past the longest row are not issued
-                raw[k][c2] = ch < nchunk ? load16_range<NTL>(tri + row_start + cbyte, (uint32_t)nbytes, lane * 16)
-                                         : make_uint4(0, 0, 0, 0);
+                raw[k][c2] = load16_range<NTL>(tri + row_start + cbyte, (uint32_t)nbytes, lane * 16);
             }
         }
+    };
+    auto consume = [&](int r, const uint4 (&raw)[ROWS][NH]) {
+        int rr[ROWS];
+        int rmax = r;
         A pr[ROWS], dot[ROWS];
 #pragma unroll
         for (int k = 0; k < ROWS; ++k) {
+            rr[k] = (r + k < b.r1) ? r + k : -1;   // -1: no such row
+            rmax = rr[k] > rmax ? rr[k] : rmax;
             pr[k] = rr[k] >= 0 ? sp[rr[k]] : (A)0;
             dot[k] = (A)0;
         }
@@ -655,13 +725,24 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
                 }
             }
         }
-#pragma unroll
-        for (int k = 0; k < ROWS; ++k) dot[k] = wave_sum(dot[k]);
-        if (lane == 0) {
-#pragma unroll
-            for (int k = 0; k < ROWS; ++k)
-                if (rr[k] >= 0) srow[half][rr[k] - b.r0] = dot[k];
-        }
+        // lane l holds the dot of row r + l / (64 / ROWS)
+        const A tot = rows_wave_sum<ROWS>(dot, lane);
+        const int k = lane / (64 / ROWS);
+        if ((lane & (64 / ROWS - 1)) == 0 && r + k < b.r1) srow[half][r + k - b.r0] = tot;
+    };
+    // software pipeline: the loads of the pair's next pass are in flight
+    // while the current pass is computed (two register sets, used in turn)
+    uint4 ra[ROWS][NH], rb[ROWS][NH];
+    int r = b.r0 + ROWS * pair;
+    if (r < b.r1) issue(r, ra);
+    while (r < b.r1) {
+        issue(r + 2 * ROWS, rb);
+        consume(r, ra);
+        r += 2 * ROWS;
+        if (r >= b.r1) break;
+        issue(r + 2 * ROWS, ra);
+        consume(r, rb);
+        r += 2 * ROWS;
     }
     __syncthreads();
     // sp is free now: sum the column partials in a fixed order (pair 0, then pair 1)

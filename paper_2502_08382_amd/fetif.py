@@ -44,7 +44,8 @@ class _Opt(ctypes.Structure):
     _fields_ = [("f_storage", ctypes.c_int), ("leaf_nodes", ctypes.c_int32),
                 ("nthreads", ctypes.c_int32), ("apply_band", ctypes.c_int32),
                 ("trsm_chunk", ctypes.c_int32), ("apply_rows", ctypes.c_int32),
-                ("apply_nontemporal", ctypes.c_int32), ("apply_split", ctypes.c_int32)]
+                ("apply_nontemporal", ctypes.c_int32), ("apply_split", ctypes.c_int32),
+                ("trsm_panel", ctypes.c_int32)]
 
 
 class _PcpgOpt(ctypes.Structure):
@@ -175,9 +176,10 @@ class _SubArrays:
 
 
 def _options(f_storage="f64", leaf_nodes=0, nthreads=0, apply_band=0, trsm_chunk=0, apply_rows=0,
-             apply_nontemporal=-1, apply_split=-1):
+             apply_nontemporal=-1, apply_split=-1, trsm_panel=0):
     prec = _PREC[f_storage] if isinstance(f_storage, str) else int(f_storage)
-    return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk, apply_rows, apply_nontemporal, apply_split)
+    return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk, apply_rows, apply_nontemporal, apply_split,
+                trsm_panel)
 
 
 class FetiContext:

@@ -197,3 +197,32 @@ def test_full_size_heat_sampled(torch_cuda):
         say(f"q[{g}]: gpu {q_g[g]:.15e} oracle {acc:.15e} bound {bound:.2e}")
         assert abs(q_g[g] - acc) <= bound
     ctx.close()
+
+
+def test_failed_upload_invalidates_assembly(torch_cuda):
+    """A factor upload that meets a non-SPD K_reg,i fails with FETIF_ENOTSPD
+    and leaves the context unassembled (ESTATE for assemble and apply) until
+    a good upload; the operator is then exact again."""
+    from paper_2502_08382_amd.fetif import FetiError
+    prob = config_problem(5, scale=(2, 6))
+    say("failed upload", "nsub", prob.nsub)
+    ctx = make_context(prob)
+    upload_and_assemble(ctx, prob)
+    bad = [s.Kreg.data.copy() for s in prob.subs]
+    A = prob.subs[3].Kreg.tocoo()
+    bad[3][np.nonzero(A.row == A.col)[0][7]] = -1.0
+    with pytest.raises(FetiError) as e:
+        ctx.factor_upload(bad)
+    assert e.value.status == 5   # FETIF_ENOTSPD
+    with pytest.raises(FetiError) as e:
+        ctx.assemble()
+    assert e.value.status == 3   # FETIF_ESTATE
+    with pytest.raises(FetiError) as e:
+        gpu_apply(ctx, prob.lam)
+    assert e.value.status == 3
+    upload_and_assemble(ctx, prob)
+    Fs = [oracle_F(prob, i) for i in range(prob.nsub)]
+    q_o = feti.apply_explicit(Fs, [s.dual_map for s in prob.subs], prob.lam, prob.n_lambda)
+    q_g = gpu_apply(ctx, prob.lam)
+    assert np.linalg.norm(q_g - q_o) <= 1e-12 * np.linalg.norm(q_o)
+    ctx.close()
