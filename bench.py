@@ -125,6 +125,7 @@ def main():
     solver = []
     pcpg_events = []
     tune = None
+    atune = None
 
     def step():
         th = time.time()
@@ -150,7 +151,11 @@ def main():
             torch.cuda.synchronize()
             log(f"warmup step {w} done: solver {solver[-1]}")
             if w == 0 and not args.no_tune:
-                from paper_2502_08382_amd.autotune import tune_apply
+                from paper_2502_08382_amd.autotune import tune_apply, tune_assembly
+                tt = time.time()
+                atune = tune_assembly(ctx, stream=stream)
+                log(f"assembly autotune {time.time() - tt:.1f}s: TRSM panel={atune['panel']} "
+                    f"chunk={atune['chunk']} ({atune['trsm_ms']:.3f} ms)")
                 tt = time.time()
                 tune = tune_apply(ctx, lam, q, stream=stream, cache=None if args.retune else tune_cache)
                 log(f"apply autotune {time.time() - tt:.1f}s{' (stored)' if tune.get('cached') else ''}: "
@@ -198,6 +203,12 @@ def main():
     log(f"apply alone: eager {t_apply_eager * 1e3:.1f} us, graph replay {t_apply_graph * 1e3:.1f} us, "
         f"graph result bitwise equal to eager: {graph_same}")
     del graph
+    # the same PCPG solve with its iterations captured in HIP graphs and replayed
+    t_pcpg_graph = None
+    if not refine:
+        ctx.profile(False)
+        t_pcpg_graph = event_time(lambda: ctx.pcpg(d, e, sol, fixed_iters=args.iters, use_graph=True, stream=stream), 2)
+        log(f"PCPG with graph-replayed iterations: {t_pcpg_graph:.3f} ms for {args.iters} iterations")
     t_backward = None
     if args.backward:
         g_d = torch.tensor(prob.mu, dtype=torch.float64, device=dev)
@@ -260,6 +271,7 @@ def main():
         "apply_gather_ms": round(t_gather, 4),
         "factor_copy_ms": round(t_upload, 3),
         "apply_shape": None if tune is None else {k: tune[k] for k in ("split", "band", "rows", "nontemporal")},
+        "trsm_shape": None if atune is None else {k: atune[k] for k in ("panel", "chunk")},
         "host_factor_s": round(float(np.mean(host_factor_s)), 3) if host_factor_s else None,
         "roofline": {"bound": "hbm", "kernel": "apply_band_kernel", "achieved": round(band_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(band_gbs / HBM_PEAK_GBS, 4),
@@ -277,6 +289,8 @@ def main():
     # solver time: HIP events around the PCPG call on its stream
     t_solve_ms = float(np.mean([a.elapsed_time(b) for a, b in pcpg_events]))
     result["solver"]["ms"] = round(t_solve_ms, 3)
+    if t_pcpg_graph is not None:
+        result["solver"]["hip_graph_ms_per_iter"] = round(t_pcpg_graph / max(1, args.iters), 4)
     result["solver"]["ms_per_iter"] = round(t_solve_ms / max(1, solver[-1]["iters"]), 4)
     result["solves_with_factors_ms"] = round(ms["solves"] / K, 3)
 

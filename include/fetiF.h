@@ -155,6 +155,14 @@ fetiF_status fetiF_apply(fetiF_ctx ctx, const double* lambda_d, double* q_d, voi
 fetiF_status fetiF_set_apply(fetiF_ctx ctx, int32_t band_elems, int32_t rows, int32_t nontemporal,
                              int32_t split);
 
+/* Re-plan the assembly TRSM (tuning hook): trsm_panel (a multiple of 16 in
+ * [16, 1280]; 0 keeps) the most supernode columns per panel, trsm_chunk
+ * (16, 32 or 64; 0 keeps) the most RHS columns per work-group.  Synchronises
+ * the device; the assembled operator stays valid (the next fetiF_assemble
+ * uses the new schedule).  The result of fetiF_assemble does not depend on
+ * these up to summation order. */
+fetiF_status fetiF_set_assembly(fetiF_ctx ctx, int32_t trsm_panel, int32_t trsm_chunk);
+
 /* Reverse mode of J = g^T F(theta) lambda for the applied operator:
  *   dlambda_d = F g_d   (F is symmetric),
  *   dtheta_d[e] = -u_g|_e^T dK_e u_lambda|_e  for every element of every

@@ -85,3 +85,28 @@ def tune_apply(ctx, lam, q, bands=None, rows=(2, 4), nontemporal=(1,), splits=(0
         with open(cache, "w") as f:
             json.dump(data, f, indent=1)
     return out
+
+
+def tune_assembly(ctx, panels=(32, 48, 64, 96), chunks=(32, 64), reps=3, stream=None, verbose=False):
+    """Try every (TRSM panel width, RHS columns per work-group) shape of the
+    assembly; install and return the fastest by the TRSM phase time.  The
+    context must hold uploaded factors (it is assembled once per trial)."""
+    import torch
+    trials = []
+    for p, c in itertools.product(panels, chunks):
+        ctx.set_assembly(p, c)
+        ctx.assemble(stream=stream)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
+        for _ in range(reps):
+            ctx.assemble(stream=stream)
+        ctx.profile(False)
+        prof = ctx.profile_read(reset=True)
+        t = prof["trsm"][0] / max(1, prof["trsm"][1])
+        trials.append(dict(panel=p, chunk=c, trsm_ms=t))
+        if verbose:
+            print(f"[autotune] trsm panel={p} chunk={c}: {t:.3f} ms", flush=True)
+    best = min(trials, key=lambda d: d["trsm_ms"])
+    ctx.set_assembly(best["panel"], best["chunk"])
+    return dict(best, trials=trials)

@@ -259,6 +259,147 @@ hipError_t install_apply(fetiF_ctx c, const ApplyPlan& A)
 
 }  // namespace
 
+// ======================================================================== TRSM plan
+
+namespace {
+
+struct TrsmPlan {
+    std::vector<DevSN> tsns;        // column panels
+    std::vector<int64_t> troff;     // X offset minus range start of every panel below row
+    std::vector<TrsmItem> items;    // all levels, level by level
+    std::vector<int64_t> level_off;
+    std::vector<int32_t> level_waves, level_maxns;
+};
+
+// TRSM schedule.  Every supernode with RHS columns is cut into column panels
+// of at most `panel` columns (a multiple of 16): panel k starts at diagonal
+// offset o = k * panel of the same storage, and the supernode's columns after
+// the panel count among its below rows, so the panel's update of them is an
+// ordinary below-row update.  Panel levels: panel k of a supernode runs one
+// level after panel k - 1, and its first panel one level after the last
+// panel of every child.  Two panels of one level then never belong to an
+// ancestor and a descendant, so they own disjoint RHS column ranges and
+// write disjoint entries of X.  A work-group has W wavefronts of 16 RHS
+// columns each (W = chunk / 16, shrunk when the solved blocks, W *
+// ceil(ncols/16) * 2 KiB of LDS, would not fit).
+bool plan_trsm(fetiF_ctx c, int32_t panel, int32_t chunk, TrsmPlan& T)
+{
+    std::vector<int32_t> tlevel;
+    int32_t tmaxlev = 0;
+    for (int32_t i = 0; i < c->nsub; ++i) {
+        const SubPlan& P = c->subs[i];
+        const Symbolic& S = P.sym;
+        const int32_t nsn = (int32_t)S.sn.size();
+        std::vector<int32_t> next_level(nsn, 0);   // first level free above each supernode's panels
+        for (int32_t s = 0; s < nsn; ++s) {        // postorder: children before parents
+            const Supernode& x = S.sn[s];
+            const DevSN& d = c->hSN[P.snbase + s];
+            int32_t L = next_level[s];
+            if (P.w[s] > 0) {
+                for (int32_t o = 0; o < x.ncols; o += panel) {
+                    const int32_t cw = std::min(panel, x.ncols - o);
+                    DevSN t = d;
+                    t.lval = d.lval + (int64_t)o * d.ld + o;
+                    t.linv = d.linv + (int64_t)(o / 16) * 256;
+                    t.xoff = d.xoff + (int64_t)o * P.w[s];
+                    t.rowsoff = (int64_t)T.troff.size();
+                    t.first = x.first + o;
+                    t.ncols = cw;
+                    t.nrows = x.ncols - o - cw + x.nrows;
+                    for (int32_t k = o + cw; k < x.ncols; ++k) T.troff.push_back(c->hRowOff[P.rowbase + x.first + k]);
+                    for (int32_t k = 0; k < x.nrows; ++k)
+                        T.troff.push_back(c->hRowOff[P.rowbase + S.rows[x.row_off + k]]);
+                    T.tsns.push_back(t);
+                    tlevel.push_back(L++);
+                }
+            }
+            if (x.parent >= 0) next_level[x.parent] = std::max(next_level[x.parent], L);
+            tmaxlev = std::max(tmaxlev, L - 1);
+        }
+    }
+    std::vector<std::vector<TrsmItem>> lv(tmaxlev + 1);
+    T.level_maxns.assign(tmaxlev + 1, 0);
+    T.level_waves.assign(tmaxlev + 1, 4);
+    for (size_t t = 0; t < T.tsns.size(); ++t)
+        T.level_maxns[tlevel[t]] = std::max(T.level_maxns[tlevel[t]], T.tsns[t].ncols);
+    const int32_t wmax = std::max(1, std::min(4, chunk / 16));
+    for (int32_t L = 0; L <= tmaxlev; ++L) {
+        const int32_t mx = std::max(1, T.level_maxns[L]);
+        int32_t W = wmax;
+        while (W > 1 && trsm_lds_bytes(W, mx) > 65536) W /= 2;
+        if (trsm_lds_bytes(W, mx) > 160 * 1024) return false;
+        T.level_waves[L] = W;
+    }
+    for (size_t t = 0; t < T.tsns.size(); ++t) {
+        const int32_t L = tlevel[t];
+        const int32_t slot = 16 * T.level_waves[L];
+        for (int32_t c0 = 0; c0 < T.tsns[t].w; c0 += slot) {
+            TrsmItem it;
+            it.sn = (int32_t)t;
+            it.c0 = c0;
+            it.cw = std::min(slot, T.tsns[t].w - c0);
+            it.pad = 0;
+            lv[L].push_back(it);
+        }
+    }
+    T.level_off.assign(tmaxlev + 2, 0);
+    for (int32_t L = 0; L <= tmaxlev; ++L) {
+        auto& v = lv[L];
+        // larger panels first
+        std::stable_sort(v.begin(), v.end(), [&](const TrsmItem& a, const TrsmItem& b) {
+            const DevSN& x = T.tsns[a.sn];
+            const DevSN& y = T.tsns[b.sn];
+            return (int64_t)x.ncols * (x.ncols + 2 * x.nrows) > (int64_t)y.ncols * (y.ncols + 2 * y.nrows);
+        });
+        T.level_off[L] = (int64_t)T.items.size();
+        T.items.insert(T.items.end(), v.begin(), v.end());
+    }
+    T.level_off[tmaxlev + 1] = (int64_t)T.items.size();
+    return true;
+}
+
+void free_trsm(fetiF_ctx c)
+{
+    for (void* p : c->trsm_allocs) (void)hipFree(p);
+    c->trsm_allocs.clear();
+    c->dTSN = nullptr;
+    c->dTRowOff = nullptr;
+    c->dItems = nullptr;
+}
+
+template <typename T>
+hipError_t talloc(fetiF_ctx c, T** p, size_t count)
+{
+    *p = nullptr;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(T) * std::max<size_t>(1, count));
+    if (e == hipSuccess) {
+        c->trsm_allocs.push_back(q);
+        *p = (T*)q;
+    }
+    return e;
+}
+
+// Device copies of a TRSM plan (replacing the previous one).
+hipError_t install_trsm(fetiF_ctx c, const TrsmPlan& T)
+{
+    free_trsm(c);
+    hipError_t e;
+    if ((e = talloc(c, &c->dTSN, T.tsns.size())) != hipSuccess) return e;
+    if ((e = talloc(c, &c->dTRowOff, T.troff.size())) != hipSuccess) return e;
+    if ((e = talloc(c, &c->dItems, T.items.size())) != hipSuccess) return e;
+    if ((e = upload(c->dTSN, T.tsns)) != hipSuccess) return e;
+    if ((e = upload(c->dTRowOff, T.troff)) != hipSuccess) return e;
+    if ((e = upload(c->dItems, T.items)) != hipSuccess) return e;
+    c->level_off = T.level_off;
+    c->level_waves = T.level_waves;
+    c->level_maxns = T.level_maxns;
+    c->trsm_levels = (int32_t)T.level_waves.size();
+    return hipSuccess;
+}
+
+}  // namespace
+
 // ======================================================================== create
 
 extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambda, int32_t nsub,
@@ -411,96 +552,15 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         }
         c->apply_nch = nch;
     }
-    // TRSM schedule.  Every supernode with RHS columns is cut into column
-    // panels of at most trsm_panel columns (a multiple of 16): panel k starts
-    // at diagonal offset o = k * trsm_panel of the same storage, and the
-    // supernode's columns after the panel count among its below rows, so the
-    // panel's update of them is an ordinary below-row update.  Panel levels:
-    // panel k of a supernode runs one level after panel k - 1, and its first
-    // panel one level after the last panel of every child.  Two panels of one
-    // level then never belong to an ancestor and a descendant, so they own
-    // disjoint RHS column ranges and write disjoint entries of X.  A
-    // work-group has W wavefronts of 16 RHS columns each; W shrinks when the
-    // solved blocks (W * ceil(ncols/16) * 2 KiB of LDS) would not fit.
-    std::vector<DevSN> tsns;
-    std::vector<int32_t> trows;
-    std::vector<int32_t> tlevel;
-    int32_t tmaxlev = 0;
-    {
-        const int32_t PW = opt.trsm_panel;
-        for (int32_t i = 0; i < nsub; ++i) {
-            const SubPlan& P = c->subs[i];
-            const Symbolic& S = P.sym;
-            const int32_t nsn = (int32_t)S.sn.size();
-            std::vector<int32_t> next_level(nsn, 0);   // first level free above each supernode's panels
-            for (int32_t s = 0; s < nsn; ++s) {        // postorder: children before parents
-                const Supernode& x = S.sn[s];
-                const DevSN& d = sns[P.snbase + s];
-                int32_t L = next_level[s];
-                if (P.w[s] > 0) {
-                    for (int32_t o = 0; o < x.ncols; o += PW) {
-                        const int32_t cw = std::min(PW, x.ncols - o);
-                        DevSN t = d;
-                        t.lval = d.lval + (int64_t)o * d.ld + o;
-                        t.linv = d.linv + (int64_t)(o / 16) * 256;
-                        t.xoff = d.xoff + (int64_t)o * P.w[s];
-                        t.rowsoff = (int64_t)trows.size();
-                        t.first = x.first + o;
-                        t.ncols = cw;
-                        t.nrows = x.ncols - o - cw + x.nrows;
-                        for (int32_t k = o + cw; k < x.ncols; ++k) trows.push_back(x.first + k);
-                        trows.insert(trows.end(), S.rows.begin() + x.row_off, S.rows.begin() + x.row_off + x.nrows);
-                        tsns.push_back(t);
-                        tlevel.push_back(L++);
-                    }
-                }
-                if (x.parent >= 0) next_level[x.parent] = std::max(next_level[x.parent], L);
-                tmaxlev = std::max(tmaxlev, L - 1);
-            }
-        }
+    // host copies the TRSM planner needs again when it re-plans
+    c->hSN = sns;
+    c->hRowOff.resize(xrows.size());
+    for (size_t r = 0; r < xrows.size(); ++r) c->hRowOff[r] = xrows[r].off - xrows[r].j0;
+    TrsmPlan tplan;
+    if (!plan_trsm(c, opt.trsm_panel, opt.trsm_chunk, tplan)) {
+        delete c;
+        return fail(nullptr, FETIF_ENOTSUP, "a TRSM panel has more than 1280 columns");
     }
-    c->level_items.assign(tmaxlev + 1, {});
-    c->level_maxns.assign(tmaxlev + 1, 0);
-    c->level_waves.assign(tmaxlev + 1, 4);
-    for (size_t t = 0; t < tsns.size(); ++t)
-        c->level_maxns[tlevel[t]] = std::max(c->level_maxns[tlevel[t]], tsns[t].ncols);
-    const int32_t wmax = std::max(1, std::min(4, opt.trsm_chunk / 16));
-    for (int32_t L = 0; L <= tmaxlev; ++L) {
-        int32_t mx = std::max(1, c->level_maxns[L]);
-        int32_t W = wmax;
-        while (W > 1 && trsm_lds_bytes(W, mx) > 65536) W /= 2;
-        if (trsm_lds_bytes(W, mx) > 160 * 1024) {
-            delete c;
-            return fail(nullptr, FETIF_ENOTSUP, "a TRSM panel has more than 1280 columns");
-        }
-        c->level_waves[L] = W;
-    }
-    for (size_t t = 0; t < tsns.size(); ++t) {
-        const int32_t L = tlevel[t];
-        const int32_t slot = 16 * c->level_waves[L];
-        for (int32_t c0 = 0; c0 < tsns[t].w; c0 += slot) {
-            TrsmItem it;
-            it.sn = (int32_t)t;
-            it.c0 = c0;
-            it.cw = std::min(slot, tsns[t].w - c0);
-            it.pad = 0;
-            c->level_items[L].push_back(it);
-        }
-    }
-    std::vector<TrsmItem> all_items;
-    c->level_off.assign(tmaxlev + 2, 0);
-    for (int32_t L = 0; L <= tmaxlev; ++L) {
-        auto& v = c->level_items[L];
-        // larger panels first
-        std::stable_sort(v.begin(), v.end(), [&](const TrsmItem& a, const TrsmItem& b) {
-            const DevSN& x = tsns[a.sn];
-            const DevSN& y = tsns[b.sn];
-            return (int64_t)x.ncols * (x.ncols + 2 * x.nrows) > (int64_t)y.ncols * (y.ncols + 2 * y.nrows);
-        });
-        c->level_off[L] = (int64_t)all_items.size();
-        all_items.insert(all_items.end(), v.begin(), v.end());
-    }
-    c->level_off[tmaxlev + 1] = (int64_t)all_items.size();
     // SYRK tiles: most expensive first
     {
         std::vector<int64_t> cost(tiles.size());
@@ -710,6 +770,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         for (void* p : c->allocations) (void)hipFree(p);
         c->allocations.clear();
         free_apply(c);
+        free_trsm(c);
         if (c->hStage) (void)hipHostFree(c->hStage);
         delete c;
         return st;
@@ -788,21 +849,16 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     }
     CK(dalloc(c, &c->dSN, sns.size()));
     CK(dalloc(c, &c->dRows, rows.size()));
-    CK(dalloc(c, &c->dTSN, tsns.size()));
-    CK(dalloc(c, &c->dTRows, trows.size()));
     CK(dalloc(c, &c->dXRows, xrows.size()));
     CK(dalloc(c, &c->dUnits, units.size()));
-    CK(dalloc(c, &c->dItems, all_items.size()));
     CK(dalloc(c, &c->dTiles, tiles.size()));
     CK(dalloc(c, &c->dLists, lists.size()));
     CK(dalloc(c, &c->dDmap, dmap.size()));
     CK(upload(c->dSN, sns));
     CK(upload(c->dRows, rows));
-    CK(upload(c->dTSN, tsns));
-    CK(upload(c->dTRows, trows));
     CK(upload(c->dXRows, xrows));
     CK(upload(c->dUnits, units));
-    CK(upload(c->dItems, all_items));
+    CK(install_trsm(c, tplan));
     CK(upload(c->dTiles, tiles));
     CK(upload(c->dLists, lists));
     CK(upload(c->dDmap, dmap));
@@ -905,10 +961,10 @@ extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
     HIPCHK(c, launch_rhs_units(c->dUnits, c->sum_m, c->dX, st));
     HIPCHK(c, t1.stop());
     PhaseTimer t2(c, st, 2);
-    for (size_t L = 0; L < c->level_items.size(); ++L) {
+    for (int32_t L = 0; L < c->trsm_levels; ++L) {
         int32_t cnt = (int32_t)(c->level_off[L + 1] - c->level_off[L]);
         HIPCHK(c, launch_trsm_level(c->dItems + c->level_off[L], cnt, c->level_waves[L], c->level_maxns[L], c->dTSN,
-                                    c->dL, c->dLinv, c->dTRows, c->dXRows, c->dX, st));
+                                    c->dL, c->dLinv, c->dTRowOff, c->dX, st));
     }
     HIPCHK(c, t2.stop());
     PhaseTimer t3(c, st, 3);
@@ -937,6 +993,27 @@ extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double*
     PhaseTimer t5(c, st, 5);
     HIPCHK(c, launch_gather(c->prec, c->n_lambda, c->dGptr, c->dGent, c->dBandZ, c->dZ, q_d, st));
     HIPCHK(c, t5.stop());
+    return FETIF_OK;
+}
+
+extern "C" fetiF_status fetiF_set_assembly(fetiF_ctx c, int32_t trsm_panel, int32_t trsm_chunk)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (trsm_panel < 0 || trsm_panel > 1280 || trsm_panel % 16 != 0 ||
+        (trsm_chunk != 0 && trsm_chunk != 16 && trsm_chunk != 32 && trsm_chunk != 64))
+        return fail(c, FETIF_EINVAL, "trsm_panel a multiple of 16 in [16, 1280] (0 keeps), trsm_chunk in {0,16,32,64}");
+    const int32_t np = trsm_panel > 0 ? trsm_panel : c->opt.trsm_panel;
+    const int32_t nc = trsm_chunk > 0 ? trsm_chunk : c->opt.trsm_chunk;
+    if (np == c->opt.trsm_panel && nc == c->opt.trsm_chunk) return FETIF_OK;
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    TrsmPlan T;
+    if (!plan_trsm(c, np, nc, T)) return fail(c, FETIF_ENOTSUP, "a TRSM panel has more than 1280 columns");
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, install_trsm(c, T));
+    c->opt.trsm_panel = np;
+    c->opt.trsm_chunk = nc;
     return FETIF_OK;
 }
 
@@ -1120,7 +1197,7 @@ extern "C" fetiF_status fetiF_query(fetiF_ctx c, fetiF_info* info)
     info->trsm_flops = c->trsm_flops;
     info->syrk_flops = c->syrk_flops;
     info->factor_flops = c->factor_flops;
-    info->trsm_levels = (int32_t)c->level_items.size();
+    info->trsm_levels = c->trsm_levels;
     info->apply_groups = c->ngroups;
     {
         const int V = prec_vec(c->prec);

@@ -85,8 +85,11 @@ struct fetiF_ctx_s {
     int nthreads = 1;
     std::vector<SubPlan> subs;
     // schedules
-    std::vector<std::vector<TrsmItem>> level_items;
+    // TRSM schedule (per panel level: wavefronts per work-group, widest panel)
+    int32_t trsm_levels = 0;
     std::vector<int32_t> level_waves, level_maxns;
+    std::vector<DevSN> hSN;          // host copy of the supernode table (TRSM re-planning)
+    std::vector<int64_t> hRowOff;    // per global row slot: X offset minus its range start
     int32_t ninv = 0;
     int64_t total_linv = 0;
     // batched solves with L: levels of all supernodes, tree tables
@@ -128,7 +131,7 @@ struct fetiF_ctx_s {
     DevSN* dSN = nullptr;
     int32_t* dRows = nullptr;
     DevSN* dTSN = nullptr;     // TRSM column panels
-    int32_t* dTRows = nullptr; // their below-row lists
+    int64_t* dTRowOff = nullptr; // X offset (minus range start) of their below rows
     XRow* dXRows = nullptr;
     RhsUnit* dUnits = nullptr;
     TrsmItem* dItems = nullptr;
@@ -146,6 +149,7 @@ struct fetiF_ctx_s {
     bool upload_pending = false;
     std::vector<void*> allocations;
     std::vector<void*> apply_allocs;  // buffers of the current apply plan
+    std::vector<void*> trsm_allocs;   // buffers of the current TRSM plan
     // phase timing
     struct Rec {
         int phase;

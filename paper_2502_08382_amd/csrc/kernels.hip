@@ -177,79 +177,99 @@ __global__ __launch_bounds__(NT) void diag_inverse_kernel(const InvItem* __restr
     for (int i = 0; i < 16; ++i) out[i] = x[i];
 }
 
-// One work-group solves one RHS column chunk of one supernode s; each of its
-// W wavefronts owns 16 columns and works alone (no barriers):
-//   for each 16-row block rb:  acc = X[rb] - sum_{kb<rb} L[rb,kb] X[kb]
-//                              X[rb] = inv(L[rb,rb]) acc          (MFMA)
-//   for each 16-row block of rows(s):  X[rows] -= L[rows, s] X_s   (MFMA)
-// The solved blocks stay in wave-private LDS in B-operand order.  Items of
-// one level touch disjoint RHS column ranges, so the updates need no atomics.
-__global__ void trsm_level_kernel(const TrsmItem* __restrict__ items, int32_t nbmax,
+// One work-group solves one RHS column chunk (up to 16 W columns) of one
+// supernode panel s, in two phases:
+//  1. each of its W wavefronts owns 16 columns and, alone,
+//       for each 16-row block rb:  acc = X[rb] - sum_{kb<rb} L[rb,kb] X[kb]
+//                                  X[rb] = inv(L[rb,rb]) acc          (MFMA)
+//     keeping the solved blocks in LDS in B-operand order;
+//  2. after a barrier the below rows are split by 16-row blocks over the
+//     wavefronts; each computes X[rows] -= L[rows, s] X_s for all of the
+//     chunk's columns, so every loaded L operand feeds one MFMA per 16-column
+//     block (independent accumulator chains) and is read once per work-group.
+// rowoff[i] is the X offset of below row i minus the first RHS column of its
+// range.  Items of one level touch disjoint RHS column ranges, so the
+// updates need no atomics.
+template <int W>
+__global__ __launch_bounds__(64 * W) void trsm_level_kernel(const TrsmItem* __restrict__ items, int32_t nbmax,
                                   const DevSN* __restrict__ sns, const double* __restrict__ L,
-                                  const double* __restrict__ Linv, const int32_t* __restrict__ rows,
-                                  const XRow* __restrict__ xrows, double* __restrict__ X)
+                                  const double* __restrict__ Linv, const int64_t* __restrict__ rowoff,
+                                  double* __restrict__ X)
 {
     extern __shared__ double smem[];
     const TrsmItem it = items[blockIdx.x];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int q = lane >> 4, j = lane & 15;
-    const int cbeg = wv * 16;
-    if (cbeg >= it.cw) return;  // this wavefront has no columns
     const DevSN s = sns[it.sn];
     const int ns = s.ncols, nr = s.nrows, d = s.ld;
     const int nb = (ns + 15) >> 4;
-    const int col = it.c0 + cbeg + j;             // column relative to j0
-    const bool cv = (cbeg + j) < it.cw;
     const double* __restrict__ P = L + s.lval;
-    const double* __restrict__ PI = Linv + s.linv;
+    double* __restrict__ sx0 = smem;                     // [W][nbmax * 4][64]
     double* __restrict__ sx = smem + (size_t)wv * nbmax * 256;
-    double* __restrict__ xs = X + s.xoff + col;   // X_s[row][col] = xs[row * w]
-    for (int rb = 0; rb < nb; ++rb) {
-        d4 acc;
+    const int cbeg = wv * 16;
+    if (cbeg < it.cw) {
+        const int col = it.c0 + cbeg + j;                // column relative to j0
+        const bool cv = (cbeg + j) < it.cw;
+        const double* __restrict__ PI = Linv + s.linv;
+        double* __restrict__ xs = X + s.xoff + col;      // X_s[row][col] = xs[row * w]
+        for (int rb = 0; rb < nb; ++rb) {
+            d4 acc;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = rb * 16 + q + 4 * r;
-            acc[r] = (cv && row < ns) ? xs[(int64_t)row * s.w] : 0.0;
-        }
-        const int arow = rb * 16 + j;
-        const bool av = arow < ns;
-        for (int kb = 0; kb < rb; ++kb) {
+            for (int r = 0; r < 4; ++r) {
+                const int row = rb * 16 + q + 4 * r;
+                acc[r] = (cv && row < ns) ? xs[(int64_t)row * s.w] : 0.0;
+            }
+            const int arow = rb * 16 + j;
+            const bool av = arow < ns;
+            for (int kb = 0; kb < rb; ++kb) {
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int kc = kb * 16 + 4 * kk + q;
-                const double a = av ? -P[(int64_t)kc * d + arow] : 0.0;
-                acc = mfma16(a, sx[(kb * 4 + kk) * 64 + lane], acc);
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int kc = kb * 16 + 4 * kk + q;
+                    const double a = av ? -P[(int64_t)kc * d + arow] : 0.0;
+                    acc = mfma16(a, sx[(kb * 4 + kk) * 64 + lane], acc);
+                }
+            }
+            d4 xn = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) xn = mfma16(PI[rb * 256 + (4 * kk + q) * 16 + j], acc[kk], xn);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                sx[(rb * 4 + r) * 64 + lane] = xn[r];
+                const int row = rb * 16 + q + 4 * r;
+                if (cv && row < ns) xs[(int64_t)row * s.w] = xn[r];
             }
         }
-        d4 xn = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) xn = mfma16(PI[rb * 256 + (4 * kk + q) * 16 + j], acc[kk], xn);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            sx[(rb * 4 + r) * 64 + lane] = xn[r];
-            const int row = rb * 16 + q + 4 * r;
-            if (cv && row < ns) xs[(int64_t)row * s.w] = xn[r];
-        }
+    } else {
+        // no columns: a zero block, so phase 2 may multiply every block
+        for (int idx = lane; idx < nb * 256; idx += 64) sx[idx] = 0.0;
     }
-    const int jglob = s.j0 + col;
-    for (int rb = 0; rb * 16 < nr; ++rb) {
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+    const int64_t jbase = (int64_t)s.j0 + it.c0;
+    for (int rb = wv; rb * 16 < nr; rb += W) {
+        d4 acc[W];
+#pragma unroll
+        for (int c = 0; c < W; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
         const int arow = ns + rb * 16 + j;
         const bool av = arow < ns + nr;
+#pragma unroll 1
         for (int kb = 0; kb < nb; ++kb) {
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
                 const int kc = kb * 16 + 4 * kk + q;
                 const double a = (av && kc < ns) ? P[(int64_t)kc * d + arow] : 0.0;
-                acc = mfma16(a, sx[(kb * 4 + kk) * 64 + lane], acc);
+#pragma unroll
+                for (int c = 0; c < W; ++c)
+                    acc[c] = mfma16(a, sx0[((size_t)c * nbmax * 4 + kb * 4 + kk) * 64 + lane], acc[c]);
             }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = rb * 16 + q + 4 * r;
-            if (cv && i < nr) {
-                const XRow xr = xrows[s.rowbase + rows[s.rowsoff + i]];
-                X[xr.off + (jglob - xr.j0)] -= acc[r];
+            if (i < nr) {
+                double* __restrict__ xr = X + rowoff[s.rowsoff + i] + jbase;
+#pragma unroll
+                for (int c = 0; c < W; ++c)
+                    if (c * 16 + j < it.cw) xr[c * 16 + j] -= acc[c][r];
             }
         }
     }
@@ -813,19 +833,24 @@ hipError_t launch_diag_inverse(const InvItem* items, int32_t nitems, const DevSN
 }
 
 hipError_t launch_trsm_level(const TrsmItem* items, int32_t nitems, int32_t waves, int32_t max_ns,
-                             const DevSN* sns, const double* L, const double* Linv, const int32_t* rows,
-                             const XRow* xrows, double* X, hipStream_t st)
+                             const DevSN* sns, const double* L, const double* Linv, const int64_t* rowoff,
+                             double* X, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
     const size_t lds = trsm_lds_bytes(waves, max_ns);
+    const void* fn = waves == 4 ? (const void*)trsm_level_kernel<4>
+                   : waves == 2 ? (const void*)trsm_level_kernel<2> : (const void*)trsm_level_kernel<1>;
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)trsm_level_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     const int32_t nbmax = (max_ns + 15) / 16;
-    hipLaunchKernelGGL(trsm_level_kernel, dim3(nitems), dim3(64 * waves), lds, st, items, nbmax, sns, L, Linv,
-                       rows, xrows, X);
+    if (waves == 4)
+        hipLaunchKernelGGL(trsm_level_kernel<4>, dim3(nitems), dim3(256), lds, st, items, nbmax, sns, L, Linv, rowoff, X);
+    else if (waves == 2)
+        hipLaunchKernelGGL(trsm_level_kernel<2>, dim3(nitems), dim3(128), lds, st, items, nbmax, sns, L, Linv, rowoff, X);
+    else
+        hipLaunchKernelGGL(trsm_level_kernel<1>, dim3(nitems), dim3(64), lds, st, items, nbmax, sns, L, Linv, rowoff, X);
     return hipGetLastError();
 }
 

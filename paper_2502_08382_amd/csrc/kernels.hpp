@@ -21,8 +21,8 @@ hipError_t launch_diag_inverse(const InvItem* items, int32_t nitems, const DevSN
 // one etree level of the supernodal forward solve; waves = wavefronts per
 // work-group (each owns 16 RHS columns), max_ns = largest supernode of the level
 hipError_t launch_trsm_level(const TrsmItem* items, int32_t nitems, int32_t waves, int32_t max_ns,
-                             const DevSN* sns, const double* L, const double* Linv, const int32_t* rows,
-                             const XRow* xrows, double* X, hipStream_t st);
+                             const DevSN* sns, const double* L, const double* Linv, const int64_t* rowoff,
+                             double* X, hipStream_t st);
 // dynamic LDS bytes of a TRSM level launch
 inline size_t trsm_lds_bytes(int32_t waves, int32_t max_ns) { return (size_t)waves * ((max_ns + 15) / 16) * 2048; }
 // ---- batched supernodal solves with L (nrhs = 1 or 2, vectors interleaved:

@@ -73,7 +73,7 @@ EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply
            "fetiF_last_error", "fetiF_host_factor", "fetiF_hfactor_info", "fetiF_hfactor_export",
            "fetiF_hfactor_supernodes", "fetiF_hfactor_free", "fetiF_profile_enable",
            "fetiF_profile_read", "fetiF_set_apply", "fetiF_apply_implicit", "fetiF_dual_rhs",
-           "fetiF_coarse_rhs", "fetiF_pcpg", "fetiF_primal"]
+           "fetiF_coarse_rhs", "fetiF_pcpg", "fetiF_primal", "fetiF_set_assembly"]
 
 PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "solves"]
 
@@ -109,6 +109,7 @@ def load_library(path=None):
     L.fetiF_profile_enable.argtypes = [vp, ctypes.c_int]
     L.fetiF_profile_read.argtypes = [vp, ctypes.c_int, vp, vp, i32]
     L.fetiF_set_apply.argtypes = [vp, i32, i32, i32, i32]
+    L.fetiF_set_assembly.argtypes = [vp, i32, i32]
     L.fetiF_apply_implicit.argtypes = [vp, vp, vp, vp]
     L.fetiF_dual_rhs.argtypes = [vp, vp, vp, vp, vp]
     L.fetiF_coarse_rhs.argtypes = [vp, vp, vp, vp]
@@ -259,6 +260,10 @@ class FetiContext:
         """Re-plan the apply (band size in stored elements, rows per pass,
         load policy, work split: 0 bands per triangle, 1 equal shares)."""
         self._check(self.L.fetiF_set_apply(self.h, int(band_elems), int(rows), int(nontemporal), int(split)))
+
+    def set_assembly(self, trsm_panel=0, trsm_chunk=0):
+        """Re-plan the assembly TRSM (supernode columns per panel, RHS columns per work-group)."""
+        self._check(self.L.fetiF_set_assembly(self.h, int(trsm_panel), int(trsm_chunk)))
 
     def profile(self, on=True):
         """Record HIP events around every device phase (see PHASES)."""

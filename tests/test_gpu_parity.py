@@ -226,3 +226,29 @@ def test_failed_upload_invalidates_assembly(torch_cuda):
     q_g = gpu_apply(ctx, prob.lam)
     assert np.linalg.norm(q_g - q_o) <= 1e-12 * np.linalg.norm(q_o)
     ctx.close()
+
+
+def test_assembly_every_trsm_shape(torch_cuda):
+    """Every TRSM panel width and work-group width the assembly tuner may
+    pick assembles the same F~_i: against the oracle to the FP64 bound, and
+    between shapes to summation-order rounding."""
+    prob = make_problem(3, "elasticity", [[8, 7], [8, 8], [7, 8]], 0.3, dirichlet_axis=2, seed=5)
+    say("assembly shapes", "nsub", prob.nsub, "m", [s.m for s in prob.subs][:4])
+    ctx = make_context(prob)
+    ctx.factor_upload([s.Kreg.data for s in prob.subs])
+    ref = None
+    Fo = [oracle_F(prob, i) for i in (0, prob.nsub - 1)]
+    for panel in (16, 32, 48, 96, 1280):
+        for chunk in (16, 32, 64):
+            ctx.set_assembly(panel, chunk)
+            ctx.assemble()
+            torch_cuda.cuda.synchronize()
+            Fg = [ctx.download_F(i) for i in (0, prob.nsub - 1)]
+            e = max(rel_fro(a, b) for a, b in zip(Fg, Fo))
+            say(f"panel {panel} chunk {chunk}: levels {ctx.info()['trsm_levels']} vs oracle {e:.2e}")
+            assert e <= 1e-12
+            if ref is None:
+                ref = Fg
+            else:
+                assert max(rel_fro(a, b) for a, b in zip(Fg, ref)) <= 1e-14
+    ctx.close()
