@@ -106,7 +106,7 @@ struct ApplyPlan {
 // ascending subdomain order with the bands whose partials hold that row.
 void plan_apply(fetiF_ctx c, int32_t band_elems, int32_t split, ApplyPlan& A)
 {
-    const int V = prec_vec(c->prec);
+    const int V = prec_row_align(c->prec);
     band_elems = std::max(1, band_elems);
     int64_t total = 0;
     for (int32_t i = 0; i < c->nsub; ++i) total += packed_row_offset(c->subs[i].m, V);
@@ -435,7 +435,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
             return fail(nullptr, FETIF_EINVAL, msg);
         }
 
-    const int V = prec_vec(c->prec);
+    const int V = prec_vec(c->prec), RA = prec_row_align(c->prec);
     const int TS = 64;
     // ---- global placement and schedules
     std::vector<DevSN> sns;
@@ -508,7 +508,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         }
         // F storage and SYRK tiles
         P.fbase = fb;
-        const int64_t fel = packed_row_offset(P.m, V);
+        const int64_t fel = packed_row_offset(P.m, RA);
         const int32_t nt = (P.m + TS - 1) / TS;
         for (int32_t ta = 0; ta < nt; ++ta)
             for (int32_t tb = 0; tb <= ta; ++tb) {
@@ -1145,7 +1145,7 @@ extern "C" fetiF_status fetiF_download_F(fetiF_ctx c, int32_t sub, double* host_
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     const SubPlan& P = c->subs[sub];
-    const int V = prec_vec(c->prec), B = prec_bytes(c->prec);
+    const int V = prec_row_align(c->prec), B = prec_bytes(c->prec);
     const int64_t fel = packed_row_offset(P.m, V);
     std::vector<char> buf((size_t)fel * B + 16);
     HIPCHK(c, hipDeviceSynchronize());
@@ -1200,7 +1200,7 @@ extern "C" fetiF_status fetiF_query(fetiF_ctx c, fetiF_info* info)
     info->trsm_levels = c->trsm_levels;
     info->apply_groups = c->ngroups;
     {
-        const int V = prec_vec(c->prec);
+        const int V = prec_row_align(c->prec);
         int64_t tot = 0;
         for (const auto& P : c->subs) tot += packed_row_offset(P.m, V);
         info->apply_elements = tot;

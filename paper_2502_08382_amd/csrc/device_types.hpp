@@ -88,6 +88,11 @@ struct ElemRef {
     int64_t dk_off;   // into the dK table (edofs x edofs, row-major)
 };
 
+// Rows of a packed triangle F~_i start on 128-byte boundaries (the cache
+// line): no line holds parts of two rows, so work split by rows or by
+// 1 KiB chunks of a row never fetches a line twice.
+constexpr int kRowAlignBytes = 128;
+
 // Packed lower-triangle row offset with rows padded to multiples of V
 // elements: row r holds columns 0..r and starts at
 // V * (V*q*(q+1)/2 + s*(q+1)) where r = q*V + s.

@@ -568,7 +568,7 @@ __global__ __launch_bounds__(NT) void syrk_kernel(const SyrkTile* __restrict__ t
             acc[1][1] = mfma16(a1, b1, acc[1][1]);
         }
     }
-    constexpr int64_t V = 16 / sizeof(T);
+    constexpr int64_t V = kRowAlignBytes / sizeof(T);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -679,6 +679,7 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
 {
     using A = typename Acc<T>::type;
     constexpr int VEC = 16 / sizeof(T);
+    constexpr int RA = kRowAlignBytes / sizeof(T);   // row granularity of the packed layout
     constexpr int CH = 64 * VEC;          // columns per chunk
     constexpr int CAP = NCH * CH;
     constexpr int NH = (NCH + 1) / 2;     // chunks per wavefront of a pair
@@ -704,8 +705,8 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
 #pragma unroll
         for (int k = 0; k < ROWS; ++k) {
             // padded row r + k: bytes [row_start, row_start + row_bytes)
-            const int64_t row_start = packed_row_offset(r + k, VEC) * (int64_t)sizeof(T);
-            const int row_bytes = r + k < b.r1 ? (int)(VEC * ((r + k) / VEC + 1) * sizeof(T)) : 0;
+            const int64_t row_start = packed_row_offset(r + k, RA) * (int64_t)sizeof(T);
+            const int row_bytes = r + k < b.r1 ? (int)(RA * ((r + k) / RA + 1) * sizeof(T)) : 0;
 #pragma unroll
             for (int c2 = 0; c2 < NH; ++c2) {
                 const int ch = 2 * c2 + half;

@@ -63,5 +63,7 @@ hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* gptr, const 
 // elements per 16-byte vector for a storage precision
 inline int prec_vec(int prec) { return prec == 0 ? 2 : (prec == 1 ? 4 : 8); }
 inline int prec_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+// row granularity of the packed triangles (elements per 128-byte line)
+inline int prec_row_align(int prec) { return kRowAlignBytes / prec_bytes(prec); }
 
 }  // namespace fetif
