@@ -47,7 +47,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2, help="workload 1..5")
-    ap.add_argument("--iters", type=int, default=200, help="solver iterations per step (FP64)")
+    ap.add_argument("--iters", type=int, default=200,
+                    help="solver iterations per step (FP64); 0: run to --tol")
     ap.add_argument("--tol", type=float, default=1e-9, help="solver tolerance with --prec f32/bf16")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--cpu-sample", type=int, default=128, help="subdomains timed by the CPU oracle")
@@ -98,8 +99,8 @@ def main():
     tune_cache = os.path.join(ROOT, "paper_2502_08382_amd", "tuned_apply.json")
 
     def shape_key(t):
-        return (f"{CONFIGS[args.config]}|{args.prec}|split{t['split']}-band{t['band']}-rows{t['rows']}"
-                f"-nt{t['nontemporal']}")
+        return (f"{CONFIGS[args.config]}|{args.prec}|seg{t.get('seg', 0)}-split{t['split']}-band{t['band']}"
+                f"-rows{t['rows']}-nt{t['nontemporal']}")
 
     if args.pmc_apply:
         from paper_2502_08382_amd.autotune import tune_apply
@@ -140,7 +141,10 @@ def main():
             r = ctx.pcpg(d, e, sol, tol=args.tol, refine=True, inner_tol=1e-4 if args.prec == "f32" else 1e-2,
                          max_iters=20000, use_graph=False, stream=stream)
         else:
-            r = ctx.pcpg(d, e, sol, fixed_iters=args.iters, use_graph=False, stream=stream)
+            if args.iters > 0:
+                r = ctx.pcpg(d, e, sol, fixed_iters=args.iters, use_graph=False, stream=stream)
+            else:
+                r = ctx.pcpg(d, e, sol, tol=args.tol, max_iters=20000, use_graph=False, stream=stream)
         ev1.record(stream)
         pcpg_events.append((ev0, ev1))
         solver.append(r)
@@ -159,7 +163,7 @@ def main():
                 tt = time.time()
                 tune = tune_apply(ctx, lam, q, stream=stream, cache=None if args.retune else tune_cache)
                 log(f"apply autotune {time.time() - tt:.1f}s{' (stored)' if tune.get('cached') else ''}: "
-                    f"split={tune['split']} band={tune['band']} rows={tune['rows']} "
+                    f"seg={tune.get('seg', 0)} split={tune['split']} band={tune['band']} rows={tune['rows']} "
                     f"nontemporal={tune['nontemporal']} ({tune['ms'] * 1e3:.1f} us)")
         host_factor_s.clear()
         solver.clear()
@@ -205,7 +209,7 @@ def main():
     del graph
     # the same PCPG solve with its iterations captured in HIP graphs and replayed
     t_pcpg_graph = None
-    if not refine:
+    if not refine and args.iters > 0:
         ctx.profile(False)
         t_pcpg_graph = event_time(lambda: ctx.pcpg(d, e, sol, fixed_iters=args.iters, use_graph=True, stream=stream), 2)
         log(f"PCPG with graph-replayed iterations: {t_pcpg_graph:.3f} ms for {args.iters} iterations")
@@ -252,7 +256,7 @@ def main():
         "data": "synthetic (seeded structured-grid FETI problem)",
         "config": {"workload": CONFIGS[args.config], "subdomains": prob.nsub,
                    "dofs_per_subdomain": int(prob.subs[0].n), "n_lambda": int(prob.n_lambda),
-                   "sum_m": int(sum_m), "applies_per_step": args.iters, "f_storage": args.prec},
+                   "sum_m": int(sum_m), "applies_per_step": int(solver[-1]["iters"]), "f_storage": args.prec},
         "assembly_ms_per_1k_subdomains": round(1000.0 * t_asm / prob.nsub, 3),
         "assembly_ms": round(t_asm, 3),
         "assembly_phase_ms": {"rhs_init": round(ms["rhs_init"] / K, 4), "trsm": round(ms["trsm"] / K, 4),
@@ -270,7 +274,8 @@ def main():
         "apply_band_ms": round(t_band, 4),
         "apply_gather_ms": round(t_gather, 4),
         "factor_copy_ms": round(t_upload, 3),
-        "apply_shape": None if tune is None else {k: tune[k] for k in ("split", "band", "rows", "nontemporal")},
+        "apply_shape": None if tune is None else {k: tune.get(k, 0) for k in ("seg", "split", "band", "rows",
+                                                                                "nontemporal")},
         "trsm_shape": None if atune is None else {k: atune[k] for k in ("panel", "chunk")},
         "host_factor_s": round(float(np.mean(host_factor_s)), 3) if host_factor_s else None,
         "roofline": {"bound": "hbm", "kernel": "apply_band_kernel", "achieved": round(band_gbs, 1),
@@ -290,7 +295,7 @@ def main():
     t_solve_ms = float(np.mean([a.elapsed_time(b) for a, b in pcpg_events]))
     result["solver"]["ms"] = round(t_solve_ms, 3)
     if t_pcpg_graph is not None:
-        result["solver"]["hip_graph_ms_per_iter"] = round(t_pcpg_graph / max(1, args.iters), 4)
+        result["solver"]["hip_graph_ms_per_iter"] = round(t_pcpg_graph / args.iters, 4)
     result["solver"]["ms_per_iter"] = round(t_solve_ms / max(1, solver[-1]["iters"]), 4)
     result["solves_with_factors_ms"] = round(ms["solves"] / K, 3)
 

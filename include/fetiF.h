@@ -111,6 +111,9 @@ typedef struct {
     int32_t apply_split;  /* apply work split: 0 bands per triangle, largest first (default);
                              1 equal shares of all stored elements, one per work-group */
     int32_t trsm_panel;   /* most supernode columns per TRSM panel, a multiple of 16 (default 48) */
+    int32_t apply_seg;    /* apply kernel: 0 whole rows per wavefront pair; 4 or 8 column segments
+                             of that many 1 KiB chunks; other values: segments of 4 when a row
+                             holds more than 8 chunks, else whole rows (default) */
 } fetiF_options;
 
 /* Preparation (Alg. 2, "preparation"; Sec. IV-B "Preparation"): nested
@@ -150,10 +153,11 @@ fetiF_status fetiF_apply(fetiF_ctx ctx, const double* lambda_d, double* q_d, voi
  * elements of F~ per work-group (the band/gather tables are rebuilt, which
  * synchronises the device), rows (2 or 4; 0 keeps) the rows per pass of a
  * wavefront pair, nontemporal (0/1; -1 keeps) the load policy for F~, split
- * (0/1; -1 keeps) the work split of fetiF_options.apply_split.  The result of
+ * (0/1; -1 keeps) the work split of fetiF_options.apply_split, seg (0, 4 or
+ * 8; -1 keeps) the kernel of fetiF_options.apply_seg.  The result of
  * fetiF_apply does not depend on these up to summation order. */
 fetiF_status fetiF_set_apply(fetiF_ctx ctx, int32_t band_elems, int32_t rows, int32_t nontemporal,
-                             int32_t split);
+                             int32_t split, int32_t seg);
 
 /* Re-plan the assembly TRSM (tuning hook): trsm_panel (a multiple of 16 in
  * [16, 1280]; 0 keeps) the most supernode columns per panel, trsm_chunk
@@ -200,11 +204,17 @@ typedef struct {
     int32_t max_iters;   /* default 1000 */
     int32_t fixed_iters; /* > 0: run exactly this many iterations */
     int32_t implicit;    /* 1: apply F implicitly with the factors; 0: assembled F~ */
-    int32_t check_every; /* iterations between convergence checks (default 10) */
+    int32_t check_every; /* iterations between convergence checks (default 10);
+                            a check also stops the solve when w^T y is not
+                            finite or exceeds 1e8 times its start value */
     int32_t refine;      /* 1: FP64 iterative refinement around the assembled
                             (FP32/BF16) operator: outer true residual
                             P(d - F lambda) with the implicit FP64 operator,
-                            inner PCPG on the correction to inner_tol */
+                            inner PCPG on the correction to inner_tol (at most
+                            2000 iterations each); a correction that does not
+                            lower the true residual is taken back and the
+                            refinement stops (rel_residual then says how far
+                            it got) */
     double inner_tol;    /* relative tolerance of each inner solve (default 1e-4) */
     int32_t use_graph;   /* 1: replay captured iterations (needs a non-NULL stream) */
 } fetiF_pcpg_options;

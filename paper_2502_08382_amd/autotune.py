@@ -42,13 +42,14 @@ def group_candidates(ctx, per_cu=(2, 3, 4, 6, 8, 12)):
     return tuple(max(1, -(-total // (ncu * k))) for k in per_cu)
 
 
-def tune_apply(ctx, lam, q, bands=None, rows=(2, 4), nontemporal=(1,), splits=(0, 1), reps=20,
+def tune_apply(ctx, lam, q, bands=None, rows=(2, 4), nontemporal=(1,), splits=(0, 1), segs=(0, 4, 8), reps=20,
                stream=None, cache=None, verbose=False):
-    """Try every (split, band, rows, nontemporal) shape; install and return
-    the best.  bands: candidate elements per work-group (default:
-    group_candidates).
+    """Try every (kernel, split, band, rows, nontemporal) shape; install and
+    return the best.  bands: candidate elements per work-group (default:
+    group_candidates); segs: 0 the whole-row kernel, 4/8 the column-segmented
+    kernel with that many chunks per segment.
 
-    Returns dict(band=..., rows=..., nontemporal=..., split=..., ms=..., trials=[...])."""
+    Returns dict(band=..., rows=..., nontemporal=..., split=..., seg=..., ms=..., trials=[...])."""
     if bands is None:
         bands = group_candidates(ctx)
     sig = signature(ctx)
@@ -57,22 +58,24 @@ def tune_apply(ctx, lam, q, bands=None, rows=(2, 4), nontemporal=(1,), splits=(0
             with open(cache) as f:
                 hit = json.load(f).get(sig)
             if hit:
-                ctx.set_apply(hit["band"], hit["rows"], hit["nontemporal"], hit.get("split", 0))
+                ctx.set_apply(hit["band"], hit["rows"], hit["nontemporal"], hit.get("split", 0), hit.get("seg", 0))
                 return dict(hit, cached=True)
         except (OSError, ValueError):
             pass
     trials = []
-    for sp, b, r, n in itertools.product(splits, bands, rows, nontemporal):
-        ctx.set_apply(b, r, n, sp)
+    for sg, sp, b, r, n in itertools.product(segs, splits, bands, rows, nontemporal):
+        if sg == 8 and r == 4:
+            continue   # no such kernel instance
+        ctx.set_apply(b, r, n, sp, sg)
         t, tb = _time_apply(ctx, lam, q, reps, stream)
-        trials.append(dict(band=b, rows=r, nontemporal=n, split=sp, ms=t, band_ms=tb))
+        trials.append(dict(band=b, rows=r, nontemporal=n, split=sp, seg=sg, ms=t, band_ms=tb))
         if verbose:
-            print(f"[autotune] split={sp} band={b} rows={r} nt={n}: apply {t * 1e3:.1f} us "
+            print(f"[autotune] seg={sg} split={sp} band={b} rows={r} nt={n}: apply {t * 1e3:.1f} us "
                   f"(band kernel {tb * 1e3:.1f} us)", flush=True)
     best = min(trials, key=lambda d: d["ms"])
-    ctx.set_apply(best["band"], best["rows"], best["nontemporal"], best["split"])
+    ctx.set_apply(best["band"], best["rows"], best["nontemporal"], best["split"], best["seg"])
     out = dict(band=best["band"], rows=best["rows"], nontemporal=best["nontemporal"], split=best["split"],
-               ms=best["ms"], trials=trials, cached=False)
+               seg=best["seg"], ms=best["ms"], trials=trials, cached=False)
     if cache:
         data = {}
         if os.path.exists(cache):
@@ -81,7 +84,7 @@ def tune_apply(ctx, lam, q, bands=None, rows=(2, 4), nontemporal=(1,), splits=(0
                     data = json.load(f)
             except (OSError, ValueError):
                 data = {}
-        data[sig] = {k: out[k] for k in ("band", "rows", "nontemporal", "split", "ms")}
+        data[sig] = {k: out[k] for k in ("band", "rows", "nontemporal", "split", "seg", "ms")}
         with open(cache, "w") as f:
             json.dump(data, f, indent=1)
     return out

@@ -254,6 +254,8 @@ hipError_t install_apply(fetiF_ctx c, const ApplyPlan& A)
     if ((e = upload(c->dGent, A.gent)) != hipSuccess) return e;
     c->nbands = (int32_t)A.bands.size();
     c->total_z = A.total_z;
+    c->apply_brmax = 0;
+    for (const Band& bd : A.bands) c->apply_brmax = std::max(c->apply_brmax, bd.r1 - bd.r0);
     return hipSuccess;
 }
 
@@ -551,6 +553,9 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
             return fail(nullptr, FETIF_ENOTSUP, msg);
         }
         c->apply_nch = nch;
+        c->max_m = max_m;
+        // column segments by default when a row would need more than 8 chunks
+        if (c->opt.apply_seg < 0) c->opt.apply_seg = nch > 8 ? 4 : 0;
     }
     // host copies the TRSM planner needs again when it re-plans
     c->hSN = sns;
@@ -987,8 +992,16 @@ extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double*
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
     PhaseTimer t4(c, st, 4);
-    HIPCHK(c, launch_apply_band(c->prec, c->apply_nch, c->opt.apply_rows, c->opt.apply_nontemporal != 0, c->dBands,
-                                c->dSegPtr, c->ngroups, c->dF, lambda_d, c->dDmap, c->dZ, st));
+    if (c->opt.apply_seg > 0) {
+        const int32_t segw = c->opt.apply_seg * 64 * prec_vec(c->prec);
+        const int32_t capp = (c->max_m + segw - 1) / segw * segw;
+        HIPCHK(c, launch_apply_seg(c->prec, c->opt.apply_seg, c->opt.apply_rows, c->opt.apply_nontemporal != 0,
+                                   c->dBands, c->dSegPtr, c->ngroups, c->dF, lambda_d, c->dDmap, c->dZ, capp,
+                                   c->apply_brmax, st));
+    } else {
+        HIPCHK(c, launch_apply_band(c->prec, c->apply_nch, c->opt.apply_rows, c->opt.apply_nontemporal != 0,
+                                    c->dBands, c->dSegPtr, c->ngroups, c->dF, lambda_d, c->dDmap, c->dZ, st));
+    }
     HIPCHK(c, t4.stop());
     PhaseTimer t5(c, st, 5);
     HIPCHK(c, launch_gather(c->prec, c->n_lambda, c->dGptr, c->dGent, c->dBandZ, c->dZ, q_d, st));
@@ -1018,14 +1031,15 @@ extern "C" fetiF_status fetiF_set_assembly(fetiF_ctx c, int32_t trsm_panel, int3
 }
 
 extern "C" fetiF_status fetiF_set_apply(fetiF_ctx c, int32_t band_elems, int32_t rows, int32_t nontemporal,
-                                        int32_t split)
+                                        int32_t split, int32_t seg)
 {
     if (!c) return FETIF_EINVAL;
     if (c->sticky) return FETIF_EDEVICE;
     if (band_elems < 0 || (rows != 0 && rows != 2 && rows != 4) || nontemporal < -1 || nontemporal > 1 ||
-        split < -1 || split > 1)
+        split < -1 || split > 1 || (seg != -1 && seg != 0 && seg != 4 && seg != 8))
         return fail(c, FETIF_EINVAL,
-                    "band_elems >= 0, rows in {0,2,4}, nontemporal in {-1,0,1}, split in {-1,0,1}");
+                    "band_elems >= 0, rows in {0,2,4}, nontemporal in {-1,0,1}, split in {-1,0,1}, "
+                    "seg in {-1,0,4,8}");
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     if (c->pcpg_graph) {
@@ -1036,6 +1050,7 @@ extern "C" fetiF_status fetiF_set_apply(fetiF_ctx c, int32_t band_elems, int32_t
     }
     if (rows) c->opt.apply_rows = rows;
     if (nontemporal >= 0) c->opt.apply_nontemporal = nontemporal;
+    if (seg >= 0) c->opt.apply_seg = seg;
     const int32_t nb = band_elems > 0 ? band_elems : c->opt.apply_band;
     const int32_t ns = split >= 0 ? split : c->opt.apply_split;
     if (nb != c->opt.apply_band || ns != c->opt.apply_split) {

@@ -140,6 +140,8 @@ struct fetiF_ctx_s {
     Band* dBands = nullptr;
     int32_t* dSegPtr = nullptr;
     int32_t ngroups = 0;
+    int32_t apply_brmax = 0;     // most rows of an apply band
+    int32_t max_m = 0;           // largest local multiplier count
     int64_t* dBandZ = nullptr;
     int32_t* dGptr = nullptr;
     GatherEnt* dGent = nullptr;

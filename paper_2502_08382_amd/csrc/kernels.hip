@@ -751,19 +751,29 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
         const int k = lane / (64 / ROWS);
         if ((lane & (64 / ROWS - 1)) == 0 && r + k < b.r1) srow[half][r + k - b.r0] = tot;
     };
-    // software pipeline: the loads of the pair's next pass are in flight
-    // while the current pass is computed (two register sets, used in turn)
-    uint4 ra[ROWS][NH], rb[ROWS][NH];
-    int r = b.r0 + ROWS * pair;
-    if (r < b.r1) issue(r, ra);
-    while (r < b.r1) {
-        issue(r + 2 * ROWS, rb);
-        consume(r, ra);
-        r += 2 * ROWS;
-        if (r >= b.r1) break;
-        issue(r + 2 * ROWS, ra);
-        consume(r, rb);
-        r += 2 * ROWS;
+    if constexpr (NCH <= 8) {
+        // software pipeline: the loads of the pair's next pass are in flight
+        // while the current pass is computed (two register sets, used in turn)
+        uint4 ra[ROWS][NH], rb[ROWS][NH];
+        int r = b.r0 + ROWS * pair;
+        if (r < b.r1) issue(r, ra);
+        while (r < b.r1) {
+            issue(r + 2 * ROWS, rb);
+            consume(r, ra);
+            r += 2 * ROWS;
+            if (r >= b.r1) break;
+            issue(r + 2 * ROWS, ra);
+            consume(r, rb);
+            r += 2 * ROWS;
+        }
+    } else {
+        // long rows: one register set (two would not leave room for a
+        // second wavefront per SIMD)
+        uint4 ra[ROWS][NH];
+        for (int r = b.r0 + ROWS * pair; r < b.r1; r += 2 * ROWS) {
+            issue(r, ra);
+            consume(r, ra);
+        }
     }
     __syncthreads();
     // sp is free now: sum the column partials in a fixed order (pair 0, then pair 1)
@@ -784,6 +794,136 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
     for (int cidx = tid; cidx < b.r1; cidx += NT)
         z[b.zoff + cidx] = sp[cidx] + (cidx >= b.r0 ? srow[0][cidx - b.r0] + srow[1][cidx - b.r0] : (A)0);
     __syncthreads();  // sp and srow are reused by the next segment
+    }
+}
+
+// Column-segmented variant for long rows.  The columns [0, r1) of a band
+// are taken in segments of SEGCH chunks (SEGCH * 64 * VEC columns); for each
+// segment, the band rows that reach into it are spread over the four
+// wavefronts, ROWS consecutive rows per pass, each wavefront reading whole
+// row pieces (no pair split), so the per-lane column partials and load
+// buffers are bounded by the segment, not by m.  Row dots add up across
+// segments in `sband` (LDS, one entry per band row); after a segment its
+// column sums are complete: columns left of the band go to z at once, the
+// band's own columns are added to `sband`.  Every sum has a fixed order.
+// Dynamic LDS: sp[capp] (p, zero past r1), sseg[SEGW], sband[brmax].
+template <typename T, int SEGCH, int ROWS, bool NTL>
+__global__ __launch_bounds__(NT) void apply_seg_kernel(const Band* __restrict__ bands,
+                                                       const int32_t* __restrict__ seg_ptr,
+                                                       const T* __restrict__ F,
+                                                       const double* __restrict__ lam,
+                                                       const int32_t* __restrict__ dmap,
+                                                       typename Acc<T>::type* __restrict__ z, int32_t capp)
+{
+    using A = typename Acc<T>::type;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int RA = kRowAlignBytes / sizeof(T);
+    constexpr int CH = 64 * VEC;          // columns per chunk
+    constexpr int SEGW = SEGCH * CH;      // columns per segment
+    extern __shared__ double smem_d[];
+    A* __restrict__ sp = reinterpret_cast<A*>(smem_d);
+    A* __restrict__ sseg = sp + capp;
+    A* __restrict__ sband = sseg + SEGW;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int seg = seg_ptr[blockIdx.x]; seg < seg_ptr[blockIdx.x + 1]; ++seg) {
+    const Band b = bands[seg];
+    for (int c = tid; c < capp; c += NT) sp[c] = c < b.r1 ? (A)lam[dmap[b.dbase + c]] : (A)0;
+    for (int c = tid; c < b.r1 - b.r0; c += NT) sband[c] = (A)0;
+    __syncthreads();
+    const char* __restrict__ tri = reinterpret_cast<const char*>(F + b.fbase);
+    const int nseg = (b.r1 + SEGW - 1) / SEGW;
+    for (int cs = 0; cs < nseg; ++cs) {
+        const int c0 = cs * SEGW;
+        A y[SEGCH][VEC];
+#pragma unroll
+        for (int ch = 0; ch < SEGCH; ++ch)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) y[ch][e] = (A)0;
+        // the ROWS rows from r on, this segment's chunks; rows at or past r1
+        // and chunks past a row's end read zero (empty range)
+        auto issue = [&](int r, uint4 (&raw)[ROWS][SEGCH]) {
+#pragma unroll
+            for (int k = 0; k < ROWS; ++k) {
+                const int64_t row_start = packed_row_offset(r + k, RA) * (int64_t)sizeof(T);
+                const int row_bytes = r + k < b.r1 ? (int)(RA * ((r + k) / RA + 1) * sizeof(T)) : 0;
+#pragma unroll
+                for (int ch = 0; ch < SEGCH; ++ch) {
+                    const int cbyte = (c0 + ch * CH) * (int)sizeof(T);
+                    const int nbytes = row_bytes > cbyte ? row_bytes - cbyte : 0;
+                    raw[k][ch] = load16_range<NTL>(tri + row_start + cbyte, (uint32_t)nbytes, lane * 16);
+                }
+            }
+        };
+        auto consume = [&](int r, const uint4 (&raw)[ROWS][SEGCH]) {
+            int rr[ROWS];
+            A pr[ROWS], dot[ROWS];
+            int rmax = r;
+#pragma unroll
+            for (int k = 0; k < ROWS; ++k) {
+                rr[k] = (r + k < b.r1) ? r + k : -1;
+                rmax = rr[k] > rmax ? rr[k] : rmax;
+                pr[k] = rr[k] >= 0 ? sp[rr[k]] : (A)0;
+                dot[k] = (A)0;
+            }
+#pragma unroll
+            for (int ch = 0; ch < SEGCH; ++ch) {
+                if (c0 + ch * CH > rmax) break;  // wavefront-uniform
+                const int col = c0 + ch * CH + lane * VEC;
+                A pc[VEC];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) pc[e] = sp[col + e];
+#pragma unroll
+                for (int k = 0; k < ROWS; ++k) {
+                    A v[VEC];
+                    unpack<T, VEC>(raw[k][ch], v);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        dot[k] += v[e] * pc[e];
+                        y[ch][e] += (col + e == rr[k] ? (A)0 : v[e]) * pr[k];
+                    }
+                }
+            }
+            const A tot = rows_wave_sum<ROWS>(dot, lane);
+            const int k = lane / (64 / ROWS);
+            if ((lane & (64 / ROWS - 1)) == 0 && r + k < b.r1) sband[r + k - b.r0] += tot;
+        };
+        // band rows reaching into the segment: r >= max(r0, c0)
+        const int rs = b.r0 > c0 ? b.r0 : c0;
+        uint4 ra[ROWS][SEGCH], rb[ROWS][SEGCH];
+        int r = rs + ROWS * wv;
+        if (r < b.r1) issue(r, ra);
+        while (r < b.r1) {
+            issue(r + 4 * ROWS, rb);
+            consume(r, ra);
+            r += 4 * ROWS;
+            if (r >= b.r1) break;
+            issue(r + 4 * ROWS, ra);
+            consume(r, rb);
+            r += 4 * ROWS;
+        }
+        // column sums of the segment, waves added in a fixed order
+        for (int w = 0; w < 4; ++w) {
+            if (wv == w) {
+#pragma unroll
+                for (int ch = 0; ch < SEGCH; ++ch)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const int cc = ch * CH + lane * VEC + e;
+                        sseg[cc] = (w == 0 ? (A)0 : sseg[cc]) + y[ch][e];
+                    }
+            }
+            __syncthreads();
+        }
+        const int c1 = c0 + SEGW < b.r1 ? c0 + SEGW : b.r1;
+        for (int c = c0 + tid; c < c1; c += NT) {
+            if (c < b.r0) z[b.zoff + c] = sseg[c - c0];
+            else sband[c - b.r0] += sseg[c - c0];
+        }
+        __syncthreads();
+    }
+    for (int c = b.r0 + tid; c < b.r1; c += NT) z[b.zoff + c] = sband[c - b.r0];
+    __syncthreads();  // LDS is reused by the next band
     }
 }
 
@@ -983,6 +1123,51 @@ static hipError_t apply_dispatch(int nch, int rows, bool ntl, const Band* bands,
         return ntl ? apply_dispatch_nch<T, 4, true>(nch, bands, seg_ptr, ngroups, F, lam, dmap, z, st)
                    : apply_dispatch_nch<T, 4, false>(nch, bands, seg_ptr, ngroups, F, lam, dmap, z, st);
     return hipErrorInvalidValue;
+}
+
+template <typename T, int SEGCH, int ROWS, bool NTL>
+static hipError_t seg_launch(const Band* bands, const int32_t* seg_ptr, int32_t ngroups, const void* F,
+                             const double* lam, const int32_t* dmap, void* z, int32_t capp, int32_t brmax,
+                             hipStream_t st)
+{
+    using A = typename Acc<T>::type;
+    constexpr int SEGW = SEGCH * 64 * (16 / (int)sizeof(T));
+    const size_t lds = sizeof(A) * ((size_t)capp + SEGW + brmax);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)apply_seg_kernel<T, SEGCH, ROWS, NTL>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((apply_seg_kernel<T, SEGCH, ROWS, NTL>), dim3(ngroups), dim3(NT), lds, st, bands, seg_ptr,
+                       (const T*)F, lam, dmap, (A*)z, capp);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t seg_dispatch(int segch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
+                               int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
+                               int32_t capp, int32_t brmax, hipStream_t st)
+{
+    // instances: (4 chunks, 2 or 4 rows) and (8 chunks, 2 rows); 8 chunks
+    // with 4 rows would not fit two wavefronts per SIMD
+    if (segch == 8)
+        return ntl ? seg_launch<T, 8, 2, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st)
+                   : seg_launch<T, 8, 2, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
+    if (rows == 4)
+        return ntl ? seg_launch<T, 4, 4, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st)
+                   : seg_launch<T, 4, 4, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
+    return ntl ? seg_launch<T, 4, 2, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st)
+               : seg_launch<T, 4, 2, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
+}
+
+hipError_t launch_apply_seg(int prec, int segch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
+                            int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
+                            int32_t capp, int32_t brmax, hipStream_t st)
+{
+    if (ngroups <= 0) return hipSuccess;
+    if (prec == 0) return seg_dispatch<double>(segch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
+    if (prec == 1) return seg_dispatch<float>(segch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
+    return seg_dispatch<bf16_t>(segch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
 }
 
 hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,

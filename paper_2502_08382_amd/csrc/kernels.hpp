@@ -57,6 +57,12 @@ hipError_t launch_syrk(int prec, const SyrkTile* tiles, int32_t ntiles, const in
 hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
                              int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
                              hipStream_t st);
+// column-segmented apply: segch chunks per segment (4 or 8); capp = LDS
+// columns of p (a multiple of the segment width, >= every r1), brmax = most
+// rows of a band
+hipError_t launch_apply_seg(int prec, int segch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
+                            int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
+                            int32_t capp, int32_t brmax, hipStream_t st);
 hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* gptr, const GatherEnt* ents,
                          const int64_t* band_zoff, const void* z, double* q, hipStream_t st);
 

@@ -1,6 +1,8 @@
 // Dual solver on the device: projected conjugate gradients (paper Alg. 1,
 // M = I), FP64 iterative refinement around a reduced-precision operator, and
 // the primal recovery of alpha and u (Sec. II).
+#include <cmath>
+
 #include "context.hpp"
 
 namespace {
@@ -174,6 +176,9 @@ fetiF_status pcpg_core(fetiF_ctx c, const double* d, const double* e, double* la
             hk = c->hHist[it];
             for (int32_t k = it - chunk + 1; k <= it; ++k)
                 if (c->hHist[k] <= goal) done = true;
+            // a reduced-precision operator can be indefinite on the projected
+            // space: stop when w^T y is no longer finite or has grown 1e8-fold
+            if (!std::isfinite(hk) || hk > 1e8 * h0) done = true;
         }
     }
     if (iters_out) *iters_out = it;
@@ -238,7 +243,11 @@ extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double*
         const Work W = work_of(c);
         HIPCHK(c, launch_gemv(c->ncoarse, c->dAinv, e_d, W.s, st));
         HIPCHK(c, launch_gs(n, 0.0, 1.0, c->dGptr2, c->dGent2, c->dGv, W.s, nullptr, lambda_d, st));
-        double w0 = 0.0, wk = 0.0;
+        // Each inner solve stops at inner_tol, after kInnerMax iterations or
+        // on divergence; a correction that does not lower the true residual
+        // is taken back and the refinement ends there.
+        constexpr int32_t kInnerMax = 2000;
+        double w0 = 0.0, wk = 0.0, wprev = 0.0;
         int32_t total = 0;
         for (int32_t outer = 0; outer < 50; ++outer) {
             HIPCHK(c, apply_op(c, 1, lambda_d, W.q, st));
@@ -250,11 +259,17 @@ extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double*
             HIPCHK(c, hipStreamSynchronize(st));
             wk = std::sqrt(std::max(0.0, ww));
             if (outer == 0) w0 = wk;
+            if (outer > 0 && !(wk < wprev)) {
+                HIPCHK(c, launch_axpby(n, 1.0, lambda_d, -1.0, W.dl, lambda_d, st));
+                wk = wprev;
+                break;
+            }
             R.outer = outer;
+            wprev = wk;
             if (!(w0 > 0.0) || wk <= o.tol * w0 || total >= o.max_iters) break;
             int32_t it = 0;
-            fetiF_status s = pcpg_core(c, W.rt, nullptr, W.dl, o.inner_tol, o.max_iters - total, 0, 0, o.check_every,
-                                       graph, st, &it, nullptr, nullptr);
+            fetiF_status s = pcpg_core(c, W.rt, nullptr, W.dl, o.inner_tol, std::min(kInnerMax, o.max_iters - total),
+                                       0, 0, o.check_every, graph, st, &it, nullptr, nullptr);
             if (s != FETIF_OK) return s;
             total += it;
             HIPCHK(c, launch_axpby(n, 1.0, lambda_d, 1.0, W.dl, lambda_d, st));

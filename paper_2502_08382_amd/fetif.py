@@ -45,7 +45,7 @@ class _Opt(ctypes.Structure):
                 ("nthreads", ctypes.c_int32), ("apply_band", ctypes.c_int32),
                 ("trsm_chunk", ctypes.c_int32), ("apply_rows", ctypes.c_int32),
                 ("apply_nontemporal", ctypes.c_int32), ("apply_split", ctypes.c_int32),
-                ("trsm_panel", ctypes.c_int32)]
+                ("trsm_panel", ctypes.c_int32), ("apply_seg", ctypes.c_int32)]
 
 
 class _PcpgOpt(ctypes.Structure):
@@ -108,7 +108,7 @@ def load_library(path=None):
     L.fetiF_hfactor_free.argtypes = [vp]
     L.fetiF_profile_enable.argtypes = [vp, ctypes.c_int]
     L.fetiF_profile_read.argtypes = [vp, ctypes.c_int, vp, vp, i32]
-    L.fetiF_set_apply.argtypes = [vp, i32, i32, i32, i32]
+    L.fetiF_set_apply.argtypes = [vp, i32, i32, i32, i32, i32]
     L.fetiF_set_assembly.argtypes = [vp, i32, i32]
     L.fetiF_apply_implicit.argtypes = [vp, vp, vp, vp]
     L.fetiF_dual_rhs.argtypes = [vp, vp, vp, vp, vp]
@@ -177,10 +177,10 @@ class _SubArrays:
 
 
 def _options(f_storage="f64", leaf_nodes=0, nthreads=0, apply_band=0, trsm_chunk=0, apply_rows=0,
-             apply_nontemporal=-1, apply_split=-1, trsm_panel=0):
+             apply_nontemporal=-1, apply_split=-1, trsm_panel=0, apply_seg=-1):
     prec = _PREC[f_storage] if isinstance(f_storage, str) else int(f_storage)
     return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk, apply_rows, apply_nontemporal, apply_split,
-                trsm_panel)
+                trsm_panel, apply_seg)
 
 
 class FetiContext:
@@ -256,10 +256,12 @@ class FetiContext:
         self._check(self.L.fetiF_query(self.h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
 
-    def set_apply(self, band_elems=0, rows=0, nontemporal=-1, split=-1):
+    def set_apply(self, band_elems=0, rows=0, nontemporal=-1, split=-1, seg=-1):
         """Re-plan the apply (band size in stored elements, rows per pass,
-        load policy, work split: 0 bands per triangle, 1 equal shares)."""
-        self._check(self.L.fetiF_set_apply(self.h, int(band_elems), int(rows), int(nontemporal), int(split)))
+        load policy, work split: 0 bands per triangle, 1 equal shares,
+        kernel: 0 whole rows, 4/8 column segments of that many chunks)."""
+        self._check(self.L.fetiF_set_apply(self.h, int(band_elems), int(rows), int(nontemporal), int(split),
+                                           int(seg)))
 
     def set_assembly(self, trsm_panel=0, trsm_chunk=0):
         """Re-plan the assembly TRSM (supernode columns per panel, RHS columns per work-group)."""
