@@ -240,6 +240,8 @@ def main():
     apply_gbs = apply_bytes / (t_apply * 1e-3) / 1e9
     band_gbs = band_bytes / (t_band * 1e-3) / 1e9
     asm_flops = info["trsm_flops"] + info["syrk_flops"]
+    # the band kernel the stored or tuned shape selects (phase 4 times it)
+    apply_kernel = "apply_seg_kernel" if (tune or {}).get("seg", 0) else "apply_band_kernel"
 
     result = {
         "metric": METRIC,
@@ -278,7 +280,7 @@ def main():
                                                                                 "nontemporal")},
         "trsm_shape": None if atune is None else {k: atune[k] for k in ("panel", "chunk")},
         "host_factor_s": round(float(np.mean(host_factor_s)), 3) if host_factor_s else None,
-        "roofline": {"bound": "hbm", "kernel": "apply_band_kernel", "achieved": round(band_gbs, 1),
+        "roofline": {"bound": "hbm", "kernel": apply_kernel, "achieved": round(band_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(band_gbs / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_launch": int(band_bytes)},
     }

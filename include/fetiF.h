@@ -112,8 +112,7 @@ typedef struct {
                              1 equal shares of all stored elements, one per work-group */
     int32_t trsm_panel;   /* most supernode columns per TRSM panel, a multiple of 16 (default 48) */
     int32_t apply_seg;    /* apply kernel: 0 whole rows per wavefront pair; 4 or 8 column segments
-                             of that many 1 KiB chunks; other values: segments of 4 when a row
-                             holds more than 8 chunks, else whole rows (default) */
+                             of that many 1 KiB chunks (default 4) */
 } fetiF_options;
 
 /* Preparation (Alg. 2, "preparation"; Sec. IV-B "Preparation"): nested

@@ -554,8 +554,6 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         }
         c->apply_nch = nch;
         c->max_m = max_m;
-        // column segments by default when a row would need more than 8 chunks
-        if (c->opt.apply_seg < 0) c->opt.apply_seg = nch > 8 ? 4 : 0;
     }
     // host copies the TRSM planner needs again when it re-plans
     c->hSN = sns;
