@@ -85,6 +85,41 @@ bool plan_subdomain(const fetiF_subdomain& in, const fetiF_options& opt, int64_t
 
 namespace {
 
+// The MI355X has 8 dies (XCDs), each with its own L2, and hands out the
+// work-groups of a launch round-robin by index (index p to die p % 8).
+// Work that re-reads the same data (the X rows and L panels of one
+// subdomain) should share a die.  xcd_order gives every group (the items of
+// one subdomain) one die -- largest groups first onto the least loaded die
+// -- keeps each die's items in group order, and places the k-th item of die
+// x at index k * kXcds + x; short queues are padded with `noop`.
+constexpr int kXcds = 8;
+
+template <typename T>
+std::vector<T> xcd_order(const std::vector<std::vector<T>>& groups, const std::vector<double>& gcost, const T& noop)
+{
+    std::vector<size_t> ord(groups.size());
+    for (size_t g = 0; g < ord.size(); ++g) ord[g] = g;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return gcost[a] > gcost[b]; });
+    std::vector<std::vector<T>> q(kXcds);
+    std::vector<double> load(kXcds, 0.0);
+    std::vector<size_t> qn(kXcds, 0);
+    for (size_t g : ord) {
+        if (groups[g].empty()) continue;
+        int best = 0;
+        for (int x = 1; x < kXcds; ++x)
+            if (load[x] < load[best] || (load[x] == load[best] && qn[x] < qn[best])) best = x;
+        q[best].insert(q[best].end(), groups[g].begin(), groups[g].end());
+        load[best] += gcost[g];
+        qn[best] = q[best].size();
+    }
+    size_t L = 0;
+    for (const auto& v : q) L = std::max(L, v.size());
+    std::vector<T> out(L * kXcds, noop);
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t k = 0; k < q[x].size(); ++k) out[k * kXcds + x] = q[x][k];
+    return out;
+}
+
 struct ApplyPlan {
     std::vector<Band> bands;      // bands of rows, in subdomain order (indexed by the gather map)
     std::vector<Band> launch;     // the same bands in launch order
@@ -286,7 +321,7 @@ struct TrsmPlan {
 // ceil(ncols/16) * 2 KiB of LDS, would not fit).
 bool plan_trsm(fetiF_ctx c, int32_t panel, int32_t chunk, TrsmPlan& T)
 {
-    std::vector<int32_t> tlevel;
+    std::vector<int32_t> tlevel, tsub;
     int32_t tmaxlev = 0;
     for (int32_t i = 0; i < c->nsub; ++i) {
         const SubPlan& P = c->subs[i];
@@ -312,6 +347,7 @@ bool plan_trsm(fetiF_ctx c, int32_t panel, int32_t chunk, TrsmPlan& T)
                     for (int32_t k = 0; k < x.nrows; ++k)
                         T.troff.push_back(c->hRowOff[P.rowbase + S.rows[x.row_off + k]]);
                     T.tsns.push_back(t);
+                    tsub.push_back(i);
                     tlevel.push_back(L++);
                 }
             }
@@ -344,15 +380,29 @@ bool plan_trsm(fetiF_ctx c, int32_t panel, int32_t chunk, TrsmPlan& T)
             lv[L].push_back(it);
         }
     }
+    // per level: the items of a subdomain on one die (they share its L
+    // panels and X rows), larger panels first
+    auto icost = [&](const TrsmItem& a) {
+        const DevSN& x = T.tsns[a.sn];
+        return (double)x.ncols * (x.ncols + 2.0 * x.nrows) * a.cw;
+    };
+    TrsmItem noop{};
+    noop.cw = 0;   // no columns: the kernel returns at once
     T.level_off.assign(tmaxlev + 2, 0);
     for (int32_t L = 0; L <= tmaxlev; ++L) {
-        auto& v = lv[L];
-        // larger panels first
-        std::stable_sort(v.begin(), v.end(), [&](const TrsmItem& a, const TrsmItem& b) {
-            const DevSN& x = T.tsns[a.sn];
-            const DevSN& y = T.tsns[b.sn];
-            return (int64_t)x.ncols * (x.ncols + 2 * x.nrows) > (int64_t)y.ncols * (y.ncols + 2 * y.nrows);
-        });
+        std::vector<std::vector<TrsmItem>> per_sub(c->nsub);
+        std::vector<double> sub_cost(c->nsub, 0.0);
+        for (const TrsmItem& it : lv[L]) {
+            per_sub[tsub[it.sn]].push_back(it);
+            sub_cost[tsub[it.sn]] += icost(it);
+        }
+        for (auto& v : per_sub)
+            std::stable_sort(v.begin(), v.end(), [&](const TrsmItem& a, const TrsmItem& b) {
+                const DevSN& x = T.tsns[a.sn];
+                const DevSN& y = T.tsns[b.sn];
+                return (int64_t)x.ncols * (x.ncols + 2 * x.nrows) > (int64_t)y.ncols * (y.ncols + 2 * y.nrows);
+            });
+        const std::vector<TrsmItem> v = xcd_order(per_sub, sub_cost, noop);
         T.level_off[L] = (int64_t)T.items.size();
         T.items.insert(T.items.end(), v.begin(), v.end());
     }
@@ -564,20 +614,27 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         delete c;
         return fail(nullptr, FETIF_ENOTSUP, "a TRSM panel has more than 1280 columns");
     }
-    // SYRK tiles: most expensive first
+    // SYRK tiles: the tiles of a subdomain on one die, most expensive first
     {
-        std::vector<int64_t> cost(tiles.size());
-        for (size_t t = 0; t < tiles.size(); ++t) {
+        std::vector<std::vector<SyrkTile>> per_sub(nsub);
+        std::vector<double> sub_cost(nsub, 0.0);
+        auto tcost = [&](const SyrkTile& t) {
             int64_t cst = 0;
-            for (int32_t li = tiles[t].list0; li < tiles[t].list1; ++li) cst += sns[lists[li]].ncols;
-            cost[t] = cst;
+            for (int32_t li = t.list0; li < t.list1; ++li) cst += sns[lists[li]].ncols;
+            return cst;
+        };
+        for (size_t t = 0, i = 0; t < tiles.size(); ++t) {
+            while (i + 1 < (size_t)nsub && tiles[t].fbase != c->subs[i].fbase) ++i;  // made subdomain by subdomain
+            per_sub[i].push_back(tiles[t]);
+            sub_cost[i] += (double)tcost(tiles[t]);
         }
-        std::vector<size_t> ord(tiles.size());
-        for (size_t t = 0; t < ord.size(); ++t) ord[t] = t;
-        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-        std::vector<SyrkTile> t2(tiles.size());
-        for (size_t t = 0; t < ord.size(); ++t) t2[t] = tiles[ord[t]];
-        tiles.swap(t2);
+        for (auto& v : per_sub)
+            std::stable_sort(v.begin(), v.end(),
+                             [&](const SyrkTile& a, const SyrkTile& b) { return tcost(a) > tcost(b); });
+        SyrkTile noop{};
+        noop.m = 0;   // no output: the kernel returns at once
+        tiles = xcd_order(per_sub, sub_cost, noop);
+        c->nsyrk = (int32_t)tiles.size();
     }
     ApplyPlan aplan;
     plan_apply(c, opt.apply_band, opt.apply_split, aplan);

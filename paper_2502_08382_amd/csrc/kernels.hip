@@ -198,6 +198,7 @@ __global__ __launch_bounds__(64 * W) void trsm_level_kernel(const TrsmItem* __re
 {
     extern __shared__ double smem[];
     const TrsmItem it = items[blockIdx.x];
+    if (it.cw == 0) return;  // padding item of the die-aware order (whole work-group)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int q = lane >> 4, j = lane & 15;
     const DevSN s = sns[it.sn];
@@ -497,12 +498,12 @@ constexpr int SP = ST + 2;
 // meets both column ranges (only their rows of X are non-zero there).
 // Wavefront w computes the 32x32 quadrant (w/2, w%2) as 2x2 MFMA blocks.  X
 // rows go through LDS 16 at a time, zero outside the range, in a software
-// pipeline: the global loads of the next 16-row stage are in flight (in
-// registers) while the current stage is multiplied, and the two LDS buffers
-// alternate, so each stage needs one barrier.  On diagonal tiles the two
-// column ranges coincide and one buffer serves both operands.
+// pipeline: the global loads of a 16-row stage are requested two stages
+// ahead (two register sets), and the two LDS buffers alternate, so each
+// stage needs one barrier.  On diagonal tiles the two column ranges
+// coincide and one buffer serves both operands.
 template <typename T>
-__global__ __launch_bounds__(NT) void syrk_kernel(const SyrkTile* __restrict__ tiles,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void syrk_kernel(const SyrkTile* __restrict__ tiles,
                                                   const int32_t* __restrict__ lists,
                                                   const DevSN* __restrict__ sns,
                                                   const double* __restrict__ X, T* __restrict__ F)
@@ -511,6 +512,7 @@ __global__ __launch_bounds__(NT) void syrk_kernel(const SyrkTile* __restrict__ t
     __shared__ double sb[2][SK][SP];
     constexpr int U = (SK * ST) / NT;   // staged values per thread and operand
     const SyrkTile t = tiles[blockIdx.x];
+    if (t.m == 0) return;  // padding tile of the die-aware order (whole work-group)
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int q = lane >> 4, j = lane & 15;
     const int wi = wv >> 1, wj = wv & 1;
@@ -521,26 +523,32 @@ __global__ __launch_bounds__(NT) void syrk_kernel(const SyrkTile* __restrict__ t
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-    // stage cursor: supernode li of the list, its rows k0 .. k0 + SK
-    int li = t.list0, k0 = 0;
-    double ra[U], rb[U];
-    auto fetch = [&](int l, int kb) {
-        const DevSN s = sns[lists[l]];
+    // stages: 16-row pieces of the listed supernodes, in list order; the
+    // fetch cursor (supernode fl, rows fk ..) runs two stages ahead
+    int nst = 0;
+    for (int l = t.list0; l < t.list1; ++l) nst += (sns[lists[l]].ncols + SK - 1) / SK;
+    int fl = t.list0, fk = 0;
+    auto fetch = [&](double (&ra)[U], double (&rb)[U]) {
+        const DevSN s = sns[lists[fl]];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int idx = tid + u * NT;
             const int kk = idx / ST, cc = idx - kk * ST;
-            const int k = kb + kk;
+            const int k = fk + kk;
             const int ja = ca0 + cc - s.j0, jb = cb0 + cc - s.j0;
             const bool kin = k < s.ncols;
             const double* xr = X + s.xoff + (int64_t)k * s.w;
             ra[u] = (kin && ja >= 0 && ja < s.w) ? xr[ja] : 0.0;
             rb[u] = (!diag && kin && jb >= 0 && jb < s.w) ? xr[jb] : 0.0;
         }
+        fk += SK;
+        if (fk >= s.ncols) {
+            ++fl;
+            fk = 0;
+        }
     };
-    if (li < t.list1) fetch(li, 0);
-    for (int stage = 0; li < t.list1; ++stage) {
-        const int buf = stage & 1;
+    auto stage = [&](int st, const double (&ra)[U], const double (&rb)[U]) {
+        const int buf = st & 1;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int idx = tid + u * NT;
@@ -549,13 +557,9 @@ __global__ __launch_bounds__(NT) void syrk_kernel(const SyrkTile* __restrict__ t
             if (!diag) sb[buf][kk][cc] = rb[u];
         }
         __syncthreads();
-        // advance the cursor and start the next stage's loads
-        k0 += SK;
-        if (k0 >= sns[lists[li]].ncols) {
-            ++li;
-            k0 = 0;
-        }
-        if (li < t.list1) fetch(li, k0);
+    };
+    auto multiply = [&](int st) {
+        const int buf = st & 1;
         const double(*pb)[SP] = diag ? sa[buf] : sb[buf];
 #pragma unroll
         for (int k4 = 0; k4 < SK / 4; ++k4) {
@@ -567,6 +571,19 @@ __global__ __launch_bounds__(NT) void syrk_kernel(const SyrkTile* __restrict__ t
             acc[1][0] = mfma16(a1, b0, acc[1][0]);
             acc[1][1] = mfma16(a1, b1, acc[1][1]);
         }
+    };
+    // two register sets: stage st's values were requested two stages earlier
+    double r0a[U], r0b[U], r1a[U], r1b[U];
+    if (nst > 0) fetch(r0a, r0b);
+    if (nst > 1) fetch(r1a, r1b);
+    for (int st = 0; st < nst; st += 2) {
+        stage(st, r0a, r0b);
+        if (st + 2 < nst) fetch(r0a, r0b);
+        multiply(st);
+        if (st + 1 >= nst) break;
+        stage(st + 1, r1a, r1b);
+        if (st + 3 < nst) fetch(r1a, r1b);
+        multiply(st + 1);
     }
     constexpr int64_t V = kRowAlignBytes / sizeof(T);
 #pragma unroll
