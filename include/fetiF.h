@@ -110,7 +110,7 @@ typedef struct {
     int32_t apply_nontemporal; /* 1: stream F~ with non-temporal loads (default), 0: cached */
     int32_t apply_split;  /* apply work split: 0 bands per triangle, largest first (default);
                              1 equal shares of all stored elements, one per work-group */
-    int32_t trsm_panel;   /* most supernode columns per TRSM panel, a multiple of 16 (default 48) */
+    int32_t trsm_panel;   /* most supernode columns per TRSM panel, a multiple of 16 up to 96 (default 48) */
     int32_t apply_seg;    /* apply kernel: 0 whole rows per wavefront pair; 4 or 8 column segments
                              of that many 1 KiB chunks (default 4) */
 } fetiF_options;
@@ -159,7 +159,7 @@ fetiF_status fetiF_set_apply(fetiF_ctx ctx, int32_t band_elems, int32_t rows, in
                              int32_t split, int32_t seg);
 
 /* Re-plan the assembly TRSM (tuning hook): trsm_panel (a multiple of 16 in
- * [16, 1280]; 0 keeps) the most supernode columns per panel, trsm_chunk
+ * [16, 96]; 0 keeps) the most supernode columns per panel, trsm_chunk
  * (16, 32 or 64; 0 keeps) the most RHS columns per work-group.  Synchronises
  * the device; the assembled operator stays valid (the next fetiF_assemble
  * uses the new schedule).  The result of fetiF_assemble does not depend on

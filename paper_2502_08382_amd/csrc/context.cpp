@@ -364,7 +364,7 @@ bool plan_trsm(fetiF_ctx c, int32_t panel, int32_t chunk, TrsmPlan& T)
     for (int32_t L = 0; L <= tmaxlev; ++L) {
         const int32_t mx = std::max(1, T.level_maxns[L]);
         int32_t W = wmax;
-        while (W > 1 && trsm_lds_bytes(W, mx) > 65536) W /= 2;
+        while (W > 1 && trsm_lds_bytes(W, mx) > 80 * 1024) W /= 2;   // keep two work-groups per CU
         if (trsm_lds_bytes(W, mx) > 160 * 1024) return false;
         T.level_waves[L] = W;
     }
@@ -612,7 +612,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     TrsmPlan tplan;
     if (!plan_trsm(c, opt.trsm_panel, opt.trsm_chunk, tplan)) {
         delete c;
-        return fail(nullptr, FETIF_ENOTSUP, "a TRSM panel has more than 1280 columns");
+        return fail(nullptr, FETIF_ENOTSUP, "TRSM panel does not fit in LDS");
     }
     // SYRK tiles: the tiles of a subdomain on one die, most expensive first
     {
@@ -1068,16 +1068,16 @@ extern "C" fetiF_status fetiF_set_assembly(fetiF_ctx c, int32_t trsm_panel, int3
 {
     if (!c) return FETIF_EINVAL;
     if (c->sticky) return FETIF_EDEVICE;
-    if (trsm_panel < 0 || trsm_panel > 1280 || trsm_panel % 16 != 0 ||
+    if (trsm_panel < 0 || trsm_panel > 96 || trsm_panel % 16 != 0 ||
         (trsm_chunk != 0 && trsm_chunk != 16 && trsm_chunk != 32 && trsm_chunk != 64))
-        return fail(c, FETIF_EINVAL, "trsm_panel a multiple of 16 in [16, 1280] (0 keeps), trsm_chunk in {0,16,32,64}");
+        return fail(c, FETIF_EINVAL, "trsm_panel a multiple of 16 in [16, 96] (0 keeps), trsm_chunk in {0,16,32,64}");
     const int32_t np = trsm_panel > 0 ? trsm_panel : c->opt.trsm_panel;
     const int32_t nc = trsm_chunk > 0 ? trsm_chunk : c->opt.trsm_chunk;
     if (np == c->opt.trsm_panel && nc == c->opt.trsm_chunk) return FETIF_OK;
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     TrsmPlan T;
-    if (!plan_trsm(c, np, nc, T)) return fail(c, FETIF_ENOTSUP, "a TRSM panel has more than 1280 columns");
+    if (!plan_trsm(c, np, nc, T)) return fail(c, FETIF_ENOTSUP, "TRSM panel does not fit in LDS");
     HIPCHK(c, hipDeviceSynchronize());
     HIPCHK(c, install_trsm(c, T));
     c->opt.trsm_panel = np;
