@@ -213,12 +213,19 @@ __global__ __launch_bounds__(64 * W) void trsm_level_kernel(const TrsmItem* __re
         const bool cv = (cbeg + j) < it.cw;
         const double* __restrict__ PI = Linv + s.linv;
         double* __restrict__ xs = X + s.xoff + col;      // X_s[row][col] = xs[row * w]
+        // X values of row block rb + 1 are requested while block rb is solved
+        d4 xin;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = q + 4 * r;
+            xin[r] = (cv && row < ns) ? xs[(int64_t)row * s.w] : 0.0;
+        }
         for (int rb = 0; rb < nb; ++rb) {
-            d4 acc;
+            d4 acc = xin;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = rb * 16 + q + 4 * r;
-                acc[r] = (cv && row < ns) ? xs[(int64_t)row * s.w] : 0.0;
+                const int row = (rb + 1) * 16 + q + 4 * r;
+                xin[r] = (cv && row < ns) ? xs[(int64_t)row * s.w] : 0.0;
             }
             const int arow = rb * 16 + j;
             const bool av = arow < ns;
@@ -247,6 +254,17 @@ __global__ __launch_bounds__(64 * W) void trsm_level_kernel(const TrsmItem* __re
     __syncthreads();
     const int64_t jbase = (int64_t)s.j0 + it.c0;
     for (int rb = wv; rb * 16 < nr; rb += W) {
+        // the target X values first: their loads (row offset, then value)
+        // are in flight while the MFMA chain below runs
+        double* xr[4];
+        double xv[4][W];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = rb * 16 + q + 4 * r;
+            xr[r] = i < nr ? X + rowoff[s.rowsoff + i] + jbase : nullptr;
+#pragma unroll
+            for (int c = 0; c < W; ++c) xv[r][c] = (xr[r] && c * 16 + j < it.cw) ? xr[r][c * 16 + j] : 0.0;
+        }
         d4 acc[W];
 #pragma unroll
         for (int c = 0; c < W; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
@@ -264,15 +282,12 @@ __global__ __launch_bounds__(64 * W) void trsm_level_kernel(const TrsmItem* __re
             }
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = rb * 16 + q + 4 * r;
-            if (i < nr) {
-                double* __restrict__ xr = X + rowoff[s.rowsoff + i] + jbase;
+        for (int r = 0; r < 4; ++r)
+            if (xr[r]) {
 #pragma unroll
                 for (int c = 0; c < W; ++c)
-                    if (c * 16 + j < it.cw) xr[c * 16 + j] -= acc[c][r];
+                    if (c * 16 + j < it.cw) xr[r][c * 16 + j] = xv[r][c] - acc[c][r];
             }
-        }
     }
 }
 
