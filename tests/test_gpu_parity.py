@@ -278,3 +278,83 @@ def test_assembly_every_trsm_shape(torch_cuda):
             else:
                 assert max(rel_fro(a, b) for a, b in zip(Fg, ref)) <= 1e-14
     ctx.close()
+
+
+def test_apply_hip_graph_replays(torch_cuda):
+    """fetiF_apply captured in a HIP graph (uneven elasticity subdomains,
+    segmented and whole-row kernels): every replay, with eager work and
+    synchronisations between replays and a new lambda copied in, equals the
+    eager apply bitwise and the oracle to the FP64 bound."""
+    t = torch_cuda
+    prob = make_problem(3, "elasticity", [[3, 6], [5, 4], [4, 3]], 0.3, dirichlet_axis=2, seed=21)
+    say("apply graph", "nsub", prob.nsub)
+    ctx = make_context(prob)
+    upload_and_assemble(ctx, prob)
+    Fs = [oracle_F(prob, i) for i in range(prob.nsub)]
+    rng = np.random.default_rng(5)
+    lams = [rng.standard_normal(prob.n_lambda) for _ in range(3)]
+    for seg in (4, 0):
+        ctx.set_apply(0, 0, -1, -1, seg)
+        lam = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+        q = t.empty_like(lam)
+        lam.copy_(t.tensor(lams[0], device="cuda"))
+        t.cuda.synchronize()
+        g = t.cuda.CUDAGraph()
+        with t.cuda.graph(g):
+            ctx.apply(lam, q)
+        for k in range(3):
+            lam.copy_(t.tensor(lams[k], device="cuda"))
+            g.replay()
+            t.cuda.synchronize()
+            qg = q.cpu().numpy()
+            _ = (lam * 3).sum().item()            # eager work between replays
+            qe = gpu_apply(ctx, lams[k])
+            q_o = feti.apply_explicit(Fs, [s.dual_map for s in prob.subs], lams[k], prob.n_lambda)
+            err = np.linalg.norm(qg - q_o) / np.linalg.norm(q_o)
+            say(f"seg {seg} replay {k}: vs oracle {err:.2e}")
+            assert np.array_equal(qg, qe)
+            assert err <= 1e-12
+        del g
+    ctx.close()
+
+
+def test_full_size_elasticity_and_heat_sampled(torch_cuda):
+    """The uneven elasticity workload (729 subdomains, m up to 3438) and the
+    216-subdomain heat workload (16^3 hexes, lognormal(0,1)) at full size in
+    the default launch configuration: F~_i of the largest and a sampled
+    subdomain against the oracle, and sampled entries of the applied
+    operator against the oracle's row sums."""
+    for k in (3, 4):
+        prob = config_problem(k)
+        say("full size", k, "nsub", prob.nsub, "max m", max(s.m for s in prob.subs))
+        ctx = make_context(prob)
+        upload_and_assemble(ctx, prob)
+        big = int(np.argmax([s.m for s in prob.subs]))
+        tolF = {}
+        Fcache = {}
+        for i in (big, prob.nsub // 3):
+            Fo = Fcache[i] = oracle_F(prob, i)
+            tolF[i] = max(1e-12, _kappa(prob.subs[i].Kreg) * np.finfo(float).eps)
+            e = rel_fro(ctx.download_F(i), Fo)
+            say(f"  sub {i} m {prob.subs[i].m}: F vs oracle {e:.2e} (tol {tolF[i]:.2e})")
+            assert e <= tolF[i]
+        q_g = gpu_apply(ctx, prob.lam)
+        owners = {}
+        for i, s in enumerate(prob.subs):
+            for a, gi in enumerate(s.dual_map):
+                owners.setdefault(int(gi), []).append((i, a))
+        rng = np.random.default_rng(11)
+        # multipliers of the largest subdomain: its F~ is cached below, so
+        # each sample needs at most one more oracle subdomain
+        for gi in rng.choice(prob.subs[big].dual_map, 2, replace=False):
+            acc, bound = 0.0, 0.0
+            for i, a in owners[int(gi)]:
+                if i not in Fcache:
+                    Fcache[i] = oracle_F(prob, i)
+                    tolF.setdefault(i, max(1e-12, _kappa(prob.subs[i].Kreg) * np.finfo(float).eps))
+                li = prob.lam[prob.subs[i].dual_map]
+                acc += Fcache[i][a] @ li
+                bound += tolF[i] * np.linalg.norm(Fcache[i], 2) * np.linalg.norm(li)
+            say(f"  q[{gi}]: gpu {q_g[gi]:.15e} oracle {acc:.15e} bound {bound:.2e}")
+            assert abs(q_g[gi] - acc) <= bound
+        ctx.close()

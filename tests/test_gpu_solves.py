@@ -150,3 +150,55 @@ def test_autograd_function_gradients(torch_cuda):
     assert np.linalg.norm(lam.grad.cpu().numpy() - dl_o) <= 1e-12 * np.linalg.norm(dl_o)
     assert np.linalg.norm(theta.grad.cpu().numpy() - dt_o) <= 1e-12 * np.linalg.norm(dt_o)
     ctx.close()
+
+
+def test_backward_full_size_sampled(torch_cuda):
+    """The 64-subdomain heat workload (10^3 hexes, theta = exp(N(0, 0.3)))
+    at full size: dJ/dlambda = F mu against the oracle's explicit apply;
+    dJ/dtheta of sampled subdomains against the oracle's adjoint (every
+    element); sampled elements against central differences (h = 1e-6) of the
+    oracle's J.  Here a subdomain's term of J is ~2e5 while dJ/dtheta_e is
+    O(1-10), so the difference quotient carries a rounding error of order
+    eps |J_i| / h (~1e-4 absolute, measured ~5e-16 |J_i| / h); the bound is
+    1e-6 relative plus 50 eps |J_i| / h."""
+    t = torch_cuda
+    prob = config_problem(5)
+    say("backward full size", "nsub", prob.nsub)
+    ctx = make_context(prob, with_elements=True)
+    ctx.factor_upload([s.Kreg.data for s in prob.subs])
+    ctx.assemble()
+    ne = sum(len(s.theta) for s in prob.subs)
+    dlam = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+    dth = t.empty(ne, dtype=t.float64, device="cuda")
+    ctx.apply_backward(_dev(t, prob.mu), _dev(t, prob.lam), dlam, dth)
+    t.cuda.synchronize()
+    dth = dth.cpu().numpy()
+    Fs = [feti.local_dual_operator(s.Kreg, s.b_dof, s.b_sign) for s in prob.subs]
+    dl_o = feti.apply_explicit(Fs, [s.dual_map for s in prob.subs], prob.mu, prob.n_lambda)
+    err = np.linalg.norm(dlam.cpu().numpy() - dl_o) / np.linalg.norm(dl_o)
+    say("dlambda rel err", err)
+    assert err <= 1e-12
+    offs = np.cumsum([0] + [len(s.theta) for s in prob.subs])
+    rng = np.random.default_rng(2)
+    h, eps = 1e-6, np.finfo(float).eps
+    for si in rng.choice(prob.nsub, 3, replace=False):
+        s = prob.subs[si]
+        g_o = feti.grad_theta(feti.RegInverse(s.Kreg), s, prob.mu, prob.lam)
+        g_g = dth[offs[si]:offs[si + 1]]
+        err = np.linalg.norm(g_g - g_o) / np.linalg.norm(g_o)
+        say(f"sub {si}: dtheta vs oracle adjoint {err:.2e}")
+        assert err <= 1e-10
+        for e in rng.choice(len(s.theta), 3, replace=False):
+            vals = []
+            for sgn in (1, -1):
+                th = s.theta.copy()
+                th[e] += sgn * h
+                Kr = regularise(assemble_stiffness(s, th), s.R, s.fix_dofs, s.rho)
+                F = feti.local_dual_operator(Kr, s.b_dof, s.b_sign)
+                vals.append(prob.mu[s.dual_map] @ F @ prob.lam[s.dual_map])
+            fd = (vals[0] - vals[1]) / (2 * h)
+            gpu = g_g[e]
+            bound = 1e-6 * abs(fd) + 50 * eps * abs(vals[0]) / h
+            say(f"sub {si} elem {e}: fd {fd:.10e} gpu {gpu:.10e} |J_i| {abs(vals[0]):.3e} bound {bound:.2e}")
+            assert abs(fd - gpu) <= bound
+    ctx.close()
