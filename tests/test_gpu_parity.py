@@ -358,3 +358,33 @@ def test_full_size_elasticity_and_heat_sampled(torch_cuda):
             say(f"  q[{gi}]: gpu {q_g[gi]:.15e} oracle {acc:.15e} bound {bound:.2e}")
             assert abs(q_g[gi] - acc) <= bound
         ctx.close()
+
+
+def test_multi_step_new_stiffness_values(torch_cuda):
+    """Alg. 2 over several steps: the stiffness values change between steps
+    (new element coefficients, same pattern, same frozen rho); each step's
+    factor upload and assembly give that step's F~_i and apply."""
+    from synth.problems import assemble_stiffness, regularise
+    prob = config_problem(5, scale=(2, 6))
+    say("multi-step", "nsub", prob.nsub)
+    ctx = make_context(prob)
+    rng = np.random.default_rng(17)
+    for step in range(3):
+        kvals = []
+        Fs = []
+        for s in prob.subs:
+            th = s.theta * np.exp(0.2 * rng.standard_normal(len(s.theta))) if step else s.theta
+            Kr = regularise(assemble_stiffness(s, th), s.R, s.fix_dofs, s.rho)
+            assert np.array_equal(Kr.indptr, s.Kreg.indptr) and np.array_equal(Kr.indices, s.Kreg.indices)
+            kvals.append(Kr.data)
+            Fs.append(feti.local_dual_operator(Kr, s.b_dof, s.b_sign))
+        ctx.factor_upload(kvals)
+        ctx.assemble()
+        torch_cuda.cuda.synchronize()
+        e_f = max(rel_fro(ctx.download_F(i), Fs[i]) for i in range(prob.nsub))
+        q_o = feti.apply_explicit(Fs, [s.dual_map for s in prob.subs], prob.lam, prob.n_lambda)
+        q_g = gpu_apply(ctx, prob.lam)
+        e_q = np.linalg.norm(q_g - q_o) / np.linalg.norm(q_o)
+        say(f"step {step}: F {e_f:.2e} apply {e_q:.2e}")
+        assert e_f <= 1e-12 and e_q <= 1e-12
+    ctx.close()
