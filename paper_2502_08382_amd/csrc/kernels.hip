@@ -134,6 +134,8 @@ __global__ void rhs_units_kernel(const RhsUnit* __restrict__ u, int64_t n, doubl
 
 // ---------------------------------------------------------------- TRSM
 
+constexpr int kTrsmMaxNb = 6;   // 16-column blocks of the widest TRSM panel (96 columns)
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // v_mfma_f64_16x16x4f64 operand layout on gfx950 (lane l, q = l / 16,
@@ -270,16 +272,24 @@ __global__ __launch_bounds__(64 * W) void trsm_level_kernel(const TrsmItem* __re
         for (int c = 0; c < W; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
         const int arow = ns + rb * 16 + j;
         const bool av = arow < ns + nr;
-#pragma unroll 1
-        for (int kb = 0; kb < nb; ++kb) {
+        // the row block's L operands of a panel of up to kTrsmMaxNb blocks,
+        // requested together (one memory latency per row block)
+        double a[kTrsmMaxNb][4];
+#pragma unroll
+        for (int kb = 0; kb < kTrsmMaxNb; ++kb)
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
                 const int kc = kb * 16 + 4 * kk + q;
-                const double a = (av && kc < ns) ? P[(int64_t)kc * d + arow] : 0.0;
+                a[kb][kk] = (kb < nb && av && kc < ns) ? P[(int64_t)kc * d + arow] : 0.0;
+            }
+#pragma unroll
+        for (int kb = 0; kb < kTrsmMaxNb; ++kb) {
+            if (kb >= nb) break;                         // wavefront-uniform
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
                 for (int c = 0; c < W; ++c)
-                    acc[c] = mfma16(a, sx0[((size_t)c * nbmax * 4 + kb * 4 + kk) * 64 + lane], acc[c]);
-            }
+                    acc[c] = mfma16(a[kb][kk], sx0[((size_t)c * nbmax * 4 + kb * 4 + kk) * 64 + lane], acc[c]);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
