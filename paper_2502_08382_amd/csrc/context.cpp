@@ -903,6 +903,8 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         CK(dalloc(c, &c->dCvec, (size_t)(3 * nc + 2 * nc)));
         CK(dalloc(c, &c->dPart, (size_t)(2 * DOT_PARTS)));
         CK(dalloc(c, &c->dSc, (size_t)SC_COUNT + 8));
+        // scalars and the dot kernel's completion counter (after SC_COUNT) start at zero
+        CK(hipMemset(c->dSc, 0, sizeof(double) * ((size_t)SC_COUNT + 8)));
         // (G^T G)^{-1} in place by Gauss-Jordan steps on the device; the two
         // trailing coarse vectors serve as the pivot row/column buffers
         CK(launch_gauss_jordan_inverse((int32_t)nc, c->dAinv, c->dCvec + 3 * nc, c->dCvec + 4 * nc, nullptr));

@@ -86,12 +86,22 @@ __global__ __launch_bounds__(NT) void gs_kernel(int64_t n, double alpha, double 
     out[g] = (w ? alpha * w[g] : 0.0) + sgn * acc;
 }
 
-// stage 1 of up to two dot products (x.y and x.z): per-block partials
-__global__ __launch_bounds__(NT) void dot_partial_kernel(int64_t n, const double* __restrict__ x,
-                                                         const double* __restrict__ y, const double* __restrict__ z,
-                                                         double* __restrict__ part)
+// Up to two dot products (x.y and x.z) in one launch, deterministic: each
+// work-group writes its partial sums; the last one to finish (counted with
+// an atomic on `done`) adds the partials in a fixed order, updates the
+// solver scalars and resets the counter for the next use (so the launch can
+// be replayed from a graph without clearing anything).
+//  mode 0 (init):   wy = x.y, ww = x.z, k = 0, hist[0] = ww
+//  mode 1 (delta):  pq = x.y, delta = wy / pq
+//  mode 2 (beta):   beta = (x.y) / wy, wy = x.y, ww = x.z, k += 1, hist[k] = ww
+//  mode 3 (plain):  sc[SC_TMP] = x.y, sc[SC_TMP2] = x.z
+__global__ __launch_bounds__(NT) void dot_kernel(int64_t n, const double* __restrict__ x,
+                                                 const double* __restrict__ y, const double* __restrict__ z,
+                                                 int mode, double* __restrict__ part, double* __restrict__ sc,
+                                                 double* __restrict__ hist, int32_t cap, unsigned int* done)
 {
     __shared__ double sh[NT];
+    __shared__ bool last;
     double a = 0.0, b = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
         a += x[i] * y[i];
@@ -102,27 +112,23 @@ __global__ __launch_bounds__(NT) void dot_partial_kernel(int64_t n, const double
     if (threadIdx.x == 0) {
         part[blockIdx.x] = a;
         part[gridDim.x + blockIdx.x] = b;
+        __threadfence();
+        last = atomicAdd(done, 1u) == gridDim.x - 1;
     }
-}
-
-// stage 2: sums the partials and updates the solver scalars
-//  mode 0 (init):   wy = x.y, ww = x.z, k = 0, hist[0] = ww
-//  mode 1 (delta):  pq = x.y, delta = wy / pq
-//  mode 2 (beta):   beta = (x.y) / wy, wy = x.y, ww = x.z, k += 1, hist[k] = ww
-//  mode 3 (plain):  sc[SC_TMP] = x.y, sc[SC_TMP2] = x.z
-__global__ __launch_bounds__(NT) void dot_finish_kernel(int nparts, int mode, double* __restrict__ part,
-                                                        double* __restrict__ sc, double* __restrict__ hist,
-                                                        int32_t cap)
-{
-    __shared__ double sh[NT];
-    double a = 0.0, b = 0.0;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const int nparts = (int)gridDim.x;
+    a = 0.0;
+    b = 0.0;
     for (int i = threadIdx.x; i < nparts; i += NT) {
-        a += part[i];
-        b += part[nparts + i];
+        a += __builtin_nontemporal_load(part + i);
+        b += __builtin_nontemporal_load(part + nparts + i);
     }
     a = block_sum(a, sh);
     b = block_sum(b, sh);
     if (threadIdx.x != 0) return;
+    *done = 0u;
     if (mode == 0) {
         sc[SC_WY] = a;
         sc[SC_WW] = b;
@@ -305,8 +311,10 @@ hipError_t launch_gs(int64_t n, double alpha, double sgn, const int32_t* gptr, c
 hipError_t launch_dot(int64_t n, const double* x, const double* y, const double* z, int mode, double* part,
                       double* sc, double* hist, int32_t hist_cap, hipStream_t st)
 {
-    hipLaunchKernelGGL(dot_partial_kernel, dim3(DOT_PARTS), dim3(NT), 0, st, n, x, y, z, part);
-    hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(NT), 0, st, DOT_PARTS, mode, part, sc, hist, hist_cap);
+    // the completion counter lives in the scalar block, after the scalars
+    unsigned int* done = reinterpret_cast<unsigned int*>(sc + SC_COUNT);
+    hipLaunchKernelGGL(dot_kernel, dim3(DOT_PARTS), dim3(NT), 0, st, n, x, y, z, mode, part, sc, hist, hist_cap,
+                       done);
     return hipGetLastError();
 }
 
