@@ -51,6 +51,8 @@ def main():
                     help="solver iterations per step (FP64); 0: run to --tol")
     ap.add_argument("--tol", type=float, default=1e-9, help="solver tolerance with --prec f32/bf16")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--precond", default="none", choices=["none", "lumped"],
+                    help="M of the PCPG (Alg. 1): identity or the lumped preconditioner")
     ap.add_argument("--cpu-sample", type=int, default=128, help="subdomains timed by the CPU oracle")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--apply-band", type=int, default=0)
@@ -96,6 +98,7 @@ def main():
     sol = torch.empty_like(lam)
     stream = torch.cuda.Stream()
     refine = args.prec != "f64"
+    pc = 1 if args.precond == "lumped" else 0
     tune_cache = os.path.join(ROOT, "paper_2502_08382_amd", "tuned_apply.json")
 
     def shape_key(t):
@@ -139,12 +142,12 @@ def main():
         ev0.record(stream)
         if refine:
             r = ctx.pcpg(d, e, sol, tol=args.tol, refine=True, inner_tol=1e-4 if args.prec == "f32" else 1e-2,
-                         max_iters=20000, use_graph=False, stream=stream)
+                         max_iters=20000, use_graph=False, precond=pc, stream=stream)
         else:
             if args.iters > 0:
-                r = ctx.pcpg(d, e, sol, fixed_iters=args.iters, use_graph=False, stream=stream)
+                r = ctx.pcpg(d, e, sol, fixed_iters=args.iters, use_graph=False, precond=pc, stream=stream)
             else:
-                r = ctx.pcpg(d, e, sol, tol=args.tol, max_iters=20000, use_graph=False, stream=stream)
+                r = ctx.pcpg(d, e, sol, tol=args.tol, max_iters=20000, use_graph=False, precond=pc, stream=stream)
         ev1.record(stream)
         pcpg_events.append((ev0, ev1))
         solver.append(r)
@@ -211,7 +214,8 @@ def main():
     t_pcpg_graph = None
     if not refine and args.iters > 0:
         ctx.profile(False)
-        t_pcpg_graph = event_time(lambda: ctx.pcpg(d, e, sol, fixed_iters=args.iters, use_graph=True, stream=stream), 2)
+        t_pcpg_graph = event_time(lambda: ctx.pcpg(d, e, sol, fixed_iters=args.iters, use_graph=True, precond=pc,
+                                                   stream=stream), 2)
         log(f"PCPG with graph-replayed iterations: {t_pcpg_graph:.3f} ms for {args.iters} iterations")
     t_backward = None
     if args.backward:
@@ -265,7 +269,7 @@ def main():
                               "syrk": round(ms["syrk"] / K, 4)},
         "assembly_tflops": round(asm_flops / (t_asm * 1e-3) / 1e12, 3),
         "assembly_mfma_frac": round(asm_flops / (t_asm * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
-        "solver": {"kind": "PCPG (Alg. 1), M = I" + (", FP64 refinement" if refine else ""),
+        "solver": {"kind": "PCPG (Alg. 1), M = " + ("lumped" if pc else "I") + (", FP64 refinement" if refine else ""),
                    "iters": solver[-1]["iters"], "outer": solver[-1]["outer"],
                    "rel_residual": solver[-1]["rel_residual"],
                    "ms_per_iter": None},

@@ -216,6 +216,9 @@ typedef struct {
                             it got) */
     double inner_tol;    /* relative tolerance of each inner solve (default 1e-4) */
     int32_t use_graph;   /* 1: replay captured iterations (needs a non-NULL stream) */
+    int32_t precond;     /* M of Alg. 1: 0 identity; 1 lumped,
+                            M = sum_i D_i^T B~_i K_reg,i B~_i^T D_i with the
+                            values of the last fetiF_factor_upload */
 } fetiF_pcpg_options;
 
 typedef struct {
@@ -227,7 +230,8 @@ typedef struct {
 } fetiF_pcpg_result;
 
 /* Solve the dual problem (eq. tfetidualproblem) for lambda by PCPG with
- * M = I and lambda_0 = G (G^T G)^{-1} e (Alg. 1).  d_d (n_lambda) from
+ * M = I or the lumped preconditioner (options.precond) and
+ * lambda_0 = G (G^T G)^{-1} e (Alg. 1).  d_d (n_lambda) from
  * fetiF_dual_rhs, e_d from fetiF_coarse_rhs; lambda_d receives the result.
  * Enqueued on `stream`; the call waits for the stream to report the
  * iteration count (every check_every iterations, and at the end). */

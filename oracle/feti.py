@@ -105,6 +105,24 @@ def G_matrix(prob):
     return G
 
 
+def lumped_preconditioner(prob):
+    """The lumped preconditioner of Alg. 1, M = sum_i D_i^T B~_i K_i B~_i^T D_i,
+    with K_i taken as the regularised stiffness K_reg,i the solver works with.
+    Returns a function w -> M w."""
+    blocks = []
+    for s in prob.subs:
+        Bt = Bt_dense(s.n, s.b_dof, s.b_sign)
+        blocks.append((s.dual_map, Bt.T @ (s.Kreg @ Bt)))
+
+    def apply(w):
+        y = np.zeros(prob.n_lambda)
+        for dmap, Mi in blocks:
+            y[dmap] += Mi @ w[dmap]
+        return y
+
+    return apply
+
+
 def e_vector(prob):
     """e = R^T f."""
     return np.concatenate([s.R.T @ s.f for s in prob.subs])

@@ -76,6 +76,38 @@ bool plan_subdomain(const fetiF_subdomain& in, const fetiF_options& opt, int64_t
         xo += (int64_t)S.sn[s].ncols * P.w[s];
     }
     P.nx = xo;
+    // lumped preconditioner tables
+    std::vector<int32_t> bpos(in.n, -1);
+    P.lb_mb.resize(in.m);
+    P.lb_ms.resize(in.m);
+    for (int32_t k = 0; k < in.m; ++k) {
+        const int32_t dof = P.b_dof[P.sigma[k]];
+        if (bpos[dof] < 0) {
+            bpos[dof] = (int32_t)P.lb_dofs.size();
+            P.lb_dofs.push_back(dof);
+        }
+        P.lb_mb[k] = bpos[dof];
+        P.lb_ms[k] = P.b_sign[P.sigma[k]];
+    }
+    const int32_t nb = (int32_t)P.lb_dofs.size();
+    P.lb_uptr.assign(nb + 1, 0);
+    for (int32_t k = 0; k < in.m; ++k) P.lb_uptr[P.lb_mb[k] + 1]++;
+    for (int32_t u = 0; u < nb; ++u) P.lb_uptr[u + 1] += P.lb_uptr[u];
+    P.lb_uk.resize(in.m);
+    {
+        std::vector<int32_t> fill(P.lb_uptr.begin(), P.lb_uptr.end() - 1);
+        for (int32_t k = 0; k < in.m; ++k) P.lb_uk[fill[P.lb_mb[k]]++] = k;
+    }
+    P.lb_kptr.assign(nb + 1, 0);
+    for (int32_t u = 0; u < nb; ++u) {
+        const int32_t row = P.lb_dofs[u];
+        for (int64_t e = A.ptr[row]; e < A.ptr[row + 1]; ++e)
+            if (bpos[A.idx[e]] >= 0) {
+                P.lb_kcol.push_back(bpos[A.idx[e]]);
+                P.lb_ksrc.push_back(e);
+            }
+        P.lb_kptr[u + 1] = (int32_t)P.lb_kcol.size();
+    }
     return true;
 }
 
@@ -899,7 +931,70 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         CK(upload(c->dR, Rcat));
         CK(dalloc(c, &c->dAinv, (size_t)(nc * nc)));
         CK(upload(c->dAinv, GtG));
-        CK(dalloc(c, &c->dVec, (size_t)(7 * n_lambda)));
+        CK(dalloc(c, &c->dVec, (size_t)(8 * n_lambda)));
+        // lumped preconditioner tables (global slots; see LumpSub)
+        {
+            std::vector<LumpSub> ls(nsub);
+            std::vector<int32_t> uptr{0}, uk, kptr{0}, kcol, mb(c->sum_m), gptr(n_lambda + 1, 0), gpos(c->sum_m);
+            std::vector<int8_t> sg(c->sum_m);
+            int32_t bb = 0;
+            int64_t kb = 0;
+            for (int32_t i = 0; i < nsub; ++i) {
+                SubPlan& P = c->subs[i];
+                const int32_t nb = (int32_t)P.lb_dofs.size();
+                ls[i] = LumpSub{bb, nb, P.dbase, P.m};
+                P.lb_kbase = kb;
+                for (int32_t u = 0; u < nb; ++u) {
+                    uptr.push_back(P.dbase + P.lb_uptr[u + 1]);
+                    kptr.push_back((int32_t)(kb + P.lb_kptr[u + 1]));
+                }
+                for (int32_t e = 0; e < P.m; ++e) uk.push_back(P.dbase + P.lb_uk[e]);
+                for (int32_t v : P.lb_kcol) kcol.push_back(bb + v);
+                for (int32_t k = 0; k < P.m; ++k) {
+                    mb[P.dbase + k] = bb + P.lb_mb[k];
+                    sg[P.dbase + k] = P.lb_ms[k];
+                    gptr[P.dual_map[P.sigma[k]] + 1]++;
+                }
+                bb += nb;
+                kb += (int64_t)P.lb_kcol.size();
+                c->lb_nbmax = std::max(c->lb_nbmax, nb);
+            }
+            if (kb > INT32_MAX) {
+                delete c;
+                return fail(nullptr, FETIF_ENOTSUP, "lumped preconditioner tables exceed 2^31 entries");
+            }
+            for (int64_t g = 0; g < n_lambda; ++g) gptr[g + 1] += gptr[g];
+            {
+                std::vector<int32_t> fill(gptr.begin(), gptr.end() - 1);
+                for (int32_t i = 0; i < nsub; ++i) {   // ascending subdomain order per multiplier
+                    const SubPlan& P = c->subs[i];
+                    for (int32_t k = 0; k < P.m; ++k) gpos[fill[P.dual_map[P.sigma[k]]]++] = P.dbase + k;
+                }
+            }
+            c->lb_nk = kb;
+            CK(dalloc(c, &c->dLump, ls.size()));
+            CK(upload(c->dLump, ls));
+            CK(dalloc(c, &c->dLbUptr, uptr.size()));
+            CK(upload(c->dLbUptr, uptr));
+            CK(dalloc(c, &c->dLbUk, uk.size()));
+            CK(upload(c->dLbUk, uk));
+            CK(dalloc(c, &c->dLbKptr, kptr.size()));
+            CK(upload(c->dLbKptr, kptr));
+            CK(dalloc(c, &c->dLbKcol, kcol.size()));
+            CK(upload(c->dLbKcol, kcol));
+            CK(dalloc(c, &c->dLbMb, mb.size()));
+            CK(upload(c->dLbMb, mb));
+            CK(dalloc(c, &c->dLbSgn, sg.size()));
+            CK(upload(c->dLbSgn, sg));
+            CK(dalloc(c, &c->dLbGptr, gptr.size()));
+            CK(upload(c->dLbGptr, gptr));
+            CK(dalloc(c, &c->dLbGpos, gpos.size()));
+            CK(upload(c->dLbGpos, gpos));
+            CK(dalloc(c, &c->dLbKval, (size_t)std::max<int64_t>(1, kb)));
+            CK(dalloc(c, &c->dLbY, (size_t)c->sum_m));
+            CK(hipHostMalloc((void**)&c->hLbKval, sizeof(double) * (size_t)std::max<int64_t>(1, kb),
+                             hipHostMallocDefault));
+        }
         CK(dalloc(c, &c->dCvec, (size_t)(3 * nc + 2 * nc)));
         CK(dalloc(c, &c->dPart, (size_t)(2 * DOT_PARTS)));
         CK(dalloc(c, &c->dSc, (size_t)SC_COUNT + 8));
@@ -969,6 +1064,8 @@ extern "C" fetiF_status fetiF_factor_upload(fetiF_ctx c, int32_t first, int32_t 
         parallel_for(k1 - k0, c->nthreads, [&](int32_t k) {
             const SubPlan& P = c->subs[first + k0 + k];
             bad[k] = numeric_cholesky(P.sym, k_vals[k0 + k], c->hStage + P.lbase);
+            if (c->hLbKval)   // the K_reg entries among boundary DOFs, for the lumped preconditioner
+                for (size_t e = 0; e < P.lb_ksrc.size(); ++e) c->hLbKval[P.lb_kbase + e] = k_vals[k0 + k][P.lb_ksrc[e]];
         });
         for (int32_t k = 0; k < k1 - k0; ++k)
             if (bad[k] >= 0) {
@@ -992,6 +1089,12 @@ extern "C" fetiF_status fetiF_factor_upload(fetiF_ctx c, int32_t first, int32_t 
         PhaseTimer t0(c, st, 0);
         HIPCHK(c, hipMemcpyAsync(c->dL + P0.lbase, c->hStage + P0.lbase, sizeof(double) * (size_t)n,
                                  hipMemcpyHostToDevice, st));
+        if (c->hLbKval) {
+            const int64_t kb0 = P0.lb_kbase, kb1 = P1.lb_kbase + (int64_t)P1.lb_ksrc.size();
+            if (kb1 > kb0)
+                HIPCHK(c, hipMemcpyAsync(c->dLbKval + kb0, c->hLbKval + kb0, sizeof(double) * (size_t)(kb1 - kb0),
+                                         hipMemcpyHostToDevice, st));
+        }
         // inverses of the 16x16 diagonal blocks of the uploaded supernodes,
         // used by the assembly TRSM and by the solves
         HIPCHK(c, launch_diag_inverse(c->dInv + P0.inv0, P1.inv0 + P1.ninv - P0.inv0, c->dSN, c->dL, c->dLinv, st));
@@ -1331,6 +1434,7 @@ extern "C" fetiF_status fetiF_destroy(fetiF_ctx c)
         for (void* p : c->allocations) (void)hipFree(p);
         free_apply(c);
         if (c->hStage) (void)hipHostFree(c->hStage);
+        if (c->hLbKval) (void)hipHostFree(c->hLbKval);
         if (c->upload_done) (void)hipEventDestroy(c->upload_done);
     }
     delete c;

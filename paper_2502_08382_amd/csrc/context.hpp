@@ -69,6 +69,14 @@ struct SubPlan {
     int32_t nk = 0;              // kernel dimension (0: none given)
     std::vector<double> R;       // n x nk row-major
     int32_t koff = 0;            // first coarse unknown
+    // lumped preconditioner B~ K_reg B~^T: boundary DOFs (those B~ touches),
+    // per sorted multiplier its boundary index and sign, the multipliers on
+    // each boundary DOF, the K_reg entries among boundary DOFs (CSR over
+    // boundary indices; lb_ksrc = position in the caller's value array)
+    std::vector<int32_t> lb_dofs, lb_mb, lb_uptr, lb_uk, lb_kptr, lb_kcol;
+    int64_t lb_kbase = 0;        // first K_bb entry of this subdomain (global)
+    std::vector<int8_t> lb_ms;
+    std::vector<int64_t> lb_ksrc;
     std::string err;
 };
 
@@ -173,6 +181,16 @@ struct fetiF_ctx_s {
     double* dR = nullptr;      // concatenated R_i (sum n_i x nk_i)
     double* dVec = nullptr;    // solver work vectors, 7 x n_lambda
     double* dCvec = nullptr;   // 3 x ncoarse
+    // lumped preconditioner (device tables; K_bb values refreshed by every factor upload)
+    LumpSub* dLump = nullptr;
+    int32_t *dLbUptr = nullptr, *dLbUk = nullptr, *dLbKptr = nullptr, *dLbKcol = nullptr, *dLbMb = nullptr;
+    int32_t *dLbGptr = nullptr, *dLbGpos = nullptr;
+    int8_t* dLbSgn = nullptr;
+    double* dLbKval = nullptr;
+    double* dLbY = nullptr;    // sum m_i partial results
+    double* hLbKval = nullptr; // pinned staging of the K_bb values
+    int64_t lb_nk = 0;         // K_bb entries over all subdomains
+    int32_t lb_nbmax = 0;
     double* dPart = nullptr;   // 2 x DOT_PARTS
     double* dSc = nullptr;     // SC_COUNT scalars
     double* dHist = nullptr;   // ||w_k||^2 history

@@ -8,7 +8,7 @@
 namespace {
 
 struct Work {
-    double *r, *w, *y, *p, *q, *rt, *dl;
+    double *r, *w, *y, *p, *q, *rt, *dl, *mz;
     double *t, *s;
 };
 
@@ -23,6 +23,7 @@ Work work_of(fetiF_ctx c)
     W.q = c->dVec + 4 * n;
     W.rt = c->dVec + 5 * n;
     W.dl = c->dVec + 6 * n;
+    W.mz = c->dVec + 7 * n;
     W.t = c->dCvec;
     W.s = c->dCvec + c->ncoarse;
     return W;
@@ -43,8 +44,20 @@ hipError_t project(fetiF_ctx c, const Work& W, const double* in, double* out, hi
     return launch_gs(c->n_lambda, 1.0, -1.0, c->dGptr2, c->dGent2, c->dGv, W.s, in, out, st);
 }
 
+// y = P M w with M = I (precond 0) or the lumped preconditioner (precond 1)
+hipError_t precondition(fetiF_ctx c, const Work& W, int precond, const double* w, double* y, hipStream_t st)
+{
+    if (!precond) return project(c, W, w, y, st);
+    hipError_t e;
+    if ((e = launch_lumped_local(c->nsub, c->lb_nbmax, c->dLump, c->dLbUptr, c->dLbUk, c->dLbSgn, c->dLbKptr,
+                                 c->dLbKcol, c->dLbKval, c->dLbMb, c->dDmap, w, c->dLbY, st)) != hipSuccess)
+        return e;
+    if ((e = launch_lumped_gather(c->n_lambda, c->dLbGptr, c->dLbGpos, c->dLbY, W.mz, st)) != hipSuccess) return e;
+    return project(c, W, W.mz, y, st);
+}
+
 // one iteration of Alg. 1 (the loop body), all scalars on the device
-hipError_t iteration(fetiF_ctx c, const Work& W, int implicit, double* lam, hipStream_t st)
+hipError_t iteration(fetiF_ctx c, const Work& W, int implicit, int precond, double* lam, hipStream_t st)
 {
     hipError_t e;
     const int64_t n = c->n_lambda;
@@ -53,7 +66,7 @@ hipError_t iteration(fetiF_ctx c, const Work& W, int implicit, double* lam, hipS
         return e;
     if ((e = launch_update_lr(n, c->dSc, W.p, W.q, lam, W.r, st)) != hipSuccess) return e;
     if ((e = project(c, W, W.r, W.w, st)) != hipSuccess) return e;
-    if ((e = project(c, W, W.w, W.y, st)) != hipSuccess) return e;  // y = P M w, M = I
+    if ((e = precondition(c, W, precond, W.w, W.y, st)) != hipSuccess) return e;  // y = P M w
     if ((e = launch_dot(n, W.w, W.y, W.w, 2, c->dPart, c->dSc, c->dHist, c->hist_cap, st)) != hipSuccess) return e;
     return launch_update_p(n, 1, c->dSc, W.y, W.p, st);
 }
@@ -81,12 +94,12 @@ hipError_t ensure_hist(fetiF_ctx c, int32_t cap)
 }
 
 // run `count` iterations, replaying a captured chunk when allowed
-hipError_t run_iters(fetiF_ctx c, const Work& W, int implicit, double* lam, int32_t count, int32_t chunk,
-                     bool graph, hipStream_t st)
+hipError_t run_iters(fetiF_ctx c, const Work& W, int implicit, int precond, double* lam, int32_t count,
+                     int32_t chunk, bool graph, hipStream_t st)
 {
     hipError_t e;
     if (graph && st != nullptr && count >= chunk) {
-        const int32_t key = (implicit ? 1 : 0) | (chunk << 1);
+        const int32_t key = (implicit ? 1 : 0) | (precond ? 2 : 0) | (chunk << 2);
         const bool reuse = c->pcpg_graph && c->pcpg_graph_key == key && c->pcpg_graph_stream == st &&
                            c->pcpg_lam == lam;
         if (!reuse) {
@@ -101,7 +114,7 @@ hipError_t run_iters(fetiF_ctx c, const Work& W, int implicit, double* lam, int3
                 return e;
             }
             hipError_t ie = hipSuccess;
-            for (int32_t k = 0; k < chunk && ie == hipSuccess; ++k) ie = iteration(c, W, implicit, lam, st);
+            for (int32_t k = 0; k < chunk && ie == hipSuccess; ++k) ie = iteration(c, W, implicit, precond, lam, st);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(st, &g);
             c->profiling = prof;
@@ -121,18 +134,18 @@ hipError_t run_iters(fetiF_ctx c, const Work& W, int implicit, double* lam, int3
         for (; done + chunk <= count; done += chunk)
             if ((e = hipGraphLaunch(c->pcpg_graph, st)) != hipSuccess) return e;
         for (; done < count; ++done)
-            if ((e = iteration(c, W, implicit, lam, st)) != hipSuccess) return e;
+            if ((e = iteration(c, W, implicit, precond, lam, st)) != hipSuccess) return e;
         return hipSuccess;
     }
     for (int32_t k = 0; k < count; ++k)
-        if ((e = iteration(c, W, implicit, lam, st)) != hipSuccess) return e;
+        if ((e = iteration(c, W, implicit, precond, lam, st)) != hipSuccess) return e;
     return hipSuccess;
 }
 
 // PCPG on P F P lambda = P d from lambda_0 = G (G^T G)^{-1} e (e != NULL)
 // or lambda_0 = 0 (e == NULL).  Returns the iterations and ||w_k||/||w_0||.
 fetiF_status pcpg_core(fetiF_ctx c, const double* d, const double* e, double* lam, double tol, int32_t maxit,
-                       int32_t fixed, int implicit, int32_t check_every, bool graph, hipStream_t st,
+                       int32_t fixed, int implicit, int precond, int32_t check_every, bool graph, hipStream_t st,
                        int32_t* iters_out, double* rel_out, double* w0_out)
 {
     const int64_t n = c->n_lambda;
@@ -148,13 +161,13 @@ fetiF_status pcpg_core(fetiF_ctx c, const double* d, const double* e, double* la
     HIPCHK(c, apply_op(c, implicit, lam, W.q, st));
     HIPCHK(c, launch_axpby(n, 1.0, d, -1.0, W.q, W.r, st));
     HIPCHK(c, project(c, W, W.r, W.w, st));
-    HIPCHK(c, project(c, W, W.w, W.y, st));
+    HIPCHK(c, precondition(c, W, precond, W.w, W.y, st));
     HIPCHK(c, launch_update_p(n, 0, c->dSc, W.y, W.p, st));
     HIPCHK(c, launch_dot(n, W.w, W.y, W.w, 0, c->dPart, c->dSc, c->dHist, c->hist_cap, st));
     int32_t it = 0;
     double h0 = 0.0, hk = 0.0;
     if (fixed > 0) {
-        HIPCHK(c, run_iters(c, W, implicit, lam, fixed, std::max(1, check_every), graph, st));
+        HIPCHK(c, run_iters(c, W, implicit, precond, lam, fixed, std::max(1, check_every), graph, st));
         it = fixed;
         HIPCHK(c, hipMemcpyAsync(c->hHist, c->dHist, sizeof(double) * (size_t)(it + 1), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
@@ -168,7 +181,7 @@ fetiF_status pcpg_core(fetiF_ctx c, const double* d, const double* e, double* la
         bool done = !(h0 > 0.0) || hk <= goal;
         while (!done && it < maxit) {
             const int32_t chunk = std::min(std::max(1, check_every), maxit - it);
-            HIPCHK(c, run_iters(c, W, implicit, lam, chunk, std::max(1, check_every), graph, st));
+            HIPCHK(c, run_iters(c, W, implicit, precond, lam, chunk, std::max(1, check_every), graph, st));
             HIPCHK(c, hipMemcpyAsync(c->hHist + it + 1, c->dHist + it + 1, sizeof(double) * (size_t)chunk,
                                      hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));
@@ -222,7 +235,8 @@ extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double*
     if (o.check_every <= 0) o.check_every = 10;
     if (!(o.inner_tol > 0.0)) o.inner_tol = 1e-4;
     if (o.fixed_iters < 0) return fail(c, FETIF_EINVAL, "fixed_iters < 0");
-    if (o.implicit || o.refine) {
+    if (o.precond != 0 && o.precond != 1) return fail(c, FETIF_EINVAL, "precond must be 0 (none) or 1 (lumped)");
+    if (o.implicit || o.refine || o.precond) {
         if (fetiF_status s1 = need_factors(c)) return s1;
     }
     if (!o.implicit && !c->assembled) return fail(c, FETIF_ESTATE, "explicit PCPG before assemble");
@@ -234,7 +248,7 @@ extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double*
     const bool graph = o.use_graph != 0;
     if (!o.refine) {
         fetiF_status s = pcpg_core(c, d_d, e_d, lambda_d, o.tol, o.max_iters, o.fixed_iters, o.implicit,
-                                   o.check_every, graph, st, &R.iters, &R.rel_residual, &R.w0);
+                                   o.precond, o.check_every, graph, st, &R.iters, &R.rel_residual, &R.w0);
         if (s != FETIF_OK) return s;
     } else {
         // outer FP64 refinement: true projected residual with the implicit
@@ -269,7 +283,7 @@ extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double*
             if (!(w0 > 0.0) || wk <= o.tol * w0 || total >= o.max_iters) break;
             int32_t it = 0;
             fetiF_status s = pcpg_core(c, W.rt, nullptr, W.dl, o.inner_tol, std::min(kInnerMax, o.max_iters - total),
-                                       0, 0, o.check_every, graph, st, &it, nullptr, nullptr);
+                                       0, 0, o.precond, o.check_every, graph, st, &it, nullptr, nullptr);
             if (s != FETIF_OK) return s;
             total += it;
             HIPCHK(c, launch_axpby(n, 1.0, lambda_d, 1.0, W.dl, lambda_d, st));

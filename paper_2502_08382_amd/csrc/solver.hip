@@ -4,6 +4,7 @@
 // reproducible; solver scalars live in device memory (no host round trip).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "solver_kernels.hpp"
@@ -149,6 +150,58 @@ __global__ __launch_bounds__(NT) void dot_kernel(int64_t n, const double* __rest
         sc[SC_TMP] = a;
         sc[SC_TMP2] = b;
     }
+}
+
+// Lumped preconditioner, local part: one work-group per subdomain.  x lives
+// on the subdomain's boundary DOFs (x_u = sum of sign_k w[D k] over the
+// multipliers k on DOF u, in a fixed order), t = K_bb x row by row, and
+// every multiplier k takes sign_k t[b_k].  uk and mb hold global sorted
+// multiplier positions / boundary slots; kcol global boundary slots.
+__global__ __launch_bounds__(NT) void lumped_local_kernel(const LumpSub* __restrict__ ls,
+                                                          const int32_t* __restrict__ uptr,
+                                                          const int32_t* __restrict__ uk,
+                                                          const int8_t* __restrict__ sgn,
+                                                          const int32_t* __restrict__ kptr,
+                                                          const int32_t* __restrict__ kcol,
+                                                          const double* __restrict__ kval,
+                                                          const int32_t* __restrict__ mb,
+                                                          const int32_t* __restrict__ dmap,
+                                                          const double* __restrict__ w, double* __restrict__ ylocal,
+                                                          int32_t nbmax)
+{
+    extern __shared__ double lsm[];
+    double* __restrict__ x = lsm;
+    double* __restrict__ t = lsm + nbmax;
+    const LumpSub S = ls[blockIdx.x];
+    for (int u = threadIdx.x; u < S.nb; u += NT) {
+        const int32_t g = S.bbase + u;
+        double a = 0.0;
+        for (int32_t e = uptr[g]; e < uptr[g + 1]; ++e) a += (double)sgn[uk[e]] * w[dmap[uk[e]]];
+        x[u] = a;
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < S.nb; u += NT) {
+        const int32_t g = S.bbase + u;
+        double a = 0.0;
+        for (int32_t e = kptr[g]; e < kptr[g + 1]; ++e) a += kval[e] * x[kcol[e] - S.bbase];
+        t[u] = a;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < S.m; k += NT) {
+        const int32_t p = S.dbase + k;
+        ylocal[p] = (double)sgn[p] * t[mb[p] - S.bbase];
+    }
+}
+
+__global__ __launch_bounds__(NT) void lumped_gather_kernel(int64_t n, const int32_t* __restrict__ gptr,
+                                                           const int32_t* __restrict__ gpos,
+                                                           const double* __restrict__ ylocal, double* __restrict__ y)
+{
+    const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (g >= n) return;
+    double a = 0.0;
+    for (int32_t e = gptr[g]; e < gptr[g + 1]; ++e) a += ylocal[gpos[e]];
+    y[g] = a;
 }
 
 // lambda += delta p ; r -= delta q
@@ -315,6 +368,31 @@ hipError_t launch_dot(int64_t n, const double* x, const double* y, const double*
     unsigned int* done = reinterpret_cast<unsigned int*>(sc + SC_COUNT);
     hipLaunchKernelGGL(dot_kernel, dim3(DOT_PARTS), dim3(NT), 0, st, n, x, y, z, mode, part, sc, hist, hist_cap,
                        done);
+    return hipGetLastError();
+}
+
+hipError_t launch_lumped_local(int32_t nsub, int32_t nbmax, const LumpSub* ls, const int32_t* uptr,
+                               const int32_t* uk, const int8_t* sgn, const int32_t* kptr, const int32_t* kcol,
+                               const double* kval, const int32_t* mb, const int32_t* dmap, const double* w,
+                               double* ylocal, hipStream_t st)
+{
+    if (nsub <= 0) return hipSuccess;
+    const size_t lds = sizeof(double) * 2 * (size_t)std::max(1, nbmax);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)lumped_local_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(lumped_local_kernel, dim3(nsub), dim3(NT), lds, st, ls, uptr, uk, sgn, kptr, kcol, kval, mb,
+                       dmap, w, ylocal, nbmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_lumped_gather(int64_t n, const int32_t* gptr, const int32_t* gpos, const double* ylocal,
+                                double* y, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lumped_gather_kernel, dim3(blocks(n)), dim3(NT), 0, st, n, gptr, gpos, ylocal, y);
     return hipGetLastError();
 }
 

@@ -47,6 +47,21 @@ hipError_t launch_update_lr(int64_t n, const double* sc, const double* p, const 
 hipError_t launch_update_p(int64_t n, int use_beta, const double* sc, const double* y, double* p, hipStream_t st);
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
                         hipStream_t st);
+// Lumped preconditioner y = sum_i D_i^T B~_i K_reg,i B~_i^T D_i w (the M of
+// Alg. 1).  Per subdomain: its first boundary-DOF slot (global), count, and
+// first sorted multiplier position.
+struct LumpSub {
+    int32_t bbase, nb, dbase, m;
+};
+// ylocal[dbase + k] = sign_k (K_bb x)[b_k] with x = B~^T D w on the boundary
+// DOFs; one work-group per subdomain, 2 * nbmax doubles of LDS
+hipError_t launch_lumped_local(int32_t nsub, int32_t nbmax, const LumpSub* ls, const int32_t* uptr,
+                               const int32_t* uk, const int8_t* sgn, const int32_t* kptr, const int32_t* kcol,
+                               const double* kval, const int32_t* mb, const int32_t* dmap, const double* w,
+                               double* ylocal, hipStream_t st);
+// y[g] = sum of ylocal over the sorted positions of multiplier g (fixed order)
+hipError_t launch_lumped_gather(int64_t n, const int32_t* gptr, const int32_t* gpos, const double* ylocal,
+                                double* y, hipStream_t st);
 hipError_t launch_gauss_jordan_inverse(int32_t n, double* A, double* rowk, double* colk, hipStream_t st);
 hipError_t launch_permute_out(int64_t n, const int32_t* xperm, const double* x, double* u, hipStream_t st);
 hipError_t launch_add_kernel_part(int32_t nsub, const CoarseSub* cs, const double* R, const double* alpha, double* u,

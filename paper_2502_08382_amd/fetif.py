@@ -51,7 +51,7 @@ class _Opt(ctypes.Structure):
 class _PcpgOpt(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
                 ("implicit", ctypes.c_int32), ("check_every", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("use_graph", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("use_graph", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class _PcpgRes(ctypes.Structure):
@@ -233,10 +233,11 @@ class FetiContext:
         self._check(self.L.fetiF_coarse_rhs(self.h, _dptr(f), _dptr(e), _stream(stream)))
 
     def pcpg(self, d, e, lam, tol=1e-9, max_iters=1000, fixed_iters=0, implicit=False, check_every=10,
-             refine=False, inner_tol=1e-4, use_graph=True, stream=None):
-        """PCPG (Alg. 1) on the device; returns dict(iters, outer, rel_residual, w0)."""
+             refine=False, inner_tol=1e-4, use_graph=True, precond=0, stream=None):
+        """PCPG (Alg. 1) on the device (precond 0: M = I, 1: lumped);
+        returns dict(iters, outer, rel_residual, w0)."""
         o = _PcpgOpt(tol, max_iters, fixed_iters, int(implicit), check_every, int(refine), inner_tol,
-                     int(use_graph))
+                     int(use_graph), int(precond))
         r = _PcpgRes()
         self._check(self.L.fetiF_pcpg(self.h, _dptr(d), _dptr(e), _dptr(lam), ctypes.byref(o), ctypes.byref(r),
                                       _stream(stream)))

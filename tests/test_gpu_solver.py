@@ -148,3 +148,62 @@ def test_pcpg_refinement_reaches_fp64_solution(torch_cuda, prec):
     assert r["rel_residual"] <= 1e-9
     assert err <= 1e-6
     ctx.close()
+
+
+@pytest.mark.parametrize("case", ["heat3d", "elast3d"])
+def test_pcpg_lumped_preconditioner(torch_cuda, case):
+    """PCPG with the lumped preconditioner M = sum_i D_i^T B~_i K_reg,i B~_i^T
+    D_i: five iterations reproduce the oracle's preconditioned iterates, the
+    converged lambda equals the oracle's and the unpreconditioned solution,
+    the primal solution equals the global FEM solve, and graph replay is
+    bitwise equal to direct launches."""
+    t = torch_cuda
+    prob = _cases()[case]()
+    say("lumped pcpg", case, "n_lambda", prob.n_lambda)
+    invs, applyF, G, e_o, d_o = _oracle(prob)
+    M = feti.lumped_preconditioner(prob)
+    ctx = make_context(prob)
+    ctx.factor_upload([s.Kreg.data for s in prob.subs])
+    ctx.assemble()
+    f = _dev(t, np.concatenate([s.f for s in prob.subs]))
+    nk = G.shape[1]
+    e = t.empty(nk, dtype=t.float64, device="cuda")
+    d = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+    ctx.coarse_rhs(f, e)
+    ctx.dual_rhs(f, d)
+    stream = t.cuda.Stream()
+    lam = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+    with t.cuda.stream(stream):
+        r5 = ctx.pcpg(d, e, lam, fixed_iters=5, precond=1, use_graph=False, stream=stream)
+    stream.synchronize()
+    lam5 = lam.cpu().numpy()
+    lam5_o, _, _ = feti.pcpg(applyF, d_o, G, e_o, fixed_iters=5, M=M)
+    err5 = np.linalg.norm(lam5 - lam5_o) / np.linalg.norm(lam5_o)
+    say("5 preconditioned iterations: rel diff", err5, r5)
+    assert err5 <= 1e-10
+    with t.cuda.stream(stream):
+        ctx.pcpg(d, e, lam, fixed_iters=5, precond=1, use_graph=True, check_every=5, stream=stream)
+    stream.synchronize()
+    assert np.array_equal(lam.cpu().numpy(), lam5)
+    with t.cuda.stream(stream):
+        r = ctx.pcpg(d, e, lam, tol=1e-12, max_iters=3000, precond=1, stream=stream)
+    stream.synchronize()
+    lam_o, it_o, _ = feti.pcpg(applyF, d_o, G, e_o, tol=1e-12, maxit=3000, M=M)
+    lam_i, it_i, _ = feti.pcpg(applyF, d_o, G, e_o, tol=1e-12, maxit=3000)
+    err = np.linalg.norm(lam.cpu().numpy() - lam_o) / np.linalg.norm(lam_o)
+    say(f"converged: gpu iters {r['iters']} oracle {it_o} (unpreconditioned {it_i}) rel err {err:.2e}")
+    assert r["rel_residual"] <= 1e-12 and err <= 1e-8
+    assert np.linalg.norm(lam_o - lam_i) <= 1e-8 * np.linalg.norm(lam_i)
+    alpha = t.empty(nk, dtype=t.float64, device="cuda")
+    u = t.empty(sum(s.n for s in prob.subs), dtype=t.float64, device="cuda")
+    ctx.primal(f, d, lam, alpha, u)
+    t.cuda.synchronize()
+    ug = global_fem_solve(prob)
+    uu = u.cpu().numpy()
+    off, worst = 0, 0.0
+    for s in prob.subs:
+        gd = (s.gnode[:, None] * prob.dpn + np.arange(prob.dpn)[None, :]).ravel()
+        worst = max(worst, np.abs(uu[off:off + s.n] - ug[gd]).max())
+        off += s.n
+    assert worst <= 1e-8 * np.abs(ug).max()
+    ctx.close()
