@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2, help="workload 1..5")
+    ap.add_argument("--elem", default="box", choices=["box", "simplex"],
+                    help="the workload's box elements, or the same grid cut into linear simplices")
     ap.add_argument("--iters", type=int, default=200,
                     help="solver iterations per step (FP64); 0: run to --tol")
     ap.add_argument("--tol", type=float, default=1e-9, help="solver tolerance with --prec f32/bf16")
@@ -72,13 +74,14 @@ def main():
         sys.exit(2)
 
     import torch
-    from synth import config_problem, CONFIGS
+    from synth import config_problem, workload_name
     from paper_2502_08382_amd import FetiContext, subdomain_dict
 
     assert torch.cuda.is_available(), "needs a GPU"
     dev = torch.device("cuda:0")
     t0 = time.time()
-    prob = config_problem(args.config)
+    prob = config_problem(args.config, elem=args.elem)
+    wname = workload_name(args.config, args.elem)
     log(f"problem C{args.config}: {prob.nsub} subdomains, n_lambda={prob.n_lambda}, "
         f"gen {time.time() - t0:.1f}s")
     t0 = time.time()
@@ -102,7 +105,7 @@ def main():
     tune_cache = os.path.join(ROOT, "paper_2502_08382_amd", "tuned_apply.json")
 
     def shape_key(t):
-        return (f"{CONFIGS[args.config]}|{args.prec}|seg{t.get('seg', 0)}-split{t['split']}-band{t['band']}"
+        return (f"{wname}|{args.prec}|seg{t.get('seg', 0)}-split{t['split']}-band{t['band']}"
                 f"-rows{t['rows']}-nt{t['nontemporal']}")
 
     if args.pmc_apply:
@@ -260,7 +263,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32 (F storage; f64 assembly)", "bf16": "bf16 (F storage; f64 assembly)"}[args.prec],
         "data": "synthetic (seeded structured-grid FETI problem)",
-        "config": {"workload": CONFIGS[args.config], "subdomains": prob.nsub,
+        "config": {"workload": wname, "subdomains": prob.nsub,
                    "dofs_per_subdomain": int(prob.subs[0].n), "n_lambda": int(prob.n_lambda),
                    "sum_m": int(sum_m), "applies_per_step": int(solver[-1]["iters"]), "f_storage": args.prec},
         "assembly_ms_per_1k_subdomains": round(1000.0 * t_asm / prob.nsub, 3),

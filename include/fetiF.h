@@ -67,7 +67,8 @@ typedef enum { FETIF_F64 = 0, FETIF_F32 = 1, FETIF_BF16 = 2 } fetiF_prec;
  *  dim,coords   optional node coordinates (n/dofs_per_node x dim, row-major)
  *               for geometric nested dissection; dim=0/coords=NULL selects
  *               graph nested dissection.
- *  m            rows of B~_i (local Lagrange multipliers).
+ *  m            rows of B~_i (local Lagrange multipliers), m >= 1 (a
+ *               subdomain with none is not coupled: FETIF_EINVAL).
  *  b_dof,b_sign row j of B~_i has the single entry b_sign[j] (+1 or -1) in
  *               column b_dof[j] (Sec. II: one gluing/Dirichlet entry per row).
  *  dual_map     D_i: global multiplier of local row j, strictly increasing,

@@ -226,8 +226,10 @@ def grad_theta(inv, sub, mu, lam):
 
     With K_reg(theta) = sum_e theta_e K_e0 + rho Rt Rt^T (rho frozen),
     dF/dtheta_e = -B K^{-1} K_e0 K^{-1} B^T, so
-    dJ/dtheta_e = -u_mu|_e^T K_e0 u_lam|_e."""
+    dJ/dtheta_e = -u_mu|_e^T K_e0 u_lam|_e  (K_e0: the element's own
+    unit-coefficient matrix)."""
     um = primal_from_dual(inv, sub, mu)
     ul = primal_from_dual(inv, sub, lam)
     ed = sub.elem_dofs()
-    return -np.einsum("ea,ab,eb->e", um[ed], sub.Ke_ref, ul[ed])
+    Ke = np.broadcast_to(sub.elem_matrices(), (ed.shape[0],) + sub.Ke_ref.shape[-2:])
+    return -np.einsum("ea,eab,eb->e", um[ed], Ke, ul[ed])

@@ -15,8 +15,9 @@ bool plan_subdomain(const fetiF_subdomain& in, const fetiF_options& opt, int64_t
     P.m = in.m;
     P.dpn = in.dofs_per_node;
     P.nnzA = A.ptr[in.n];
-    if (in.m < 0 || (in.m > 0 && (!in.b_dof || !in.b_sign || !in.dual_map))) {
-        P.err = "B~ arrays missing";
+    if (in.m <= 0 || !in.b_dof || !in.b_sign || !in.dual_map) {
+        // a subdomain without multipliers is not coupled to the problem
+        P.err = "every subdomain needs m >= 1 rows of B~ (b_dof, b_sign, dual_map)";
         return false;
     }
     P.b_dof.assign(in.b_dof, in.b_dof + in.m);

@@ -15,17 +15,19 @@ namespace {
 
 constexpr int NT = 256;
 
+// Sum over the work-group, returned to every thread: a butterfly inside each
+// wavefront, then the wavefront sums added in wavefront order (a fixed tree,
+// so the result does not depend on timing).  sh holds NT / 64 doubles.
 __device__ __forceinline__ double block_sum(double v, double* sh)
 {
-    const int tid = threadIdx.x;
-    sh[tid] = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();  // an earlier call may still be reading sh
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int o = NT / 2; o > 0; o >>= 1) {
-        if (tid < o) sh[tid] += sh[tid + o];
-        __syncthreads();
-    }
     double r = sh[0];
-    __syncthreads();
+#pragma unroll
+    for (int k = 1; k < NT / 64; ++k) r += sh[k];
     return r;
 }
 
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(NT) void gt_kernel(const CoarseSub* __restrict__ cs
                                                 const int32_t* __restrict__ dmap, const double* __restrict__ w,
                                                 double* __restrict__ t)
 {
-    __shared__ double sh[NT];
+    __shared__ double sh[NT / 64];
     const CoarseSub c = cs[blockIdx.x];
     double acc[COARSE_MAXK];
 #pragma unroll
@@ -87,29 +89,21 @@ __global__ __launch_bounds__(NT) void gs_kernel(int64_t n, double alpha, double 
     out[g] = (w ? alpha * w[g] : 0.0) + sgn * acc;
 }
 
-// Up to two dot products (x.y and x.z) in one launch, deterministic: each
-// work-group writes its partial sums; the last one to finish (counted with
-// an atomic on `done`) adds the partials in a fixed order, updates the
-// solver scalars and resets the counter for the next use (so the launch can
-// be replayed from a graph without clearing anything).
-//  mode 0 (init):   wy = x.y, ww = x.z, k = 0, hist[0] = ww
-//  mode 1 (delta):  pq = x.y, delta = wy / pq
-//  mode 2 (beta):   beta = (x.y) / wy, wy = x.y, ww = x.z, k += 1, hist[k] = ww
-//  mode 3 (plain):  sc[SC_TMP] = x.y, sc[SC_TMP2] = x.z
-__global__ __launch_bounds__(NT) void dot_kernel(int64_t n, const double* __restrict__ x,
-                                                 const double* __restrict__ y, const double* __restrict__ z,
-                                                 int mode, double* __restrict__ part, double* __restrict__ sc,
-                                                 double* __restrict__ hist, int32_t cap, unsigned int* done)
+// Deterministic completion of up to two grid-wide sums (a, b): each
+// work-group writes its partials; the last one to finish (counted with an
+// atomic on `done`) adds the partials in a fixed order, updates the solver
+// scalars and resets the counter (so a captured graph can be replayed
+// without clearing anything).  Called by every thread of every work-group.
+//  mode 0 (init):   wy = a, ww = b, k = 0, hist[0] = ww
+//  mode 1 (delta):  pq = a, delta = wy / pq
+//  mode 2 (beta):   beta = a / wy, wy = a, ww = b, k += 1, hist[k] = ww
+//  mode 3 (plain):  sc[SC_TMP] = a, sc[SC_TMP2] = b
+__device__ void finish_sums(double a, double b, int mode, double* __restrict__ part, double* __restrict__ sc,
+                            double* __restrict__ hist, int32_t cap, unsigned int* done, double* sh)
 {
-    __shared__ double sh[NT];
     __shared__ bool last;
-    double a = 0.0, b = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
-        a += x[i] * y[i];
-        if (z) b += x[i] * z[i];
-    }
     a = block_sum(a, sh);
-    if (z) b = block_sum(b, sh);
+    b = block_sum(b, sh);
     if (threadIdx.x == 0) {
         part[blockIdx.x] = a;
         part[gridDim.x + blockIdx.x] = b;
@@ -150,6 +144,65 @@ __global__ __launch_bounds__(NT) void dot_kernel(int64_t n, const double* __rest
         sc[SC_TMP] = a;
         sc[SC_TMP2] = b;
     }
+}
+
+// x.y (and x.z when z != NULL) over DOT_PARTS work-groups, then the scalar
+// update `mode` of finish_sums.  Each thread requests its (up to) four
+// elements of a pass before adding them.
+__global__ __launch_bounds__(NT) void dot_kernel(int64_t n, const double* __restrict__ x,
+                                                 const double* __restrict__ y, const double* __restrict__ z,
+                                                 int mode, double* __restrict__ part, double* __restrict__ sc,
+                                                 double* __restrict__ hist, int32_t cap, unsigned int* done)
+{
+    __shared__ double sh[NT / 64];
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    double a = 0.0, b = 0.0;
+    for (int64_t i0 = (int64_t)blockIdx.x * NT + threadIdx.x; i0 < n; i0 += 4 * stride) {
+        double xv[4], yv[4], zv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = i0 + k * stride;
+            const bool in = i < n;
+            xv[k] = in ? x[i] : 0.0;
+            yv[k] = in ? y[i] : 0.0;
+            zv[k] = in && z ? z[i] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a += xv[k] * yv[k];
+            b += xv[k] * zv[k];
+        }
+    }
+    finish_sums(a, b, mode, part, sc, hist, cap, done, sh);
+}
+
+// The projection's last step fused with dot products of its input and
+// output: y[g] = x[g] - sum_{entries of g} Gv[e] . s[koff .. koff+nk) over
+// DOT_PARTS work-groups, then finish_sums(a, b, mode) with (a, b) =
+// (x.y, x.x) when pair != 0, else (y.y, y.y).
+__global__ __launch_bounds__(NT) void gs_dot_kernel(int64_t n, const int32_t* __restrict__ gptr,
+                                                    const GEnt* __restrict__ ents, const double* __restrict__ gv,
+                                                    const double* __restrict__ s, const double* __restrict__ x,
+                                                    double* __restrict__ y, int pair, int mode,
+                                                    double* __restrict__ part, double* __restrict__ sc,
+                                                    double* __restrict__ hist, int32_t cap, unsigned int* done)
+{
+    __shared__ double sh[NT / 64];
+    double a = 0.0, b = 0.0;
+    for (int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x; g < n; g += (int64_t)gridDim.x * NT) {
+        double acc = 0.0;
+        for (int32_t e = gptr[g]; e < gptr[g + 1]; ++e) {
+            const GEnt E = ents[e];
+            const double* v = gv + E.gv;
+            for (int k = 0; k < E.nk; ++k) acc += v[k] * s[E.koff + k];
+        }
+        const double xg = x[g];
+        const double yg = xg - acc;
+        y[g] = yg;
+        a += (pair ? xg : yg) * yg;
+        b += pair ? xg * xg : yg * yg;
+    }
+    finish_sums(a, b, mode, part, sc, hist, cap, done, sh);
 }
 
 // Lumped preconditioner, local part: one work-group per subdomain.  x lives
@@ -311,7 +364,7 @@ __global__ __launch_bounds__(NT) void load_primal_rhs_kernel(const int32_t* __re
 __global__ __launch_bounds__(NT) void rtf_kernel(const CoarseSub* __restrict__ cs, const double* __restrict__ R,
                                                  const double* __restrict__ f, double* __restrict__ e)
 {
-    __shared__ double sh[NT];
+    __shared__ double sh[NT / 64];
     const CoarseSub c = cs[blockIdx.x];
     double acc[COARSE_MAXK];
 #pragma unroll
@@ -368,6 +421,16 @@ hipError_t launch_dot(int64_t n, const double* x, const double* y, const double*
     unsigned int* done = reinterpret_cast<unsigned int*>(sc + SC_COUNT);
     hipLaunchKernelGGL(dot_kernel, dim3(DOT_PARTS), dim3(NT), 0, st, n, x, y, z, mode, part, sc, hist, hist_cap,
                        done);
+    return hipGetLastError();
+}
+
+hipError_t launch_gs_dot(int64_t n, const int32_t* gptr, const GEnt* ents, const double* gv, const double* s,
+                         const double* x, double* y, int pair, int mode, double* part, double* sc, double* hist,
+                         int32_t hist_cap, hipStream_t st)
+{
+    unsigned int* done = reinterpret_cast<unsigned int*>(sc + SC_COUNT);
+    hipLaunchKernelGGL(gs_dot_kernel, dim3(DOT_PARTS), dim3(NT), 0, st, n, gptr, ents, gv, s, x, y, pair, mode, part,
+                       sc, hist, hist_cap, done);
     return hipGetLastError();
 }
 

@@ -42,6 +42,12 @@ hipError_t launch_gs(int64_t n, double alpha, double sgn, const int32_t* gptr, c
 // `mode`; the history index is a device counter (graph-replay safe)
 hipError_t launch_dot(int64_t n, const double* x, const double* y, const double* z, int mode, double* part,
                       double* sc, double* hist, int32_t hist_cap, hipStream_t st);
+// y = x - G s (the last step of the projection), then the scalar update
+// `mode` of launch_dot with the sums (x.y, x.x) when pair != 0, else
+// (y.y, y.y)
+hipError_t launch_gs_dot(int64_t n, const int32_t* gptr, const GEnt* ents, const double* gv, const double* s,
+                         const double* x, double* y, int pair, int mode, double* part, double* sc, double* hist,
+                         int32_t hist_cap, hipStream_t st);
 hipError_t launch_update_lr(int64_t n, const double* sc, const double* p, const double* q, double* lam, double* r,
                             hipStream_t st);
 hipError_t launch_update_p(int64_t n, int use_beta, const double* sc, const double* y, double* p, hipStream_t st);

@@ -16,6 +16,8 @@ def subdomain_dict(sub, with_elements=False, with_kernel=True):
     if with_kernel and getattr(sub, "R", None) is not None:
         d["R"] = sub.R
     if with_elements:
+        if np.ndim(sub.Ke_ref) != 2:
+            raise ValueError("element data needs one dK_reg/dtheta_e shared by every element of the subdomain")
         d["elem_dofs"] = sub.elem_dofs()
         d["dK"] = sub.Ke_ref
     return d

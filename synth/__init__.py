@@ -9,7 +9,9 @@ F_i): everything here is problem *definition* (Sec. II, the FEM system, the
 Total-FETI tearing and the generalised-inverse regularisation).
 """
 from .problems import (Problem, Subdomain, make_problem, config_problem,
-                       element_matrix, assemble_stiffness, CONFIGS)
+                       element_matrix, simplex_element_matrix, kuhn_simplices,
+                       assemble_stiffness, workload_name, CONFIGS, CONFIGS_SIMPLEX)
 
 __all__ = ["Problem", "Subdomain", "make_problem", "config_problem",
-           "element_matrix", "assemble_stiffness", "CONFIGS"]
+           "element_matrix", "simplex_element_matrix", "kuhn_simplices",
+           "assemble_stiffness", "workload_name", "CONFIGS", "CONFIGS_SIMPLEX"]

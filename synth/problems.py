@@ -4,7 +4,9 @@ What is built here is the *problem*, not the method:
 
 * the FEM system K~ u~ = f~ of steady heat conduction or linear elasticity on
   the unit line/square/cube, discretised with linear/bilinear/trilinear
-  Lagrange elements (paper Sec. II, eq. femsystem);
+  Lagrange elements on the grid cells, or with linear simplices (triangles,
+  tetrahedra: every cell cut into dim! simplices, the paper's element type)
+  (paper Sec. II, eq. femsystem);
 * its Total-FETI tearing into box subdomains: every subdomain keeps its own
   copy of the interface nodes, gluing between copies and the Dirichlet
   conditions become rows of B with right-hand side c (Sec. II, eqs.
@@ -25,6 +27,11 @@ Conventions (the paper leaves these open; the readings are fixed here):
   multipliers of a subdomain are ordered by ascending global index, so the
   dual map D_i is strictly increasing.
 * Local DOF order: lexicographic local nodes (x fastest), dof = dpn*node+comp.
+* Simplices: the Kuhn subdivision of each cell, one simplex per permutation
+  pi of the axes (itertools order) with vertices 0, e_pi0, e_pi0 + e_pi1, ...,
+  (1,...,1); neighbouring cells then share their face diagonals.  The dim!
+  simplices are images of one another under axis permutations, so with this
+  vertex order their heat element matrices coincide.
 * rho = max_j (K_i)_jj of the coefficients the problem is generated with; it
   is frozen (a later change of theta keeps rho), so K_reg depends on theta
   only through K_i.
@@ -134,6 +141,36 @@ def element_matrix(dim, physics, h=1.0, E=1.0, nu=0.3):
     return Ke * h ** (dim - 2)
 
 
+def kuhn_simplices(dim):
+    """Vertex offsets (dim!, dim+1, dim) of the Kuhn simplices of a unit cell."""
+    out = []
+    for pi in itertools.permutations(range(dim)):
+        v = np.zeros(dim, dtype=np.int64)
+        verts = [v.copy()]
+        for a in pi:
+            v[a] += 1
+            verts.append(v.copy())
+        out.append(np.array(verts))
+    return np.array(out)
+
+
+def simplex_element_matrix(dim, physics, verts, h=1.0, E=1.0, nu=0.3):
+    """Unit-coefficient stiffness of the linear simplex with vertex grid
+    offsets verts (dim+1, dim) and grid step h: the shape functions are the
+    barycentric coordinates, whose gradients are constant."""
+    X = np.asarray(verts, dtype=np.float64) * h
+    J = (X[1:] - X[0]).T
+    Jinv = np.linalg.inv(J)
+    g = np.zeros((dim + 1, dim))
+    g[1:] = Jinv
+    g[0] = -Jinv.sum(axis=0)
+    vol = abs(np.linalg.det(J)) / float(np.prod(np.arange(1, dim + 1)))
+    if physics == "heat":
+        return vol * g @ g.T
+    Bm = _strain_matrix(dim, g)
+    return vol * Bm.T @ _elasticity_D(dim, E, nu) @ Bm
+
+
 # --------------------------------------------------------------------------
 # data containers
 # --------------------------------------------------------------------------
@@ -161,6 +198,7 @@ class Subdomain:
     b_sign: np.ndarray      # (m,) int8 +1/-1
     dual_map: np.ndarray    # (m,) int32 global multiplier index, increasing
     f: np.ndarray           # (n,) load
+    etype: np.ndarray = None  # (ne,) index into Ke_ref when it stacks several matrices
 
     @property
     def n(self):
@@ -171,10 +209,22 @@ class Subdomain:
         return len(self.b_dof)
 
     def elem_dofs(self):
-        """(ne, 2^dim*dpn) local dofs per element, dof = dpn*node + comp."""
+        """(ne, nodes per element * dpn) local dofs per element, dof = dpn*node + comp."""
         d = self.dpn
         return (self.elems[:, :, None] * d + np.arange(d)[None, None, :]).reshape(
             self.elems.shape[0], -1)
+
+    @property
+    def uniform_elements(self):
+        """True when every element has the matrix Ke_ref (nd x nd)."""
+        return self.Ke_ref.ndim == 2
+
+    def elem_matrices(self):
+        """(ne, nd, nd) unit-coefficient element matrices (a broadcast view
+        (1, nd, nd) when they are all equal)."""
+        if self.uniform_elements:
+            return self.Ke_ref[None, :, :]
+        return self.Ke_ref[self.etype]
 
 
 @dataclass
@@ -210,7 +260,7 @@ def assemble_stiffness(sub: Subdomain, theta=None):
     ne, nd = edofs.shape
     rows = np.repeat(edofs, nd, axis=1).ravel()
     cols = np.tile(edofs, (1, nd)).ravel()
-    vals = (th[:, None, None] * sub.Ke_ref[None, :, :]).ravel()
+    vals = (th[:, None, None] * sub.elem_matrices()).ravel()
     n = sub.coords.shape[0] * sub.dpn
     K = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
     K.sum_duplicates()
@@ -273,7 +323,7 @@ def _lex_index(c, shape):
 
 
 def make_problem(dim, physics, widths, theta_sigma=0.0, dirichlet_axis=None,
-                 seed=0, E=1.0, nu=0.3, name="custom"):
+                 seed=0, E=1.0, nu=0.3, name="custom", elem="box"):
     """Build a torn structured-grid problem.
 
     widths : list (one per axis) of lists of element counts per subdomain slab.
@@ -284,6 +334,8 @@ def make_problem(dim, physics, widths, theta_sigma=0.0, dirichlet_axis=None,
     seed : int, numpy SeedSequence, or the list of its five spawned
            streams [widths, theta, f, lambda, mu] (the first stream is used by
            config_problem to draw uneven slab widths).
+    elem : "box" (multilinear element per grid cell) or "simplex" (dim!
+           linear simplices per cell, each with its own coefficient).
     """
     if isinstance(seed, (list, tuple)):
         s_widths, s_theta, s_f, s_lam, s_mu = seed
@@ -296,18 +348,27 @@ def make_problem(dim, physics, widths, theta_sigma=0.0, dirichlet_axis=None,
     n_el = tuple(int(sum(w)) for w in widths)
     n_nd = tuple(e + 1 for e in n_el)
     h = 1.0 / max(n_el)
-    Ke_ref = element_matrix(dim, physics, h=h, E=E, nu=nu)
+    if elem == "box":
+        cell_elems = _corner_offsets(dim)[None]
+        Ke_ref = element_matrix(dim, physics, h=h, E=E, nu=nu)
+    elif elem == "simplex":
+        cell_elems = kuhn_simplices(dim)
+        Ke_ref = np.stack([simplex_element_matrix(dim, physics, v, h=h, E=E, nu=nu) for v in cell_elems])
+        if np.allclose(Ke_ref, Ke_ref[0], rtol=0.0, atol=1e-14 * np.abs(Ke_ref).max()):
+            Ke_ref = Ke_ref[0].copy()
+    else:
+        raise ValueError(elem)
+    per_cell = cell_elems.shape[0]
 
     # global element coefficients, drawn in global element order so that the
     # field does not depend on the decomposition
-    n_gel = int(np.prod(n_el))
+    n_gel = int(np.prod(n_el)) * per_cell
     if theta_sigma > 0:
         theta_glob = np.exp(theta_sigma * np.random.default_rng(s_theta).standard_normal(n_gel))
     else:
         theta_glob = np.ones(n_gel)
     rng_f = np.random.default_rng(s_f)
 
-    corners = _corner_offsets(dim)
     sub_grid = [len(w) for w in widths]
     offs = [np.concatenate([[0], np.cumsum(w)[:-1]]).astype(int) for w in widths]
     subs = []
@@ -322,13 +383,17 @@ def make_problem(dim, physics, widths, theta_sigma=0.0, dirichlet_axis=None,
         gnode = _lex_index(coords, n_nd)
         ec = np.stack(np.meshgrid(*[np.arange(s) for s in w[::-1]], indexing="ij")[::-1],
                       axis=-1).reshape(-1, dim)
-        elems = _lex_index(ec[:, None, :] + corners[None, :, :], nshape)
-        gelem = _lex_index(ec + np.array(o), n_el)
+        # cell-major, then the cell's elements
+        elems = _lex_index(ec[:, None, None, :] + cell_elems[None, :, :, :], nshape).reshape(
+            -1, cell_elems.shape[1])
+        gelem = (_lex_index(ec + np.array(o), n_el)[:, None] * per_cell
+                 + np.arange(per_cell)[None, :]).ravel()
         theta = theta_glob[gelem].copy()
+        etype = None if Ke_ref.ndim == 2 else np.tile(np.arange(per_cell), len(ec))
         sub = Subdomain(index=sidx, dim=dim, dpn=dpn, widths=w, offset=o, coords=coords,
                         gnode=gnode, elems=elems, gelem=gelem, theta=theta,
                         Ke_ref=Ke_ref, K=None, Kreg=None, rho=0.0, fix_dofs=None,
-                        R=None, b_dof=None, b_sign=None, dual_map=None, f=None)
+                        R=None, b_dof=None, b_sign=None, dual_map=None, f=None, etype=etype)
         sub.K = assemble_stiffness(sub)
         sub.rho = float(sub.K.diagonal().max())
         sub.R = _kernel_basis(physics, dim, coords * h)
@@ -397,7 +462,7 @@ def make_problem(dim, physics, widths, theta_sigma=0.0, dirichlet_axis=None,
     return Problem(name=name, dim=dim, physics=physics, dpn=dpn, h=h, n_elems=n_el,
                    subs=subs, n_lambda=n_lambda, c=c, lam=lam, mu=mu,
                    dirichlet_axis=dirichlet_axis,
-                   meta=dict(theta_sigma=theta_sigma, E=E, nu=nu))
+                   meta=dict(theta_sigma=theta_sigma, E=E, nu=nu, elem=elem))
 
 
 # --------------------------------------------------------------------------
@@ -418,22 +483,45 @@ CONFIGS = {
 }
 
 
-def config_problem(k, scale=None):
+# the same workloads on linear simplices (every cell cut into dim! simplices)
+CONFIGS_SIMPLEX = {
+    1: "2D heat, unit square, 32x32 cells x 2 linear triangles in 2x2 subdomains of 16x16 cells, "
+       "conductivity 1, Dirichlet x=0",
+    2: "3D heat, 96^3 cells x 6 linear tetrahedra in 8^3 subdomains of 12^3 cells, "
+       "conductivity lognormal(0,0.5), Dirichlet z=0",
+    3: "3D elasticity, linear tetrahedra (6 per cell), 9^3 subdomains with seeded slab widths "
+       "U{6..14} cells, E=1 nu=0.3, Dirichlet z=0",
+    4: "3D heat, 96^3 cells x 6 linear tetrahedra in 6^3 subdomains of 16^3 cells, "
+       "conductivity lognormal(0,1), Dirichlet z=0",
+    5: "3D heat, 40^3 cells x 6 linear tetrahedra in 4^3 subdomains of 10^3 cells, "
+       "conductivity exp(N(0,0.3)), Dirichlet z=0",
+}
+
+
+def workload_name(k, elem="box"):
+    """Description of workload k on box elements or on simplices."""
+    return CONFIGS[k] if elem == "box" else CONFIGS_SIMPLEX[k]
+
+
+def config_problem(k, scale=None, elem="box"):
     """Problem for workload k (1..5), seeded with SeedSequence(1000+k).
 
     scale : optional (subdomains per axis, elements per subdomain axis) override
             that keeps the workload's physics and coefficient law but shrinks
             the mesh (used for quick tests); None gives the full workload.
+    elem :  "box" (the workload's multilinear elements) or "simplex" (the
+            same grid cut into linear triangles / tetrahedra).
     """
     ss = list(np.random.SeedSequence(1000 + k).spawn(5))
+    kw = dict(elem=elem)
     if k == 1:
         S, W = scale or (2, 16)
         return make_problem(2, "heat", [[W] * S] * 2, 0.0, dirichlet_axis=0, seed=ss,
-                            name="C1")
+                            name="C1", **kw)
     if k == 2:
         S, W = scale or (8, 12)
         return make_problem(3, "heat", [[W] * S] * 3, 0.5, dirichlet_axis=2, seed=ss,
-                            name="C2")
+                            name="C2", **kw)
     if k == 3:
         S, W = scale or (9, None)
         rng = np.random.default_rng(ss[0])
@@ -442,13 +530,13 @@ def config_problem(k, scale=None):
         else:
             widths = [[W] * S] * 3
         return make_problem(3, "elasticity", widths, 0.0, dirichlet_axis=2, seed=ss,
-                            name="C3")
+                            name="C3", **kw)
     if k == 4:
         S, W = scale or (6, 16)
         return make_problem(3, "heat", [[W] * S] * 3, 1.0, dirichlet_axis=2, seed=ss,
-                            name="C4")
+                            name="C4", **kw)
     if k == 5:
         S, W = scale or (4, 10)
         return make_problem(3, "heat", [[W] * S] * 3, 0.3, dirichlet_axis=2, seed=ss,
-                            name="C5")
+                            name="C5", **kw)
     raise ValueError(k)

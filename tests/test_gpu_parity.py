@@ -35,6 +35,12 @@ def _cases():
         "C4s": lambda: config_problem(4, scale=(2, 16)),
         "el8": lambda: make_problem(3, "elasticity", [[8, 7], [8, 8], [7, 8]], 0.3,
                                     dirichlet_axis=2, seed=5),
+        # linear simplices (the paper's element type): other factor sparsity
+        "C2s_tet": lambda: config_problem(2, scale=(2, 12), elem="simplex"),
+        "el_tet": lambda: make_problem(3, "elasticity", [[5, 7], [6, 6], [7, 5]], 0.3,
+                                       dirichlet_axis=2, seed=4, elem="simplex"),
+        "heat2d_tri": lambda: make_problem(2, "heat", [[9, 6, 11], [10, 7]], 0.5,
+                                           dirichlet_axis=0, seed=2, elem="simplex"),
     }
 
 

@@ -32,6 +32,8 @@ def _cases():
         "C1": lambda: config_problem(1),
         "heat3d": lambda: make_problem(3, "heat", [[3, 4], [4, 3], [3, 3]], 0.5, dirichlet_axis=2, seed=4),
         "elast3d": lambda: make_problem(3, "elasticity", [[3, 3], [3, 4], [4, 3]], 0.2, dirichlet_axis=2, seed=6),
+        "heat3d_tet": lambda: make_problem(3, "heat", [[4, 3], [3, 4], [3, 3]], 0.5, dirichlet_axis=2, seed=8,
+                                           elem="simplex"),
     }
 
 

@@ -20,6 +20,7 @@ def _cases():
         "C2s": lambda: config_problem(2, scale=(2, 12)),
         "el3": lambda: make_problem(3, "elasticity", [[3, 4], [3, 3], [4, 3]], 0.3, dirichlet_axis=2, seed=3),
         "heat2d": lambda: make_problem(2, "heat", [[7, 13, 5], [9, 11]], 0.5, dirichlet_axis=0, seed=9),
+        "C5s_tet": lambda: config_problem(5, scale=(2, 6), elem="simplex"),
     }
 
 
@@ -67,7 +68,7 @@ def test_implicit_apply_and_dual_rhs(torch_cuda, case):
     ctx.close()
 
 
-@pytest.mark.parametrize("case", ["C5s", "el3"])
+@pytest.mark.parametrize("case", ["C5s", "el3", "C5s_tet"])
 def test_backward_matches_oracle(torch_cuda, case):
     t = torch_cuda
     prob = _cases()[case]()

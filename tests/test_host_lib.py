@@ -119,7 +119,7 @@ def test_create_without_device_reports_edevice():
     assert e.value.status == 4
 
 
-@pytest.mark.parametrize("bad", ["dual_map_order", "dual_map_range", "b_sign", "b_dof", "n_lambda"])
+@pytest.mark.parametrize("bad", ["dual_map_order", "dual_map_range", "b_sign", "b_dof", "n_lambda", "no_multipliers"])
 def test_create_validates_arguments(bad):
     P = _problems()["heat2d"]
     subs = [subdomain_dict(s) for s in P.subs]
@@ -135,6 +135,10 @@ def test_create_validates_arguments(bad):
         d["b_dof"] = d["b_dof"] + 10 ** 6
     elif bad == "n_lambda":
         nl = 0
+    elif bad == "no_multipliers":
+        d["b_dof"] = np.zeros(0, np.int32)
+        d["b_sign"] = np.zeros(0, np.int8)
+        d["dual_map"] = np.zeros(0, np.int32)
     subs[1] = d
     with pytest.raises(FetiError) as e:
         FetiContext(subs, nl)

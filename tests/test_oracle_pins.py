@@ -10,7 +10,7 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from synth import make_problem, config_problem, element_matrix
+from synth import make_problem, config_problem, element_matrix, simplex_element_matrix, kuhn_simplices
 from synth.problems import assemble_stiffness, regularise
 from oracle import feti
 from oracle import implicit as orc_impl
@@ -77,10 +77,20 @@ def tiny(kind, seed=7):
     if kind == "elast2d":
         return make_problem(2, "elasticity", [[3, 2, 3], [3, 2]], 0.3, dirichlet_axis=0,
                             seed=seed)
+    # linear simplices on the same kind of grids (the paper's element type)
+    if kind == "heat2d_tri":
+        return make_problem(2, "heat", [[3, 4], [4, 3]], 0.5, dirichlet_axis=0, seed=seed,
+                            elem="simplex")
+    if kind == "heat3d_tet":
+        return make_problem(3, "heat", [[3, 2], [2, 3], [2, 2]], 0.5, dirichlet_axis=2, seed=seed,
+                            elem="simplex")
+    if kind == "elast3d_tet":
+        return make_problem(3, "elasticity", [[2, 2], [2, 2], [2, 2]], 0.3, dirichlet_axis=2,
+                            seed=seed, elem="simplex")
     raise ValueError(kind)
 
 
-KINDS = ["heat2d", "heat3d", "elast3d", "elast2d"]
+KINDS = ["heat2d", "heat3d", "elast3d", "elast2d", "heat2d_tri", "heat3d_tet", "elast3d_tet"]
 
 
 # ---------------------------------------------------------------- element matrices
@@ -110,6 +120,43 @@ def test_element_matrices_closed_form():
     rot[0::3] = -corners[:, 1]
     rot[1::3] = corners[:, 0]
     assert np.allclose(Ke @ rot, 0, atol=1e-14)
+
+
+def test_simplex_element_matrices_closed_form():
+    """Linear simplices of the Kuhn subdivision: the barycentric gradients of
+    (0,0),(1,0),(1,1) are (-1,0),(1,-1),(0,1) (area 1/2), those of
+    (0,0,0),(1,0,0),(1,1,0),(1,1,1) are -e_x, e_x-e_y, e_y-e_z, e_z (volume
+    1/6): tridiagonal [1,-1; -1,2,-1; ...; -1,1] scaled by the measure."""
+    T2 = np.array([[1, -1, 0], [-1, 2, -1], [0, -1, 1]], float) / 2
+    assert np.allclose(simplex_element_matrix(2, "heat", kuhn_simplices(2)[0]), T2)
+    T3 = np.array([[1, -1, 0, 0], [-1, 2, -1, 0], [0, -1, 2, -1], [0, 0, -1, 1]], float) / 6
+    for v in kuhn_simplices(3):       # every Kuhn simplex, vertices in Kuhn order
+        assert np.allclose(simplex_element_matrix(3, "heat", v, h=0.5), 0.5 * T3)
+    # the six tetrahedra tile the cube: a linear field a.x has energy |a|^2 h^3
+    h = 0.25
+    a = np.array([0.3, -1.1, 0.7])
+    cube = np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)])
+    E = 0.0
+    for v in kuhn_simplices(3):
+        u = (v * h) @ a
+        E += u @ simplex_element_matrix(3, "heat", v, h=h) @ u
+    assert np.isclose(E, a @ a * h ** 3)
+    assert len(kuhn_simplices(3)) == 6 and {tuple(c) for v in kuhn_simplices(3) for c in v} <= {tuple(c) for c in cube}
+    # elasticity: rigid motions in the kernel (rank 12 - 6), and a uniform
+    # strain eps has energy eps:D:eps times the volume
+    for v in kuhn_simplices(3):
+        Ke = simplex_element_matrix(3, "elasticity", v, h=1.0, E=1.0, nu=0.3)
+        assert np.allclose(Ke, Ke.T)
+        assert np.sum(np.linalg.eigvalsh(Ke) < 1e-12) == 6
+    nu, Ey = 0.3, 1.0
+    lam_, mu_ = Ey * nu / ((1 + nu) * (1 - 2 * nu)), Ey / (2 * (1 + nu))
+    Gd = np.array([[0.2, 0.1, 0.0], [0.1, -0.3, 0.05], [0.0, 0.05, 0.4]])  # symmetric displacement gradient
+    Etot = 0.0
+    for v in kuhn_simplices(3):
+        u = (v.astype(float) @ Gd.T).ravel()
+        Etot += u @ simplex_element_matrix(3, "elasticity", v, h=1.0, E=Ey, nu=nu) @ u
+    eps_energy = lam_ * np.trace(Gd) ** 2 + 2 * mu_ * np.sum(Gd * Gd)
+    assert np.isclose(Etot, eps_energy)
 
 
 # ---------------------------------------------------------------- 1D closed form
@@ -217,7 +264,8 @@ def test_F_additivity_and_apply_routes():
 
 # ---------------------------------------------------------------- whole FETI
 
-@pytest.mark.parametrize("kind", ["C1", "heat3d", "elast3d", "elast2d"])
+@pytest.mark.parametrize("kind", ["C1", "heat3d", "elast3d", "elast2d", "heat2d_tri", "heat3d_tet",
+                                  "elast3d_tet"])
 def test_feti_solution_equals_global_fem(kind):
     """The torn system is equivalent to the FEM system: PCPG (Alg. 1) + alpha
     (eq. alphacompute) + u recovery (eq. solutionUeval) reproduce the global
@@ -260,18 +308,23 @@ def _J(sub, theta, mu, lam):
     return mu[sub.dual_map] @ F @ lam[sub.dual_map]
 
 
-def test_gradient_central_differences():
-    P = make_problem(3, "heat", [[3, 3], [3, 3], [3, 3]], 0.3, dirichlet_axis=2, seed=11)
+@pytest.mark.parametrize("elem,physics", [("box", "heat"), ("simplex", "heat"), ("simplex", "elasticity")])
+def test_gradient_central_differences(elem, physics):
+    w = [[3, 3]] * 3 if physics == "heat" else [[2, 2]] * 3
+    P = make_problem(3, physics, w, 0.3, dirichlet_axis=2, seed=11, elem=elem)
     rng = np.random.default_rng(0)
+    eps = np.finfo(float).eps
     for s in P.subs[:3]:
         inv = feti.RegInverse(s.Kreg)
         g = feti.grad_theta(inv, s, P.mu, P.lam)
+        J0 = abs(_J(s, s.theta, P.mu, P.lam))
         for e in rng.choice(len(s.theta), 6, replace=False):
             h = 1e-6
             tp = s.theta.copy(); tp[e] += h
             tm = s.theta.copy(); tm[e] -= h
             fd = (_J(s, tp, P.mu, P.lam) - _J(s, tm, P.mu, P.lam)) / (2 * h)
-            assert abs(fd - g[e]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max())
+            # truncation O(h^2) plus the rounding of the two J values (eps |J| / h)
+            assert abs(fd - g[e]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()) + 50 * eps * J0 / h
 
 
 def test_gradient_euler_identity():
