@@ -114,6 +114,10 @@ typedef struct {
     int32_t trsm_panel;   /* most supernode columns per TRSM panel, a multiple of 16 up to 96 (default 48) */
     int32_t apply_seg;    /* apply kernel: 0 whole rows per wavefront pair; 4 or 8 column segments
                              of that many 1 KiB chunks (default 4) */
+    int32_t assembly_groups; /* contiguous subdomain groups of about equal factor size, each
+                                with its own assembly schedule (default 1; at most nsub):
+                                fetiF_factor_assemble factors group g+1 on the host while the
+                                device copies and assembles group g */
 } fetiF_options;
 
 /* Preparation (Alg. 2, "preparation"; Sec. IV-B "Preparation"): nested
@@ -142,6 +146,18 @@ fetiF_status fetiF_factor_upload(fetiF_ctx ctx, int32_t first, int32_t count,
  * chosen precision.  Requires every subdomain uploaded since the last
  * assembly (else FETIF_ESTATE).  Asynchronous on `stream`. */
 fetiF_status fetiF_assemble(fetiF_ctx ctx, void* stream);
+
+/* Factorisation, copy and assembly of every subdomain, pipelined by the
+ * assembly groups (Sec. IV-B "Preprocessing": the host factors the next
+ * subdomains while the device assembles the previous ones): for each group,
+ * host factorisation of its subdomains, then on `stream` the copy of their
+ * factor values and their assembly, while the host goes on to the next
+ * group.  k_vals[i] holds the CSR values of K_reg of subdomain i (all nsub).
+ * The result is the one of fetiF_factor_upload over all subdomains followed
+ * by fetiF_assemble (bitwise).  Returns when the last group is enqueued (the
+ * host arrays may be freed then); FETIF_ENOTSPD as fetiF_factor_upload, after
+ * which no subdomain counts as uploaded and F~ as not assembled. */
+fetiF_status fetiF_factor_assemble(fetiF_ctx ctx, const double* const* k_vals, void* stream);
 
 /* q_d[0..n_lambda) = sum_i D_i^T F~_i D_i lambda_d (Alg. 2 scatter, apply,
  * gather; eq. dualop_apply_expl).  FP64 vectors.  Each q entry is summed in
@@ -267,6 +283,7 @@ typedef struct {
     int32_t trsm_levels;    /* launches of the level-scheduled TRSM */
     int32_t apply_groups;   /* work-groups of one apply */
     int64_t apply_elements; /* stored elements the apply streams (sum of packed triangles) */
+    int32_t assembly_groups; /* groups of fetiF_factor_assemble (see fetiF_options) */
 } fetiF_info;
 
 fetiF_status fetiF_query(fetiF_ctx ctx, fetiF_info* info);

@@ -341,6 +341,24 @@ struct TrsmPlan {
     std::vector<int32_t> level_waves, level_maxns;
 };
 
+// Assembly groups: contiguous subdomain ranges of about equal factor size
+// (at most G of them, none empty); first[g] .. first[g+1] is group g.
+std::vector<int32_t> plan_groups(fetiF_ctx c, int32_t G)
+{
+    G = std::max(1, std::min(G, c->nsub));
+    int64_t total = 0;
+    for (int32_t i = 0; i < c->nsub; ++i) total += c->subs[i].sym.nvals;
+    std::vector<int32_t> first{0};
+    int64_t acc = 0;
+    for (int32_t i = 0; i + 1 < c->nsub; ++i) {
+        acc += c->subs[i].sym.nvals;
+        const int32_t g = (int32_t)first.size();   // index of the next group
+        if (g < G && (double)acc * G >= (double)total * g && c->nsub - (i + 1) >= G - g) first.push_back(i + 1);
+    }
+    first.push_back(c->nsub);
+    return first;
+}
+
 // TRSM schedule.  Every supernode with RHS columns is cut into column panels
 // of at most `panel` columns (a multiple of 16): panel k starts at diagonal
 // offset o = k * panel of the same storage, and the supernode's columns after
@@ -421,25 +439,34 @@ bool plan_trsm(fetiF_ctx c, int32_t panel, int32_t chunk, TrsmPlan& T)
     };
     TrsmItem noop{};
     noop.cw = 0;   // no columns: the kernel returns at once
-    T.level_off.assign(tmaxlev + 2, 0);
-    for (int32_t L = 0; L <= tmaxlev; ++L) {
-        std::vector<std::vector<TrsmItem>> per_sub(c->nsub);
-        std::vector<double> sub_cost(c->nsub, 0.0);
-        for (const TrsmItem& it : lv[L]) {
-            per_sub[tsub[it.sn]].push_back(it);
-            sub_cost[tsub[it.sn]] += icost(it);
+    // items ordered by assembly group, then level: group g's level L is
+    // items [level_off[g * nlev + L], level_off[g * nlev + L + 1])
+    const int32_t G = (int32_t)c->grp_first.size() - 1;
+    const int32_t nlev = tmaxlev + 1;
+    T.level_off.assign((size_t)G * nlev + 1, 0);
+    for (int32_t g = 0; g < G; ++g) {
+        const int32_t s0 = c->grp_first[g], s1 = c->grp_first[g + 1];
+        for (int32_t L = 0; L < nlev; ++L) {
+            std::vector<std::vector<TrsmItem>> per_sub(s1 - s0);
+            std::vector<double> sub_cost(s1 - s0, 0.0);
+            for (const TrsmItem& it : lv[L]) {
+                const int32_t i = tsub[it.sn];
+                if (i < s0 || i >= s1) continue;
+                per_sub[i - s0].push_back(it);
+                sub_cost[i - s0] += icost(it);
+            }
+            for (auto& v : per_sub)
+                std::stable_sort(v.begin(), v.end(), [&](const TrsmItem& a, const TrsmItem& b) {
+                    const DevSN& x = T.tsns[a.sn];
+                    const DevSN& y = T.tsns[b.sn];
+                    return (int64_t)x.ncols * (x.ncols + 2 * x.nrows) > (int64_t)y.ncols * (y.ncols + 2 * y.nrows);
+                });
+            const std::vector<TrsmItem> v = xcd_order(per_sub, sub_cost, noop);
+            T.level_off[(size_t)g * nlev + L] = (int64_t)T.items.size();
+            T.items.insert(T.items.end(), v.begin(), v.end());
         }
-        for (auto& v : per_sub)
-            std::stable_sort(v.begin(), v.end(), [&](const TrsmItem& a, const TrsmItem& b) {
-                const DevSN& x = T.tsns[a.sn];
-                const DevSN& y = T.tsns[b.sn];
-                return (int64_t)x.ncols * (x.ncols + 2 * x.nrows) > (int64_t)y.ncols * (y.ncols + 2 * y.nrows);
-            });
-        const std::vector<TrsmItem> v = xcd_order(per_sub, sub_cost, noop);
-        T.level_off[L] = (int64_t)T.items.size();
-        T.items.insert(T.items.end(), v.begin(), v.end());
     }
-    T.level_off[tmaxlev + 1] = (int64_t)T.items.size();
+    T.level_off[(size_t)G * nlev] = (int64_t)T.items.size();
     return true;
 }
 
@@ -642,6 +669,8 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     c->hSN = sns;
     c->hRowOff.resize(xrows.size());
     for (size_t r = 0; r < xrows.size(); ++r) c->hRowOff[r] = xrows[r].off - xrows[r].j0;
+    c->grp_first = plan_groups(c, opt.assembly_groups);
+    const int32_t ngrp = (int32_t)c->grp_first.size() - 1;
     TrsmPlan tplan;
     if (!plan_trsm(c, opt.trsm_panel, opt.trsm_chunk, tplan)) {
         delete c;
@@ -666,7 +695,18 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
                              [&](const SyrkTile& a, const SyrkTile& b) { return tcost(a) > tcost(b); });
         SyrkTile noop{};
         noop.m = 0;   // no output: the kernel returns at once
-        tiles = xcd_order(per_sub, sub_cost, noop);
+        // group by group: group g's tiles are [syrk_off[g], syrk_off[g+1])
+        tiles.clear();
+        c->syrk_off.assign(ngrp + 1, 0);
+        for (int32_t g = 0; g < ngrp; ++g) {
+            const int32_t s0 = c->grp_first[g], s1 = c->grp_first[g + 1];
+            const std::vector<std::vector<SyrkTile>> gs(per_sub.begin() + s0, per_sub.begin() + s1);
+            const std::vector<double> gc(sub_cost.begin() + s0, sub_cost.begin() + s1);
+            const std::vector<SyrkTile> v = xcd_order(gs, gc, noop);
+            c->syrk_off[g] = (int64_t)tiles.size();
+            tiles.insert(tiles.end(), v.begin(), v.end());
+        }
+        c->syrk_off[ngrp] = (int64_t)tiles.size();
         c->nsyrk = (int32_t)tiles.size();
     }
     ApplyPlan aplan;
@@ -997,7 +1037,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
                              hipHostMallocDefault));
         }
         CK(dalloc(c, &c->dCvec, (size_t)(3 * nc + 2 * nc)));
-        CK(dalloc(c, &c->dPart, (size_t)(2 * DOT_PARTS)));
+        CK(dalloc(c, &c->dPart, (size_t)2 * dot_parts(c->n_lambda)));
         CK(dalloc(c, &c->dSc, (size_t)SC_COUNT + 8));
         // scalars and the dot kernel's completion counter (after SC_COUNT) start at zero
         CK(hipMemset(c->dSc, 0, sizeof(double) * ((size_t)SC_COUNT + 8)));
@@ -1033,29 +1073,18 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
 
 // ======================================================================== factor + upload
 
-extern "C" fetiF_status fetiF_factor_upload(fetiF_ctx c, int32_t first, int32_t count,
-                                            const double* const* k_vals, void* stream)
+namespace {
+
+// Host factorisation of subdomains [first, first+count) and the asynchronous
+// copy of their values on st (no wait for earlier copies: every subdomain has
+// its own staging area).  Chunks of about 64 MiB of factor values: the copy
+// of a chunk and its diagonal-block inverses run on the stream while the host
+// factors the next chunk.
+fetiF_status upload_range(fetiF_ctx c, int32_t first, int32_t count, const double* const* k_vals, hipStream_t st)
 {
-    if (!c) return FETIF_EINVAL;
-    if (c->sticky) return FETIF_EDEVICE;
-    if (first < 0 || count <= 0 || first + count > c->nsub || !k_vals)
-        return fail(c, FETIF_EINVAL, "subdomain range out of bounds or k_vals NULL");
-    for (int32_t k = 0; k < count; ++k)
-        if (!k_vals[k]) return fail(c, FETIF_EINVAL, "k_vals entry is NULL");
-    DeviceGuard dg(c->device);
-    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
-    hipStream_t st = (hipStream_t)stream;
-    // the staging area may still be read by the previous asynchronous copy
-    if (c->upload_pending) {
-        HIPCHK(c, hipEventSynchronize(c->upload_done));
-        c->upload_pending = false;
-    }
     // any upload replaces factor values: F~ must be assembled again, and on
     // failure the whole range counts as not uploaded
     c->assembled = false;
-    // chunks of about 64 MiB of factor values: the copy of a chunk and its
-    // diagonal-block inverses run on the stream while the host factors the
-    // next chunk (each subdomain has its own staging area)
     constexpr int64_t kChunkVals = int64_t(8) << 20;
     for (int32_t k0 = 0; k0 < count;) {
         int32_t k1 = k0;
@@ -1076,10 +1105,9 @@ extern "C" fetiF_status fetiF_factor_upload(fetiF_ctx c, int32_t first, int32_t 
                         c->uploaded[first + t] = 0;
                         c->n_uploaded--;
                     }
-                if (k0 > 0) {   // earlier chunks' copies may still read the staging area
-                    HIPCHK(c, hipEventRecord(c->upload_done, st));
-                    c->upload_pending = true;
-                }
+                // earlier copies may still read the staging area
+                HIPCHK(c, hipEventRecord(c->upload_done, st));
+                c->upload_pending = true;
                 return fail(c, FETIF_ENOTSPD,
                             "subdomain " + std::to_string(first + k0 + k) + ": non-positive pivot at permuted column " +
                                 std::to_string(bad[k]) + " (original dof " + std::to_string(P.sym.perm[bad[k]]) + ")");
@@ -1112,6 +1140,57 @@ extern "C" fetiF_status fetiF_factor_upload(fetiF_ctx c, int32_t first, int32_t 
     return FETIF_OK;
 }
 
+// The device work of one assembly group g (contiguous subdomains): RHS
+// initialisation of its X, its TRSM levels, its SYRK tiles.
+hipError_t rhs_group(fetiF_ctx c, int32_t g, hipStream_t st)
+{
+    const SubPlan& A = c->subs[c->grp_first[g]];
+    const SubPlan& B = c->subs[c->grp_first[g + 1] - 1];
+    hipError_t e = launch_fill_zero(c->dX + A.xbase, B.xbase + B.nx - A.xbase, st);
+    if (e != hipSuccess) return e;
+    return launch_rhs_units(c->dUnits + A.dbase, (int64_t)B.dbase + B.m - A.dbase, c->dX, st);
+}
+
+hipError_t trsm_group(fetiF_ctx c, int32_t g, hipStream_t st)
+{
+    const int32_t nlev = c->trsm_levels;
+    for (int32_t L = 0; L < nlev; ++L) {
+        const size_t k = (size_t)g * nlev + L;
+        const int32_t cnt = (int32_t)(c->level_off[k + 1] - c->level_off[k]);
+        hipError_t e = launch_trsm_level(c->dItems + c->level_off[k], cnt, c->level_waves[L], c->level_maxns[L],
+                                         c->dTSN, c->dL, c->dLinv, c->dTRowOff, c->dX, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t syrk_group(fetiF_ctx c, int32_t g, hipStream_t st)
+{
+    return launch_syrk(c->prec, c->dTiles + c->syrk_off[g], (int32_t)(c->syrk_off[g + 1] - c->syrk_off[g]),
+                       c->dLists, c->dSN, c->dX, c->dF, st);
+}
+
+}  // namespace
+
+extern "C" fetiF_status fetiF_factor_upload(fetiF_ctx c, int32_t first, int32_t count,
+                                            const double* const* k_vals, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (first < 0 || count <= 0 || first + count > c->nsub || !k_vals)
+        return fail(c, FETIF_EINVAL, "subdomain range out of bounds or k_vals NULL");
+    for (int32_t k = 0; k < count; ++k)
+        if (!k_vals[k]) return fail(c, FETIF_EINVAL, "k_vals entry is NULL");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    // the staging area may still be read by the previous asynchronous copy
+    if (c->upload_pending) {
+        HIPCHK(c, hipEventSynchronize(c->upload_done));
+        c->upload_pending = false;
+    }
+    return upload_range(c, first, count, k_vals, (hipStream_t)stream);
+}
+
 // ======================================================================== assemble
 
 extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
@@ -1122,20 +1201,59 @@ extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
+    const int32_t G = (int32_t)c->grp_first.size() - 1;
+    // phase by phase over the groups (one timer per phase)
     PhaseTimer t1(c, st, 1);
-    HIPCHK(c, launch_fill_zero(c->dX, c->total_X, st));
-    HIPCHK(c, launch_rhs_units(c->dUnits, c->sum_m, c->dX, st));
+    for (int32_t g = 0; g < G; ++g) HIPCHK(c, rhs_group(c, g, st));
     HIPCHK(c, t1.stop());
     PhaseTimer t2(c, st, 2);
-    for (int32_t L = 0; L < c->trsm_levels; ++L) {
-        int32_t cnt = (int32_t)(c->level_off[L + 1] - c->level_off[L]);
-        HIPCHK(c, launch_trsm_level(c->dItems + c->level_off[L], cnt, c->level_waves[L], c->level_maxns[L], c->dTSN,
-                                    c->dL, c->dLinv, c->dTRowOff, c->dX, st));
-    }
+    for (int32_t g = 0; g < G; ++g) HIPCHK(c, trsm_group(c, g, st));
     HIPCHK(c, t2.stop());
     PhaseTimer t3(c, st, 3);
-    HIPCHK(c, launch_syrk(c->prec, c->dTiles, c->nsyrk, c->dLists, c->dSN, c->dX, c->dF, st));
+    for (int32_t g = 0; g < G; ++g) HIPCHK(c, syrk_group(c, g, st));
     HIPCHK(c, t3.stop());
+    c->assembled = true;
+    return FETIF_OK;
+}
+
+extern "C" fetiF_status fetiF_factor_assemble(fetiF_ctx c, const double* const* k_vals, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (!k_vals) return fail(c, FETIF_EINVAL, "k_vals NULL");
+    for (int32_t k = 0; k < c->nsub; ++k)
+        if (!k_vals[k]) return fail(c, FETIF_EINVAL, "k_vals entry is NULL");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    if (c->upload_pending) {
+        HIPCHK(c, hipEventSynchronize(c->upload_done));
+        c->upload_pending = false;
+    }
+    const int32_t G = (int32_t)c->grp_first.size() - 1;
+    for (int32_t g = 0; g < G; ++g) {
+        const int32_t s0 = c->grp_first[g], s1 = c->grp_first[g + 1];
+        fetiF_status s = upload_range(c, s0, s1 - s0, k_vals + s0, st);
+        if (s != FETIF_OK) {
+            // earlier groups were uploaded and assembled from this call's
+            // values, later ones hold older factors: nothing counts as uploaded
+            std::fill(c->uploaded.begin(), c->uploaded.end(), 0);
+            c->n_uploaded = 0;
+            c->assembled = false;
+            return s;
+        }
+        // the group's assembly is enqueued behind its copy; the host goes on
+        // to factor the next group meanwhile
+        PhaseTimer t1(c, st, 1);
+        HIPCHK(c, rhs_group(c, g, st));
+        HIPCHK(c, t1.stop());
+        PhaseTimer t2(c, st, 2);
+        HIPCHK(c, trsm_group(c, g, st));
+        HIPCHK(c, t2.stop());
+        PhaseTimer t3(c, st, 3);
+        HIPCHK(c, syrk_group(c, g, st));
+        HIPCHK(c, t3.stop());
+    }
     c->assembled = true;
     return FETIF_OK;
 }
@@ -1375,6 +1493,7 @@ extern "C" fetiF_status fetiF_query(fetiF_ctx c, fetiF_info* info)
     info->factor_flops = c->factor_flops;
     info->trsm_levels = c->trsm_levels;
     info->apply_groups = c->ngroups;
+    info->assembly_groups = (int32_t)c->grp_first.size() - 1;
     {
         const int V = prec_row_align(c->prec);
         int64_t tot = 0;
@@ -1434,6 +1553,7 @@ extern "C" fetiF_status fetiF_destroy(fetiF_ctx c)
         if (c->dHist) (void)hipFree(c->dHist);
         for (void* p : c->allocations) (void)hipFree(p);
         free_apply(c);
+        free_trsm(c);
         if (c->hStage) (void)hipHostFree(c->hStage);
         if (c->hLbKval) (void)hipHostFree(c->hLbKval);
         if (c->upload_done) (void)hipEventDestroy(c->upload_done);

@@ -107,7 +107,9 @@ struct fetiF_ctx_s {
     int64_t total_u = 0;
     int64_t nelem_total = 0;
     bool has_elems = false;
-    std::vector<int64_t> level_off;
+    std::vector<int64_t> level_off;   // TRSM items of group g, level L: [g * levels + L, .. + 1)
+    std::vector<int32_t> grp_first;   // assembly group g = subdomains [grp_first[g], grp_first[g+1])
+    std::vector<int64_t> syrk_off;    // SYRK tiles of group g: [syrk_off[g], syrk_off[g+1])
     int32_t apply_nch = 1;
     int32_t nbands = 0;
     int32_t nsyrk = 0;
@@ -191,7 +193,7 @@ struct fetiF_ctx_s {
     double* hLbKval = nullptr; // pinned staging of the K_bb values
     int64_t lb_nk = 0;         // K_bb entries over all subdomains
     int32_t lb_nbmax = 0;
-    double* dPart = nullptr;   // 2 x DOT_PARTS
+    double* dPart = nullptr;   // 2 x dot_parts(n_lambda)
     double* dSc = nullptr;     // SC_COUNT scalars
     double* dHist = nullptr;   // ||w_k||^2 history
     double* hHist = nullptr;   // pinned copy

@@ -52,6 +52,7 @@ void options_defaults(const fetiF_options* in, fetiF_options& o)
     if (o.apply_seg != 0 && o.apply_seg != 4 && o.apply_seg != 8) o.apply_seg = 4;
     if (o.trsm_panel <= 0) o.trsm_panel = 48;
     o.trsm_panel = std::max(16, std::min(96, (o.trsm_panel + 15) / 16 * 16));
+    if (o.assembly_groups <= 0) o.assembly_groups = 1;
 }
 
 }  // namespace fetif

@@ -44,22 +44,10 @@ hipError_t project(fetiF_ctx c, const Work& W, const double* in, double* out, hi
     return launch_gs(c->n_lambda, 1.0, -1.0, c->dGptr2, c->dGent2, c->dGv, W.s, in, out, st);
 }
 
-// out = P in and the scalar update `mode` of launch_dot, the sums fused
-// into the projection's last launch: (in.out, in.in) when pair, else
-// (out.out, out.out)
-hipError_t project_dot(fetiF_ctx c, const Work& W, const double* in, double* out, bool pair, int mode,
-                       hipStream_t st)
+// y = P M w with M = I (precond 0) or the lumped preconditioner (precond 1)
+hipError_t precondition(fetiF_ctx c, const Work& W, int precond, const double* w, double* y, hipStream_t st)
 {
-    hipError_t e;
-    if ((e = launch_gt(c->nsub, c->dCoarse, c->dGv, c->dDmap, in, W.t, st)) != hipSuccess) return e;
-    if ((e = launch_gemv(c->ncoarse, c->dAinv, W.t, W.s, st)) != hipSuccess) return e;
-    return launch_gs_dot(c->n_lambda, c->dGptr2, c->dGent2, c->dGv, W.s, in, out, pair ? 1 : 0, mode, c->dPart,
-                         c->dSc, c->dHist, c->hist_cap, st);
-}
-
-// y = P M w with the lumped preconditioner M
-hipError_t precondition(fetiF_ctx c, const Work& W, const double* w, double* y, hipStream_t st)
-{
+    if (!precond) return project(c, W, w, y, st);
     hipError_t e;
     if ((e = launch_lumped_local(c->nsub, c->lb_nbmax, c->dLump, c->dLbUptr, c->dLbUk, c->dLbSgn, c->dLbKptr,
                                  c->dLbKcol, c->dLbKval, c->dLbMb, c->dDmap, w, c->dLbY, st)) != hipSuccess)
@@ -68,11 +56,7 @@ hipError_t precondition(fetiF_ctx c, const Work& W, const double* w, double* y, 
     return project(c, W, W.mz, y, st);
 }
 
-// one iteration of Alg. 1 (the loop body), all scalars on the device.  With
-// M = I, y = P w is still formed (in exact arithmetic it equals w; the second
-// projection removes the rounding left in the range of G, which otherwise
-// slows convergence at tight tolerances), with w.y and w.w taken in its last
-// launch.
+// one iteration of Alg. 1 (the loop body), all scalars on the device
 hipError_t iteration(fetiF_ctx c, const Work& W, int implicit, int precond, double* lam, hipStream_t st)
 {
     hipError_t e;
@@ -82,11 +66,7 @@ hipError_t iteration(fetiF_ctx c, const Work& W, int implicit, int precond, doub
         return e;
     if ((e = launch_update_lr(n, c->dSc, W.p, W.q, lam, W.r, st)) != hipSuccess) return e;
     if ((e = project(c, W, W.r, W.w, st)) != hipSuccess) return e;
-    if (!precond) {
-        if ((e = project_dot(c, W, W.w, W.y, true, 2, st)) != hipSuccess) return e;
-        return launch_update_p(n, 1, c->dSc, W.y, W.p, st);
-    }
-    if ((e = precondition(c, W, W.w, W.y, st)) != hipSuccess) return e;  // y = P M w
+    if ((e = precondition(c, W, precond, W.w, W.y, st)) != hipSuccess) return e;  // y = P M w
     if ((e = launch_dot(n, W.w, W.y, W.w, 2, c->dPart, c->dSc, c->dHist, c->hist_cap, st)) != hipSuccess) return e;
     return launch_update_p(n, 1, c->dSc, W.y, W.p, st);
 }
@@ -181,14 +161,9 @@ fetiF_status pcpg_core(fetiF_ctx c, const double* d, const double* e, double* la
     HIPCHK(c, apply_op(c, implicit, lam, W.q, st));
     HIPCHK(c, launch_axpby(n, 1.0, d, -1.0, W.q, W.r, st));
     HIPCHK(c, project(c, W, W.r, W.w, st));
-    if (!precond) {
-        HIPCHK(c, project_dot(c, W, W.w, W.y, true, 0, st));
-        HIPCHK(c, launch_update_p(n, 0, c->dSc, W.y, W.p, st));
-    } else {
-        HIPCHK(c, precondition(c, W, W.w, W.y, st));
-        HIPCHK(c, launch_update_p(n, 0, c->dSc, W.y, W.p, st));
-        HIPCHK(c, launch_dot(n, W.w, W.y, W.w, 0, c->dPart, c->dSc, c->dHist, c->hist_cap, st));
-    }
+    HIPCHK(c, precondition(c, W, precond, W.w, W.y, st));
+    HIPCHK(c, launch_update_p(n, 0, c->dSc, W.y, W.p, st));
+    HIPCHK(c, launch_dot(n, W.w, W.y, W.w, 0, c->dPart, c->dSc, c->dHist, c->hist_cap, st));
     int32_t it = 0;
     double h0 = 0.0, hk = 0.0;
     if (fixed > 0) {
@@ -291,7 +266,8 @@ extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double*
         for (int32_t outer = 0; outer < 50; ++outer) {
             HIPCHK(c, apply_op(c, 1, lambda_d, W.q, st));
             HIPCHK(c, launch_axpby(n, 1.0, d_d, -1.0, W.q, W.rt, st));
-            HIPCHK(c, project_dot(c, W, W.rt, W.w, false, 3, st));
+            HIPCHK(c, project(c, W, W.rt, W.w, st));
+            HIPCHK(c, launch_dot(n, W.w, W.w, nullptr, 3, c->dPart, c->dSc, nullptr, 0, st));
             double ww = 0.0;
             HIPCHK(c, hipMemcpyAsync(&ww, c->dSc + SC_TMP, sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));

@@ -146,7 +146,7 @@ __device__ void finish_sums(double a, double b, int mode, double* __restrict__ p
     }
 }
 
-// x.y (and x.z when z != NULL) over DOT_PARTS work-groups, then the scalar
+// x.y (and x.z when z != NULL) over dot_parts(n) work-groups, then the scalar
 // update `mode` of finish_sums.  Each thread requests its (up to) four
 // elements of a pass before adding them.
 __global__ __launch_bounds__(NT) void dot_kernel(int64_t n, const double* __restrict__ x,
@@ -172,35 +172,6 @@ __global__ __launch_bounds__(NT) void dot_kernel(int64_t n, const double* __rest
             a += xv[k] * yv[k];
             b += xv[k] * zv[k];
         }
-    }
-    finish_sums(a, b, mode, part, sc, hist, cap, done, sh);
-}
-
-// The projection's last step fused with dot products of its input and
-// output: y[g] = x[g] - sum_{entries of g} Gv[e] . s[koff .. koff+nk) over
-// DOT_PARTS work-groups, then finish_sums(a, b, mode) with (a, b) =
-// (x.y, x.x) when pair != 0, else (y.y, y.y).
-__global__ __launch_bounds__(NT) void gs_dot_kernel(int64_t n, const int32_t* __restrict__ gptr,
-                                                    const GEnt* __restrict__ ents, const double* __restrict__ gv,
-                                                    const double* __restrict__ s, const double* __restrict__ x,
-                                                    double* __restrict__ y, int pair, int mode,
-                                                    double* __restrict__ part, double* __restrict__ sc,
-                                                    double* __restrict__ hist, int32_t cap, unsigned int* done)
-{
-    __shared__ double sh[NT / 64];
-    double a = 0.0, b = 0.0;
-    for (int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x; g < n; g += (int64_t)gridDim.x * NT) {
-        double acc = 0.0;
-        for (int32_t e = gptr[g]; e < gptr[g + 1]; ++e) {
-            const GEnt E = ents[e];
-            const double* v = gv + E.gv;
-            for (int k = 0; k < E.nk; ++k) acc += v[k] * s[E.koff + k];
-        }
-        const double xg = x[g];
-        const double yg = xg - acc;
-        y[g] = yg;
-        a += (pair ? xg : yg) * yg;
-        b += pair ? xg * xg : yg * yg;
     }
     finish_sums(a, b, mode, part, sc, hist, cap, done, sh);
 }
@@ -419,18 +390,9 @@ hipError_t launch_dot(int64_t n, const double* x, const double* y, const double*
 {
     // the completion counter lives in the scalar block, after the scalars
     unsigned int* done = reinterpret_cast<unsigned int*>(sc + SC_COUNT);
-    hipLaunchKernelGGL(dot_kernel, dim3(DOT_PARTS), dim3(NT), 0, st, n, x, y, z, mode, part, sc, hist, hist_cap,
+    static_assert(NT == 256, "dot_parts assumes 256 threads per work-group");
+    hipLaunchKernelGGL(dot_kernel, dim3(dot_parts(n)), dim3(NT), 0, st, n, x, y, z, mode, part, sc, hist, hist_cap,
                        done);
-    return hipGetLastError();
-}
-
-hipError_t launch_gs_dot(int64_t n, const int32_t* gptr, const GEnt* ents, const double* gv, const double* s,
-                         const double* x, double* y, int pair, int mode, double* part, double* sc, double* hist,
-                         int32_t hist_cap, hipStream_t st)
-{
-    unsigned int* done = reinterpret_cast<unsigned int*>(sc + SC_COUNT);
-    hipLaunchKernelGGL(gs_dot_kernel, dim3(DOT_PARTS), dim3(NT), 0, st, n, gptr, ents, gv, s, x, y, pair, mode, part,
-                       sc, hist, hist_cap, done);
     return hipGetLastError();
 }
 

@@ -7,7 +7,16 @@
 namespace fetif {
 
 constexpr int COARSE_MAXK = 6;  // kernel dimension per subdomain (3D elasticity: 6)
-constexpr int DOT_PARTS = 256;  // fixed partial count of the deterministic dot
+// The deterministic dots use up to 256 work-groups of 256 threads
+// (grid-stride beyond), so their partial count depends on n only; the
+// partial buffer holds 2 * dot_parts(n_lambda) values.  More work-groups
+// measured slower: every one of them adds an atomic on the completion
+// counter.
+inline int32_t dot_parts(int64_t n)
+{
+    const int64_t b = (n + 255) / 256;
+    return (int32_t)(b < 1 ? 1 : (b > 256 ? 256 : b));
+}
 
 // solver scalars in device memory
 enum { SC_WY = 0, SC_PQ, SC_DELTA, SC_BETA, SC_WW, SC_TMP, SC_TMP2, SC_K, SC_COUNT };
@@ -42,12 +51,6 @@ hipError_t launch_gs(int64_t n, double alpha, double sgn, const int32_t* gptr, c
 // `mode`; the history index is a device counter (graph-replay safe)
 hipError_t launch_dot(int64_t n, const double* x, const double* y, const double* z, int mode, double* part,
                       double* sc, double* hist, int32_t hist_cap, hipStream_t st);
-// y = x - G s (the last step of the projection), then the scalar update
-// `mode` of launch_dot with the sums (x.y, x.x) when pair != 0, else
-// (y.y, y.y)
-hipError_t launch_gs_dot(int64_t n, const int32_t* gptr, const GEnt* ents, const double* gv, const double* s,
-                         const double* x, double* y, int pair, int mode, double* part, double* sc, double* hist,
-                         int32_t hist_cap, hipStream_t st);
 hipError_t launch_update_lr(int64_t n, const double* sc, const double* p, const double* q, double* lam, double* r,
                             hipStream_t st);
 hipError_t launch_update_p(int64_t n, int use_beta, const double* sc, const double* y, double* p, hipStream_t st);

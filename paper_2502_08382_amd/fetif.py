@@ -45,7 +45,8 @@ class _Opt(ctypes.Structure):
                 ("nthreads", ctypes.c_int32), ("apply_band", ctypes.c_int32),
                 ("trsm_chunk", ctypes.c_int32), ("apply_rows", ctypes.c_int32),
                 ("apply_nontemporal", ctypes.c_int32), ("apply_split", ctypes.c_int32),
-                ("trsm_panel", ctypes.c_int32), ("apply_seg", ctypes.c_int32)]
+                ("trsm_panel", ctypes.c_int32), ("apply_seg", ctypes.c_int32),
+                ("assembly_groups", ctypes.c_int32)]
 
 
 class _PcpgOpt(ctypes.Structure):
@@ -65,7 +66,8 @@ class _Info(ctypes.Structure):
                 ("f_elements", ctypes.c_int64), ("f_tri_elements", ctypes.c_int64),
                 ("trsm_flops", ctypes.c_double), ("syrk_flops", ctypes.c_double),
                 ("factor_flops", ctypes.c_double), ("trsm_levels", ctypes.c_int32),
-                ("apply_groups", ctypes.c_int32), ("apply_elements", ctypes.c_int64)]
+                ("apply_groups", ctypes.c_int32), ("apply_elements", ctypes.c_int64),
+                ("assembly_groups", ctypes.c_int32)]
 
 
 EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply",
@@ -73,7 +75,7 @@ EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply
            "fetiF_last_error", "fetiF_host_factor", "fetiF_hfactor_info", "fetiF_hfactor_export",
            "fetiF_hfactor_supernodes", "fetiF_hfactor_free", "fetiF_profile_enable",
            "fetiF_profile_read", "fetiF_set_apply", "fetiF_apply_implicit", "fetiF_dual_rhs",
-           "fetiF_coarse_rhs", "fetiF_pcpg", "fetiF_primal", "fetiF_set_assembly"]
+           "fetiF_coarse_rhs", "fetiF_pcpg", "fetiF_primal", "fetiF_set_assembly", "fetiF_factor_assemble"]
 
 PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "solves"]
 
@@ -94,6 +96,7 @@ def load_library(path=None):
                                ctypes.POINTER(_Opt)]
     L.fetiF_factor_upload.argtypes = [vp, i32, i32, ctypes.POINTER(vp), vp]
     L.fetiF_assemble.argtypes = [vp, vp]
+    L.fetiF_factor_assemble.argtypes = [vp, ctypes.POINTER(vp), vp]
     L.fetiF_apply.argtypes = [vp, vp, vp, vp]
     L.fetiF_apply_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fetiF_download_F.argtypes = [vp, i32, vp]
@@ -177,10 +180,10 @@ class _SubArrays:
 
 
 def _options(f_storage="f64", leaf_nodes=0, nthreads=0, apply_band=0, trsm_chunk=0, apply_rows=0,
-             apply_nontemporal=-1, apply_split=-1, trsm_panel=0, apply_seg=-1):
+             apply_nontemporal=-1, apply_split=-1, trsm_panel=0, apply_seg=-1, assembly_groups=0):
     prec = _PREC[f_storage] if isinstance(f_storage, str) else int(f_storage)
     return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk, apply_rows, apply_nontemporal, apply_split,
-                trsm_panel, apply_seg)
+                trsm_panel, apply_seg, assembly_groups)
 
 
 class FetiContext:
@@ -215,6 +218,15 @@ class FetiContext:
 
     def assemble(self, stream=None):
         self._check(self.L.fetiF_assemble(self.h, _stream(stream)))
+
+    def factor_assemble(self, k_vals, stream=None):
+        """Factorisation, copy and assembly of every subdomain, pipelined by
+        the context's assembly groups (the C call fetiF_factor_assemble)."""
+        if len(k_vals) != self.nsub:
+            raise ValueError("factor_assemble needs the K_reg values of every subdomain")
+        arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in k_vals]
+        ptrs = (ctypes.c_void_p * len(arrs))(*[_ptr(a) for a in arrs])
+        self._check(self.L.fetiF_factor_assemble(self.h, ptrs, _stream(stream)))
 
     def apply(self, lam, q, stream=None):
         self._check(self.L.fetiF_apply(self.h, _dptr(lam), _dptr(q), _stream(stream)))

@@ -394,3 +394,46 @@ def test_multi_step_new_stiffness_values(torch_cuda):
         say(f"step {step}: F {e_f:.2e} apply {e_q:.2e}")
         assert e_f <= 1e-12 and e_q <= 1e-12
     ctx.close()
+
+
+def test_pipelined_factor_assemble_is_bitwise_equal(torch_cuda):
+    """fetiF_factor_assemble (host factorisation of group g+1 while the device
+    copies and assembles group g) gives bitwise the F~_i of a one-group
+    context's factor upload + assembly, and so does the group context's own
+    assemble; a non-SPD subdomain in a later group leaves nothing uploaded."""
+    from paper_2502_08382_amd.fetif import FetiError
+    prob = config_problem(2, scale=(3, 8))
+    kv = [s.Kreg.data for s in prob.subs]
+    say("pipelined factor+assemble", "nsub", prob.nsub, "groups 5")
+    ref = make_context(prob)
+    upload_and_assemble(ref, prob)
+    ctx = make_context(prob, assembly_groups=5)
+    assert ctx.info()["assembly_groups"] == 5 and ref.info()["assembly_groups"] == 1
+    stream = torch_cuda.cuda.Stream()   # a non-default stream handle (64-bit) through the binding
+    ctx.factor_assemble(kv, stream=stream)
+    stream.synchronize()
+    for i in range(prob.nsub):
+        assert np.array_equal(ctx.download_F(i), ref.download_F(i)), i
+    q_ref = gpu_apply(ref, prob.lam)
+    assert np.array_equal(gpu_apply(ctx, prob.lam), q_ref)
+    Fs = [oracle_F(prob, i) for i in range(prob.nsub)]
+    q_o = feti.apply_explicit(Fs, [s.dual_map for s in prob.subs], prob.lam, prob.n_lambda)
+    assert np.linalg.norm(q_ref - q_o) <= 1e-12 * np.linalg.norm(q_o)
+    # a non-SPD K_reg in the last group
+    bad = [v.copy() for v in kv]
+    A = prob.subs[prob.nsub - 2].Kreg.tocoo()
+    bad[prob.nsub - 2][np.nonzero(A.row == A.col)[0][5]] = -1.0
+    with pytest.raises(FetiError) as e:
+        ctx.factor_assemble(bad)
+    assert e.value.status == 5   # FETIF_ENOTSPD
+    with pytest.raises(FetiError) as e:
+        gpu_apply(ctx, prob.lam)
+    assert e.value.status == 3   # FETIF_ESTATE
+    # the group context's phase-by-phase assemble, then the pipeline again
+    upload_and_assemble(ctx, prob)
+    assert np.array_equal(gpu_apply(ctx, prob.lam), q_ref)
+    ctx.factor_assemble(kv)
+    torch_cuda.cuda.synchronize()
+    assert np.array_equal(gpu_apply(ctx, prob.lam), q_ref)
+    ctx.close()
+    ref.close()

@@ -24,6 +24,15 @@ def _gpu_present():
         return False
 
 
+def test_every_binding_declares_its_argument_types():
+    """Without argtypes ctypes passes Python ints as C int: a 64-bit stream
+    handle or pointer would be cut to 32 bits."""
+    from paper_2502_08382_amd.fetif import EXPORTS, load_library
+    L = load_library()
+    missing = [n for n in EXPORTS if getattr(L, n).argtypes is None]
+    assert not missing, missing
+
+
 def test_library_exports_every_declared_symbol():
     src = open(HEADER).read()
     names = set(re.findall(r"\b(fetiF_[A-Za-z_]+)\s*\(", src))
