@@ -255,21 +255,34 @@ __global__ __launch_bounds__(64 * W) void trsm_level_kernel(const TrsmItem* __re
     }
     __syncthreads();
     const int64_t jbase = (int64_t)s.j0 + it.c0;
+    // row offsets of the wavefront's next row block are requested one block
+    // ahead, so a block's X addresses do not wait for them
+    int64_t ro[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = wv * 16 + q + 4 * r;
+        ro[r] = i < nr ? rowoff[s.rowsoff + i] : 0;
+    }
     for (int rb = wv; rb * 16 < nr; rb += W) {
-        // the target X values first: their loads (row offset, then value)
-        // are in flight while the MFMA chain below runs
+        // the target X values first: their loads are in flight while the
+        // MFMA chain below runs
         double* xr[4];
         double xv[4][W];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = rb * 16 + q + 4 * r;
-            xr[r] = i < nr ? X + rowoff[s.rowsoff + i] + jbase : nullptr;
+            xr[r] = i < nr ? X + ro[r] + jbase : nullptr;
 #pragma unroll
             for (int c = 0; c < W; ++c) xv[r][c] = (xr[r] && c * 16 + j < it.cw) ? xr[r][c * 16 + j] : 0.0;
         }
         d4 acc[W];
 #pragma unroll
         for (int c = 0; c < W; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = (rb + W) * 16 + q + 4 * r;
+            ro[r] = i < nr ? rowoff[s.rowsoff + i] : 0;
+        }
         const int arow = ns + rb * 16 + j;
         const bool av = arow < ns + nr;
         // the row block's L operands of a panel of up to kTrsmMaxNb blocks,
