@@ -171,7 +171,10 @@ fetiF_status fetiF_apply(fetiF_ctx ctx, const double* lambda_d, double* q_d, voi
  * wavefront pair, nontemporal (0/1; -1 keeps) the load policy for F~, split
  * (0/1; -1 keeps) the work split of fetiF_options.apply_split, seg (0, 4 or
  * 8; -1 keeps) the kernel of fetiF_options.apply_seg.  The result of
- * fetiF_apply does not depend on these up to summation order. */
+ * fetiF_apply does not depend on these up to summation order.  A new band
+ * size or split frees the previous apply tables: HIP graphs the caller
+ * captured around fetiF_apply must be captured again (the library's own
+ * captured solver iterations are discarded here). */
 fetiF_status fetiF_set_apply(fetiF_ctx ctx, int32_t band_elems, int32_t rows, int32_t nontemporal,
                              int32_t split, int32_t seg);
 

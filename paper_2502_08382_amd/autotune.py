@@ -90,7 +90,7 @@ def tune_apply(ctx, lam, q, bands=None, rows=(2, 4), nontemporal=(1,), splits=(0
     return out
 
 
-def tune_assembly(ctx, panels=(32, 48, 64, 96), chunks=(32, 64), reps=3, stream=None, verbose=False):
+def tune_assembly(ctx, panels=(32, 48, 64, 96), chunks=(16, 32, 64), reps=3, stream=None, verbose=False):
     """Try every (TRSM panel width, RHS columns per work-group) shape of the
     assembly; install and return the fastest by the TRSM phase time.  The
     context must hold uploaded factors (it is assembled once per trial)."""

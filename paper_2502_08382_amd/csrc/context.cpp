@@ -159,7 +159,8 @@ struct ApplyPlan {
     std::vector<int32_t> seg_ptr; // work-group g handles launch[seg_ptr[g] .. seg_ptr[g+1])
     std::vector<int64_t> band_z;
     std::vector<int32_t> gptr;
-    std::vector<GatherEnt> gent;
+    std::vector<int32_t> zptr;    // global multiplier g sums z[zpos[zptr[g] .. zptr[g+1])]
+    std::vector<int64_t> zpos;
     int64_t total_z = 0;
 };
 
@@ -253,24 +254,38 @@ void plan_apply(fetiF_ctx c, int32_t band_elems, int32_t split, ApplyPlan& A)
         A.seg_ptr.resize(nb + 1);
         for (int64_t k = 0; k <= nb; ++k) A.seg_ptr[k] = (int32_t)k;
     }
+    // gather map: local row a of a subdomain receives the partial sums of
+    // the subdomain's bands from the one holding row a to its last one (each
+    // band's partial vector covers its columns 0 .. r1); multiplier g adds
+    // its (subdomain, row) terms in ascending subdomain order, bands in
+    // order.  Stored flat as positions in the partial vectors.
     const int64_t nl = c->n_lambda;
-    A.gptr.assign(nl + 1, 0);
-    for (int32_t i = 0; i < c->nsub; ++i)
-        for (int32_t g : c->subs[i].dual_map) A.gptr[g + 1]++;
-    for (int64_t g = 0; g < nl; ++g) A.gptr[g + 1] += A.gptr[g];
-    A.gent.resize(A.gptr[nl]);
-    std::vector<int32_t> fill(A.gptr.begin(), A.gptr.end() - 1);
+    std::vector<int64_t> cnt(nl + 1, 0);
     for (int32_t i = 0; i < c->nsub; ++i) {
         const SubPlan& P = c->subs[i];
         int32_t bcur = P.band0;
         for (int32_t a = 0; a < P.m; ++a) {
             while (A.bands[bcur].r1 <= a) ++bcur;
-            GatherEnt e;
-            e.a = a;
-            e.b0 = bcur;
-            e.b1 = P.band0 + P.nband;
-            e.pad = 0;
-            A.gent[fill[P.dual_map[P.sigma[a]]]++] = e;
+            cnt[P.dual_map[P.sigma[a]] + 1] += P.band0 + P.nband - bcur;
+        }
+    }
+    int64_t total_terms = 0;
+    for (int64_t g = 1; g <= nl; ++g) total_terms += cnt[g];
+    if (total_terms > INT32_MAX) {   // not representable: install_apply refuses the plan
+        A.zptr.clear();
+        return;
+    }
+    A.zptr.assign(nl + 1, 0);
+    for (int64_t g = 0; g < nl; ++g) A.zptr[g + 1] = A.zptr[g] + (int32_t)cnt[g + 1];
+    A.zpos.resize(A.zptr[nl]);
+    std::vector<int32_t> fill(A.zptr.begin(), A.zptr.end() - 1);
+    for (int32_t i = 0; i < c->nsub; ++i) {
+        const SubPlan& P = c->subs[i];
+        int32_t bcur = P.band0;
+        for (int32_t a = 0; a < P.m; ++a) {
+            while (A.bands[bcur].r1 <= a) ++bcur;
+            int32_t& f = fill[P.dual_map[P.sigma[a]]];
+            for (int32_t bb = bcur; bb < P.band0 + P.nband; ++bb) A.zpos[f++] = A.band_z[bb] + a;
         }
     }
 }
@@ -283,9 +298,8 @@ void free_apply(fetiF_ctx c)
     c->dBands = nullptr;
     c->dSegPtr = nullptr;
     c->ngroups = 0;
-    c->dBandZ = nullptr;
-    c->dGptr = nullptr;
-    c->dGent = nullptr;
+    c->dZptr = nullptr;
+    c->dZpos = nullptr;
 }
 
 template <typename T>
@@ -313,13 +327,12 @@ hipError_t install_apply(fetiF_ctx c, const ApplyPlan& A)
     if ((e = aalloc(c, &c->dSegPtr, A.seg_ptr.size())) != hipSuccess) return e;
     if ((e = upload(c->dSegPtr, A.seg_ptr)) != hipSuccess) return e;
     c->ngroups = (int32_t)A.seg_ptr.size() - 1;
-    if ((e = aalloc(c, &c->dBandZ, A.band_z.size())) != hipSuccess) return e;
-    if ((e = aalloc(c, &c->dGptr, A.gptr.size())) != hipSuccess) return e;
-    if ((e = aalloc(c, &c->dGent, A.gent.size())) != hipSuccess) return e;
+    if (A.zptr.empty()) return hipErrorInvalidValue;   // more gather terms than int32 indexes
+    if ((e = aalloc(c, &c->dZptr, A.zptr.size())) != hipSuccess) return e;
+    if ((e = aalloc(c, &c->dZpos, A.zpos.size())) != hipSuccess) return e;
     if ((e = upload(c->dBands, A.launch)) != hipSuccess) return e;
-    if ((e = upload(c->dBandZ, A.band_z)) != hipSuccess) return e;
-    if ((e = upload(c->dGptr, A.gptr)) != hipSuccess) return e;
-    if ((e = upload(c->dGent, A.gent)) != hipSuccess) return e;
+    if ((e = upload(c->dZptr, A.zptr)) != hipSuccess) return e;
+    if ((e = upload(c->dZpos, A.zpos)) != hipSuccess) return e;
     c->nbands = (int32_t)A.bands.size();
     c->total_z = A.total_z;
     c->apply_brmax = 0;
@@ -1283,7 +1296,7 @@ extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double*
     }
     HIPCHK(c, t4.stop());
     PhaseTimer t5(c, st, 5);
-    HIPCHK(c, launch_gather(c->prec, c->n_lambda, c->dGptr, c->dGent, c->dBandZ, c->dZ, q_d, st));
+    HIPCHK(c, launch_gather(c->prec, c->n_lambda, c->dZptr, c->dZpos, c->dZ, q_d, st));
     HIPCHK(c, t5.stop());
     return FETIF_OK;
 }

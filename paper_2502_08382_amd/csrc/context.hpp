@@ -152,9 +152,8 @@ struct fetiF_ctx_s {
     int32_t ngroups = 0;
     int32_t apply_brmax = 0;     // most rows of an apply band
     int32_t max_m = 0;           // largest local multiplier count
-    int64_t* dBandZ = nullptr;
-    int32_t* dGptr = nullptr;
-    GatherEnt* dGent = nullptr;
+    int32_t* dZptr = nullptr;    // gather: multiplier g sums z[dZpos[dZptr[g] .. dZptr[g+1])]
+    int64_t* dZpos = nullptr;
     int32_t* dDmap = nullptr;
     double* hStage = nullptr;  // pinned staging of factor values
     hipEvent_t upload_done = nullptr;

@@ -64,14 +64,6 @@ struct Band {
     int32_t pad;
 };
 
-// Gather entry: contributions of local row a of a subdomain to one global
-// multiplier, held by the bands [b0, b1) of that subdomain.
-struct GatherEnt {
-    int32_t a;
-    int32_t b0, b1;
-    int32_t pad;
-};
-
 // Implicit-apply gather entry: one (subdomain, local multiplier) term of a
 // global multiplier, read from the solved vector at `xpos` with `sign`.
 struct XGatherEnt {

@@ -982,19 +982,18 @@ __global__ __launch_bounds__(NT) void apply_seg_kernel(const Band* __restrict__ 
     }
 }
 
+// q[g]: the partial sums of every band that holds a term of multiplier g,
+// read straight from their positions in the partial vectors, in a fixed
+// order (one thread per multiplier; two dependent loads per term).
 template <typename A>
-__global__ __launch_bounds__(NT) void gather_kernel(int64_t n_lambda, const int32_t* __restrict__ gptr,
-                                                    const GatherEnt* __restrict__ ents,
-                                                    const int64_t* __restrict__ band_zoff,
-                                                    const A* __restrict__ z, double* __restrict__ q)
+__global__ __launch_bounds__(NT) void gather_kernel(int64_t n_lambda, const int32_t* __restrict__ zptr,
+                                                    const int64_t* __restrict__ zpos, const A* __restrict__ z,
+                                                    double* __restrict__ q)
 {
     const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (g >= n_lambda) return;
     double acc = 0.0;
-    for (int32_t e = gptr[g]; e < gptr[g + 1]; ++e) {
-        const GatherEnt E = ents[e];
-        for (int32_t bb = E.b0; bb < E.b1; ++bb) acc += (double)z[band_zoff[bb] + E.a];
-    }
+    for (int32_t k = zptr[g]; k < zptr[g + 1]; ++k) acc += (double)z[zpos[k]];
     q[g] = acc;
 }
 
@@ -1235,17 +1234,15 @@ hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* 
     return apply_dispatch<bf16_t>(nch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, st);
 }
 
-hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* gptr, const GatherEnt* ents,
-                         const int64_t* band_zoff, const void* z, double* q, hipStream_t st)
+hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* zptr, const int64_t* zpos, const void* z,
+                         double* q, hipStream_t st)
 {
     if (n_lambda <= 0) return hipSuccess;
     dim3 grid((unsigned)((n_lambda + NT - 1) / NT));
     if (prec == 0)
-        hipLaunchKernelGGL(gather_kernel<double>, grid, dim3(NT), 0, st, n_lambda, gptr, ents, band_zoff,
-                           (const double*)z, q);
+        hipLaunchKernelGGL(gather_kernel<double>, grid, dim3(NT), 0, st, n_lambda, zptr, zpos, (const double*)z, q);
     else
-        hipLaunchKernelGGL(gather_kernel<float>, grid, dim3(NT), 0, st, n_lambda, gptr, ents, band_zoff,
-                           (const float*)z, q);
+        hipLaunchKernelGGL(gather_kernel<float>, grid, dim3(NT), 0, st, n_lambda, zptr, zpos, (const float*)z, q);
     return hipGetLastError();
 }
 

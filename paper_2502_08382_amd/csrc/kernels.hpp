@@ -63,8 +63,9 @@ hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* 
 hipError_t launch_apply_seg(int prec, int segch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
                             int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
                             int32_t capp, int32_t brmax, hipStream_t st);
-hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* gptr, const GatherEnt* ents,
-                         const int64_t* band_zoff, const void* z, double* q, hipStream_t st);
+// q[g] = sum of z[zpos[k]] for k in [zptr[g], zptr[g+1]), in that order
+hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* zptr, const int64_t* zpos, const void* z,
+                         double* q, hipStream_t st);
 
 // elements per 16-byte vector for a storage precision
 inline int prec_vec(int prec) { return prec == 0 ? 2 : (prec == 1 ? 4 : 8); }

@@ -437,3 +437,15 @@ def test_pipelined_factor_assemble_is_bitwise_equal(torch_cuda):
     assert np.array_equal(gpu_apply(ctx, prob.lam), q_ref)
     ctx.close()
     ref.close()
+
+
+def test_create_rejects_more_than_4096_multipliers(torch_cuda):
+    """A subdomain with more than 4096 local multipliers (the apply's row
+    limit) is refused at create with FETIF_ENOTSUP and a message naming m."""
+    from paper_2502_08382_amd.fetif import FetiError
+    prob = make_problem(3, "elasticity", [[20, 20], [20, 20], [20, 20]], 0.0, dirichlet_axis=2, seed=1)
+    assert max(s.m for s in prob.subs) > 4096
+    say("create with m up to", max(s.m for s in prob.subs))
+    with pytest.raises(FetiError) as e:
+        make_context(prob)
+    assert e.value.status == 6 and "4096" in str(e.value)
