@@ -340,13 +340,14 @@ def main():
             ctx2.apply(lam, q2, stream=stream)
             torch.cuda.synchronize()
         same = bool(torch.equal(q, q2))
+        ngroups = ctx2.info()["assembly_groups"]
         ctx2.close()
         th, tp = min(t_host) * 1e3, min(t_pipe) * 1e3
         t_overlap = max(0.0, tp - th)
         result["pipelined_preprocessing"] = {
-            "groups": args.groups, "host_factor_ms": round(th, 3), "factor_copy_assembly_wall_ms": round(tp, 3),
+            "groups": ngroups, "host_factor_ms": round(th, 3), "factor_copy_assembly_wall_ms": round(tp, 3),
             "beyond_host_factor_ms": round(t_overlap, 3), "apply_bitwise_equal": same}
-        log(f"pipelined factorisation + copy + assembly ({args.groups} groups): {tp:.1f} ms wall, host "
+        log(f"pipelined factorisation + copy + assembly ({ngroups} groups): {tp:.1f} ms wall, host "
             f"factorisation alone {th:.1f} ms, apply equal to the one-group context: {same}")
 
     # ---- CPU oracle: implicit apply on host threads, bounded sample

@@ -104,7 +104,8 @@ typedef struct {
 typedef struct {
     fetiF_prec f_storage; /* storage precision of F~_i (default FP64) */
     int32_t leaf_nodes;   /* nested-dissection leaf size in nodes (default 24) */
-    int32_t nthreads;     /* host threads for analysis/factorisation (default: all) */
+    int32_t nthreads;     /* host threads for analysis/factorisation (default: the CPUs of
+                             the process's affinity mask) */
     int32_t apply_band;   /* stored elements of F~ per apply work-group (default 131072) */
     int32_t trsm_chunk;   /* most RHS columns per TRSM work-group: 16, 32 or 64 (default 64) */
     int32_t apply_rows;   /* rows of F~ per pass of a wavefront pair in apply, 2 or 4 (default 4) */
@@ -115,7 +116,8 @@ typedef struct {
     int32_t apply_seg;    /* apply kernel: 0 whole rows per wavefront pair; 4 or 8 column segments
                              of that many 1 KiB chunks (default 4) */
     int32_t assembly_groups; /* contiguous subdomain groups of about equal factor size, each
-                                with its own assembly schedule (default 1; at most nsub):
+                                with its own assembly schedule (default 1; fewer when a group
+                                would hold fewer subdomains than there are host threads):
                                 fetiF_factor_assemble factors group g+1 on the host while the
                                 device copies and assembles group g */
 } fetiF_options;

@@ -1,6 +1,8 @@
 // The fetiF context: preparation (ordering, symbolic analysis, schedules,
 // device structures), per-step factorisation + upload, assembly and
 // application (paper Alg. 2 and Sec. IV-B).
+#include <sched.h>
+
 #include "context.hpp"
 
 thread_local std::string fetif::g_create_error;
@@ -355,10 +357,12 @@ struct TrsmPlan {
 };
 
 // Assembly groups: contiguous subdomain ranges of about equal factor size
-// (at most G of them, none empty); first[g] .. first[g+1] is group g.
+// (at most G of them, each of at least one subdomain per host thread so the
+// group's factorisation keeps every thread busy); first[g] .. first[g+1] is
+// group g.
 std::vector<int32_t> plan_groups(fetiF_ctx c, int32_t G)
 {
-    G = std::max(1, std::min(G, c->nsub));
+    G = std::max(1, std::min(G, c->nsub / std::max(1, c->nthreads)));
     int64_t total = 0;
     for (int32_t i = 0; i < c->nsub; ++i) total += c->subs[i].sym.nvals;
     std::vector<int32_t> first{0};
@@ -544,7 +548,15 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     c->nsub = nsub;
     c->opt = opt;
     c->prec = (int)opt.f_storage;
-    unsigned hc = std::thread::hardware_concurrency();
+    // default: the CPUs this process may run on (the affinity mask), not
+    // every CPU of the machine
+    unsigned hc = 0;
+    {
+        cpu_set_t cs;
+        CPU_ZERO(&cs);
+        if (sched_getaffinity(0, sizeof(cs), &cs) == 0) hc = (unsigned)CPU_COUNT(&cs);
+        if (!hc) hc = std::thread::hardware_concurrency();
+    }
     c->nthreads = opt.nthreads > 0 ? opt.nthreads : (int)(hc ? hc : 1);
     c->subs.resize(nsub);
 
@@ -1090,9 +1102,10 @@ namespace {
 
 // Host factorisation of subdomains [first, first+count) and the asynchronous
 // copy of their values on st (no wait for earlier copies: every subdomain has
-// its own staging area).  Chunks of about 64 MiB of factor values: the copy
-// of a chunk and its diagonal-block inverses run on the stream while the host
-// factors the next chunk.
+// its own staging area).  Chunks of at least 64 MiB of factor values and at
+// least one subdomain per host thread (a shorter rest joins the last chunk):
+// the copy of a chunk and its diagonal-block inverses run on the stream while
+// the host factors the next chunk.
 fetiF_status upload_range(fetiF_ctx c, int32_t first, int32_t count, const double* const* k_vals, hipStream_t st)
 {
     // any upload replaces factor values: F~ must be assembled again, and on
@@ -1102,7 +1115,8 @@ fetiF_status upload_range(fetiF_ctx c, int32_t first, int32_t count, const doubl
     for (int32_t k0 = 0; k0 < count;) {
         int32_t k1 = k0;
         int64_t vals = 0;
-        while (k1 < count && (k1 == k0 || vals < kChunkVals)) vals += c->subs[first + k1++].sym.nvals;
+        while (k1 < count && (k1 - k0 < c->nthreads || vals < kChunkVals)) vals += c->subs[first + k1++].sym.nvals;
+        if (count - k1 < c->nthreads) k1 = count;
         std::vector<int32_t> bad(k1 - k0, -1);
         parallel_for(k1 - k0, c->nthreads, [&](int32_t k) {
             const SubPlan& P = c->subs[first + k0 + k];

@@ -407,7 +407,7 @@ def test_pipelined_factor_assemble_is_bitwise_equal(torch_cuda):
     say("pipelined factor+assemble", "nsub", prob.nsub, "groups 5")
     ref = make_context(prob)
     upload_and_assemble(ref, prob)
-    ctx = make_context(prob, assembly_groups=5)
+    ctx = make_context(prob, assembly_groups=5, nthreads=4)   # groups hold >= nthreads subdomains
     assert ctx.info()["assembly_groups"] == 5 and ref.info()["assembly_groups"] == 1
     stream = torch_cuda.cuda.Stream()   # a non-default stream handle (64-bit) through the binding
     ctx.factor_assemble(kv, stream=stream)
