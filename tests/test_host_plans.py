@@ -1,0 +1,148 @@
+"""The library's host code (planners, schedules, group and chunk bookkeeping,
+argument checks) under AddressSanitizer, on the CPU.
+
+The host sources are compiled with g++ -fsanitize=address against a test
+double of the HIP runtime (tests/hostsim: device memory is host memory, no
+kernel runs), then driven through the Python binding in a child process with
+the sanitizer preloaded: every create / upload / assemble / pipelined
+assemble / apply / solver path for several shapes and options, and the error
+paths.  Any out-of-bounds or use-after-free access in host code fails the
+test.  Nothing numeric is checked here (no kernel runs); the GPU tests do that.
+"""
+import os
+import re
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2502_08382_amd", "csrc")
+HOSTSIM = os.path.join(ROOT, "tests", "hostsim")
+SOURCES = ["context.cpp", "solver.cpp", "host_api.cpp", "host_sparse.cpp"]
+
+
+def _libasan():
+    try:
+        p = subprocess.run(["g++", "-print-file-name=libasan.so"], capture_output=True, text=True, check=True)
+    except (OSError, subprocess.CalledProcessError):
+        return None
+    path = p.stdout.strip()
+    return path if os.path.isabs(path) and os.path.exists(path) else None
+
+
+@pytest.fixture(scope="module")
+def hostsim_lib(tmp_path_factory):
+    if shutil.which("g++") is None or _libasan() is None:
+        pytest.skip("g++ with AddressSanitizer is not available")
+    out = tmp_path_factory.mktemp("hostsim")
+    # every kernel launcher declared in the two launcher headers returns
+    # success without running anything
+    stubs = ['#include "kernels.hpp"', '#include "solver_kernels.hpp"', "namespace fetif {"]
+    for h in ("kernels.hpp", "solver_kernels.hpp"):
+        with open(os.path.join(CSRC, h)) as f:
+            text = f.read()
+        for m in re.finditer(r"hipError_t\s+(launch_\w+)\s*\(([^;]*?)\);", text, re.S):
+            stubs.append(f"hipError_t {m.group(1)}({m.group(2)}) {{ return hipSuccess; }}")
+    stubs.append("}")
+    stub_cpp = out / "launch_stubs.cpp"
+    stub_cpp.write_text("\n".join(stubs) + "\n")
+    lib = out / "libfetiF_hostsim.so"
+    cmd = (["g++", "-std=c++17", "-O1", "-g", "-fPIC", "-shared", "-fsanitize=address", "-fno-omit-frame-pointer",
+            "-I" + HOSTSIM, "-I" + CSRC, os.path.join(HOSTSIM, "runtime_stand_in.cpp"), str(stub_cpp)]
+           + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", str(lib), "-lpthread"])
+    subprocess.run(cmd, check=True)
+    return str(lib)
+
+
+DRIVER = r'''
+import sys
+import numpy as np
+sys.path.insert(0, ROOT)
+from paper_2502_08382_amd.fetif import load_library, FetiContext, FetiError
+from paper_2502_08382_amd import subdomain_dict
+from synth import config_problem, make_problem
+load_library(LIB)
+ST = 0x7f0012345670           # any 64-bit stream handle: the test double ignores it
+
+
+def expect(status, fn):
+    try:
+        fn()
+    except FetiError as e:
+        assert e.status == status, (e.status, str(e))
+        return
+    raise AssertionError("expected status %d" % status)
+
+
+def flow(prob, with_elements=False, **opts):
+    subs = [subdomain_dict(s, with_elements) for s in prob.subs]
+    kv = [s.Kreg.data for s in prob.subs]
+    ctx = FetiContext(subs, prob.n_lambda, device=0, **opts)
+    info = ctx.info()
+    assert 1 <= info["assembly_groups"] <= prob.nsub
+    expect(3, lambda: ctx.assemble(stream=ST))            # before any upload
+    ctx.factor_upload(kv, stream=ST)
+    ctx.assemble(stream=ST)
+    for panel, chunk in ((16, 16), (48, 64), (96, 32)):
+        ctx.set_assembly(panel, chunk)
+        ctx.assemble(stream=ST)
+        ctx.factor_assemble(kv, stream=ST)
+    n = prob.n_lambda
+    lam = np.zeros(n)
+    q = np.zeros(n)
+    for seg in (0, 4, 8):
+        for split in (0, 1):
+            for band in (1, 3000, 0):
+                ctx.set_apply(band, 2, 1, split, seg)
+                ctx.apply(lam.ctypes.data, q.ctypes.data, stream=ST)
+    ctx.apply_implicit(lam.ctypes.data, q.ctypes.data, stream=ST)
+    f = np.zeros(sum(s.n for s in prob.subs))
+    e = np.zeros(sum(s.R.shape[1] for s in prob.subs))
+    d = np.zeros(n)
+    ctx.coarse_rhs(f.ctypes.data, e.ctypes.data, stream=ST)
+    ctx.dual_rhs(f.ctypes.data, d.ctypes.data, stream=ST)
+    ctx.pcpg(d.ctypes.data, e.ctypes.data, lam.ctypes.data, fixed_iters=3, use_graph=True, stream=ST)
+    ctx.pcpg(d.ctypes.data, e.ctypes.data, lam.ctypes.data, fixed_iters=2, precond=1, stream=ST)
+    if with_elements:
+        ne = sum(len(s.theta) for s in prob.subs)
+        dth = np.zeros(ne)
+        ctx.apply_backward(lam.ctypes.data, lam.ctypes.data, q.ctypes.data, dth.ctypes.data, stream=ST)
+    for i in range(prob.nsub):
+        ctx.download_F(i)
+    # a non-SPD K_reg in the last subdomain: nothing counts as uploaded after it
+    bad = [v.copy() for v in kv]
+    A = prob.subs[-1].Kreg.tocoo()
+    bad[-1][np.nonzero(A.row == A.col)[0][2]] = -1.0
+    expect(5, lambda: ctx.factor_assemble(bad, stream=ST))
+    expect(3, lambda: ctx.apply(lam.ctypes.data, q.ctypes.data, stream=ST))
+    expect(5, lambda: ctx.factor_upload(bad, stream=ST))
+    ctx.factor_upload(kv, stream=ST)
+    ctx.assemble(stream=ST)
+    ctx.close()
+
+
+flow(config_problem(1), with_elements=True)
+flow(config_problem(5, scale=(2, 5)), with_elements=True, assembly_groups=3, nthreads=2)
+flow(config_problem(2, scale=(3, 6), elem="simplex"), assembly_groups=8, nthreads=1, f_storage="f32")
+flow(make_problem(3, "elasticity", [[3, 4, 2], [3, 2], [2, 3]], 0.3, dirichlet_axis=2, seed=3),
+     assembly_groups=5, nthreads=2, f_storage="bf16")
+flow(make_problem(2, "heat", [[7, 13, 5], [9, 11]], 0.5, dirichlet_axis=0, seed=9), assembly_groups=100)
+# more than 4096 multipliers in a subdomain: refused at create
+big = make_problem(3, "elasticity", [[20, 20], [20, 20], [20, 20]], 0.0, dirichlet_axis=2, seed=1)
+expect(6, lambda: FetiContext([subdomain_dict(s) for s in big.subs], big.n_lambda, device=0))
+print("hostsim flows done")
+'''
+
+
+def test_host_code_under_address_sanitizer(hostsim_lib):
+    env = dict(os.environ)
+    env["LD_PRELOAD"] = _libasan()
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=0"
+    code = f"ROOT = {ROOT!r}\nLIB = {hostsim_lib!r}\n" + DRIVER
+    p = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
+    out = p.stdout + p.stderr
+    assert "AddressSanitizer" not in out, out[-4000:]
+    assert p.returncode == 0, out[-4000:]
+    assert "hostsim flows done" in p.stdout
