@@ -66,6 +66,9 @@ def main():
                          "timed steps (0: skip that measurement)")
     ap.add_argument("--backward", action="store_true",
                     help="also time fetiF_apply_backward (dlambda and the element adjoint dtheta)")
+    ap.add_argument("--pmc-assemble", type=int, default=0, metavar="N",
+                    help="profiling mode: upload the factors, install the TRSM shape 96/32 (the tuned one on "
+                         "the 3D heat workloads), run N assemblies and exit")
     ap.add_argument("--pmc-apply", type=int, default=0, metavar="N",
                     help="profiling mode: assemble, run N applies in the tuned shape, then copy a 1 GiB "
                          "buffer three times (the counter calibration) and exit")
@@ -110,6 +113,18 @@ def main():
     def shape_key(t):
         return (f"{wname}|{args.prec}|seg{t.get('seg', 0)}-split{t['split']}-band{t['band']}"
                 f"-rows{t['rows']}-nt{t['nontemporal']}")
+
+    if args.pmc_assemble:
+        with torch.cuda.stream(stream):
+            ctx.factor_upload(kvals, stream=stream)
+            ctx.set_assembly(96, 32)
+            for _ in range(args.pmc_assemble):
+                ctx.assemble(stream=stream)
+            torch.cuda.synchronize()
+        log(f"{args.pmc_assemble} assemblies done; trsm flops {info['trsm_flops']:.6g}, "
+            f"syrk flops {info['syrk_flops']:.6g}")
+        ctx.close()
+        return
 
     if args.pmc_apply:
         from paper_2502_08382_amd.autotune import tune_apply
