@@ -321,6 +321,18 @@ def main():
     # solver time: HIP events around the PCPG call on its stream
     t_solve_ms = float(np.mean([a.elapsed_time(b) for a, b in pcpg_events]))
     result["solver"]["ms"] = round(t_solve_ms, 3)
+    if refine:
+        # the reduced-precision solution against an FP64 one: PCPG to 1e-12
+        # with the implicit FP64 operator (the factors), outside the timing
+        sol64 = torch.empty_like(sol)
+        with torch.cuda.stream(stream):
+            r64 = ctx.pcpg(d, e, sol64, tol=1e-12, implicit=True, max_iters=20000, use_graph=False,
+                           stream=stream)
+        torch.cuda.synchronize()
+        err = float(torch.linalg.vector_norm(sol - sol64) / torch.linalg.vector_norm(sol64))
+        result["solver"]["lambda_rel_err_vs_fp64"] = err
+        result["solver"]["fp64_reference"] = f"implicit FP64 PCPG to 1e-12 ({r64['iters']} iterations)"
+        log(f"lambda vs the FP64 solution: rel err {err:.2e} ({r64['iters']} FP64 iterations)")
     if t_pcpg_graph is not None:
         result["solver"]["hip_graph_ms_per_iter"] = round(t_pcpg_graph / args.iters, 4)
     result["solver"]["ms_per_iter"] = round(t_solve_ms / max(1, solver[-1]["iters"]), 4)
