@@ -193,7 +193,7 @@ __global__ __launch_bounds__(NT) void diag_inverse_kernel(const InvItem* __restr
 // range.  Items of one level touch disjoint RHS column ranges, so the
 // updates need no atomics.
 template <int W>
-__global__ __launch_bounds__(64 * W) void trsm_level_kernel(const TrsmItem* __restrict__ items, int32_t nbmax,
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 4 ? 2 : 3))) void trsm_level_kernel(const TrsmItem* __restrict__ items, int32_t nbmax,
                                   const DevSN* __restrict__ sns, const double* __restrict__ L,
                                   const double* __restrict__ Linv, const int64_t* __restrict__ rowoff,
                                   double* __restrict__ X)
@@ -224,24 +224,36 @@ __global__ __launch_bounds__(64 * W) void trsm_level_kernel(const TrsmItem* __re
         }
         for (int rb = 0; rb < nb; ++rb) {
             d4 acc = xin;
+            // every L operand of the block's chain and its diagonal inverse
+            // are requested together: one memory latency per row block
+            // instead of one per 16-column step of the chain
+            const int arow = rb * 16 + j;
+            const bool av = arow < ns;
+            double ap[kTrsmMaxNb - 1][4];
+#pragma unroll
+            for (int kb = 0; kb < kTrsmMaxNb - 1; ++kb)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int kc = kb * 16 + 4 * kk + q;
+                    ap[kb][kk] = (kb < rb && av) ? -P[(int64_t)kc * d + arow] : 0.0;
+                }
+            double pi[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) pi[kk] = PI[rb * 256 + (4 * kk + q) * 16 + j];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = (rb + 1) * 16 + q + 4 * r;
                 xin[r] = (cv && row < ns) ? xs[(int64_t)row * s.w] : 0.0;
             }
-            const int arow = rb * 16 + j;
-            const bool av = arow < ns;
-            for (int kb = 0; kb < rb; ++kb) {
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const int kc = kb * 16 + 4 * kk + q;
-                    const double a = av ? -P[(int64_t)kc * d + arow] : 0.0;
-                    acc = mfma16(a, sx[(kb * 4 + kk) * 64 + lane], acc);
-                }
+            for (int kb = 0; kb < kTrsmMaxNb - 1; ++kb) {
+                if (kb >= rb) break;                     // wavefront-uniform
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) acc = mfma16(ap[kb][kk], sx[(kb * 4 + kk) * 64 + lane], acc);
             }
             d4 xn = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) xn = mfma16(PI[rb * 256 + (4 * kk + q) * 16 + j], acc[kk], xn);
+            for (int kk = 0; kk < 4; ++kk) xn = mfma16(pi[kk], acc[kk], xn);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 sx[(rb * 4 + r) * 64 + lane] = xn[r];
