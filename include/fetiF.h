@@ -114,7 +114,8 @@ typedef struct {
                              1 equal shares of all stored elements, one per work-group */
     int32_t trsm_panel;   /* most supernode columns per TRSM panel, a multiple of 16 up to 96 (default 48) */
     int32_t apply_seg;    /* apply kernel: 0 whole rows per wavefront pair; 4 or 8 column segments
-                             of that many 1 KiB chunks (default 4) */
+                             of that many 1 KiB chunks (default 4; with 8 the rows per pass
+                             are 2 whatever apply_rows says) */
     int32_t assembly_groups; /* contiguous subdomain groups of about equal factor size, each
                                 with its own assembly schedule (default 1; fewer when a group
                                 would hold fewer subdomains than there are host threads):

@@ -81,7 +81,11 @@ def flow(prob, with_elements=False, **opts):
     kv = [s.Kreg.data for s in prob.subs]
     ctx = FetiContext(subs, prob.n_lambda, device=0, **opts)
     info = ctx.info()
-    assert 1 <= info["assembly_groups"] <= prob.nsub
+    assert 1 <= info["assembly_groups"] <= min(prob.nsub, opts.get("assembly_groups", 1))
+    assert info["nsub"] == prob.nsub and info["n_lambda"] == prob.n_lambda
+    assert info["sum_m"] == sum(s.m for s in prob.subs)
+    assert info["f_tri_elements"] == sum(s.m * (s.m + 1) // 2 for s in prob.subs)
+    assert info["apply_elements"] >= info["f_tri_elements"] and info["trsm_levels"] > 0
     expect(3, lambda: ctx.assemble(stream=ST))            # before any upload
     ctx.factor_upload(kv, stream=ST)
     ctx.assemble(stream=ST)
