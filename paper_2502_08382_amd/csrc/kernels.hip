@@ -539,6 +539,19 @@ __global__ __launch_bounds__(NT) void elem_adjoint_kernel(int64_t nelem, const E
 
 // ---------------------------------------------------------------- SYRK
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// 8 bytes per lane from a buffer descriptor covering [base, base + nbytes):
+// lanes whose bytes fall outside (a negative offset wraps to a large one)
+// read zero, so the loads need no branches.
+__device__ __forceinline__ double load8_range(const double* base, uint32_t nbytes, int lane_off)
+{
+    __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)nbytes, 0x00020000);
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, 0, 0);
+    return __hiloint2double((int)v.y, (int)v.x);
+}
+
 constexpr int ST = 64;   // output tile edge
 constexpr int SK = 16;   // rows of X per LDS stage
 constexpr int SP = ST + 2;
@@ -563,7 +576,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sy
     constexpr int U = (SK * ST) / NT;   // staged values per thread and operand
     const SyrkTile t = tiles[blockIdx.x];
     if (t.m == 0) return;  // padding tile of the die-aware order (whole work-group)
-    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int q = lane >> 4, j = lane & 15;
     const int wi = wv >> 1, wj = wv & 1;
     const int ca0 = t.ta * ST, cb0 = t.tb * ST;
@@ -578,18 +591,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sy
     int nst = 0;
     for (int l = t.list0; l < t.list1; ++l) nst += (sns[lists[l]].ncols + SK - 1) / SK;
     int fl = t.list0, fk = 0;
+    // A wavefront's load u reads one X row of the stage (row wv + 4u, lane =
+    // column): a buffer descriptor over that row's RHS range returns zero
+    // for the columns outside it, for rows past the supernode (empty range)
+    // and for the B operand of a diagonal tile, so every load is issued
+    // unconditionally and the compiler waits only for the stage it stages.
+    static_assert(ST == 64 && NT == 256, "one X row per wavefront and load");
     auto fetch = [&](double (&ra)[U], double (&rb)[U]) {
         const DevSN s = sns[lists[fl]];
+        const int la = (ca0 + lane - s.j0) * 8, lb = (cb0 + lane - s.j0) * 8;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int idx = tid + u * NT;
-            const int kk = idx / ST, cc = idx - kk * ST;
-            const int k = fk + kk;
-            const int ja = ca0 + cc - s.j0, jb = cb0 + cc - s.j0;
-            const bool kin = k < s.ncols;
-            const double* xr = X + s.xoff + (int64_t)k * s.w;
-            ra[u] = (kin && ja >= 0 && ja < s.w) ? xr[ja] : 0.0;
-            rb[u] = (!diag && kin && jb >= 0 && jb < s.w) ? xr[jb] : 0.0;
+            const int k = fk + wv + 4 * u;
+            const int kin = k < s.ncols ? 1 : 0;
+            // rows past the supernode: an empty range at row 0
+            const double* xr = X + s.xoff + (int64_t)(k * kin) * s.w;
+            const uint32_t nb = (uint32_t)(s.w * kin) * 8u;
+            ra[u] = load8_range(xr, nb, la);
+            rb[u] = load8_range(xr, diag ? 0u : nb, lb);
         }
         fk += SK;
         if (fk >= s.ncols) {
