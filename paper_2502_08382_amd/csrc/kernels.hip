@@ -147,6 +147,19 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// 8 bytes per lane from a buffer descriptor covering [base, base + nbytes):
+// lanes whose bytes fall outside (a negative offset wraps to a large one)
+// read zero, so the loads need no branches.
+__device__ __forceinline__ double load8_range(const double* base, uint32_t nbytes, int lane_off)
+{
+    __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)nbytes, 0x00020000);
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, 0, 0);
+    return __hiloint2double((int)v.y, (int)v.x);
+}
+
 // Inverse of one 16x16 lower-triangular diagonal block of a supernode panel
 // (rows/columns beyond the supernode are the identity).  Thread j of the
 // block forms column j by forward substitution.  Stored column-major.
@@ -214,37 +227,44 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 4 ?
         const int col = it.c0 + cbeg + j;                // column relative to j0
         const bool cv = (cbeg + j) < it.cw;
         const double* __restrict__ PI = Linv + s.linv;
-        double* __restrict__ xs = X + s.xoff + col;      // X_s[row][col] = xs[row * w]
-        // X values of row block rb + 1 are requested while block rb is solved
-        d4 xin;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = q + 4 * r;
-            xin[r] = (cv && row < ns) ? xs[(int64_t)row * s.w] : 0.0;
-        }
-        for (int rb = 0; rb < nb; ++rb) {
-            d4 acc = xin;
-            // every L operand of the block's chain and its diagonal inverse
-            // are requested together: one memory latency per row block
-            // instead of one per 16-column step of the chain
+        // Row block rb's operands -- the chain's L entries, the diagonal
+        // inverse and the X rows -- are requested one row block ahead,
+        // during block rb - 1's chain.  The loads go through buffer
+        // descriptors over the panel, its inverses and its X block, so an
+        // entry outside them (a lane past the panel, the block after the
+        // last) reads zero without a branch and the compiler waits only for
+        // the block in use.
+        double* __restrict__ xsb = X + s.xoff;           // X_s[row][col] at row * w + col
+        const uint32_t l_bytes = (uint32_t)ns * (uint32_t)d * 8u;
+        const uint32_t pi_bytes = (uint32_t)nb * 256u * 8u;
+        const uint32_t x_bytes = (uint32_t)ns * (uint32_t)s.w * 8u;
+        constexpr int kOut = 0x7ffffff0;                 // beyond every range
+        auto load_ops = [&](int rb, double (&ap)[kTrsmMaxNb - 1][4], double (&pi)[4], d4& xv) {
             const int arow = rb * 16 + j;
             const bool av = arow < ns;
-            double ap[kTrsmMaxNb - 1][4];
 #pragma unroll
             for (int kb = 0; kb < kTrsmMaxNb - 1; ++kb)
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const int kc = kb * 16 + 4 * kk + q;
-                    ap[kb][kk] = (kb < rb && av) ? -P[(int64_t)kc * d + arow] : 0.0;
+                    const int off = (kb < rb && av) ? (kc * d + arow) * 8 : kOut;
+                    ap[kb][kk] = -load8_range(P, l_bytes, off);
                 }
-            double pi[4];
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) pi[kk] = PI[rb * 256 + (4 * kk + q) * 16 + j];
+            for (int kk = 0; kk < 4; ++kk) pi[kk] = load8_range(PI, pi_bytes, (rb * 256 + (4 * kk + q) * 16 + j) * 8);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = (rb + 1) * 16 + q + 4 * r;
-                xin[r] = (cv && row < ns) ? xs[(int64_t)row * s.w] : 0.0;
+                const int row = rb * 16 + q + 4 * r;
+                xv[r] = load8_range(xsb, x_bytes, (cv && row < ns) ? (row * s.w + col) * 8 : kOut);
             }
+        };
+        double ap[kTrsmMaxNb - 1][4], pi[4];
+        d4 xin;
+        load_ops(0, ap, pi, xin);
+        for (int rb = 0; rb < nb; ++rb) {
+            d4 acc = xin;
+            double apn[kTrsmMaxNb - 1][4], pin[4];
+            load_ops(rb + 1, apn, pin, xin);
 #pragma unroll
             for (int kb = 0; kb < kTrsmMaxNb - 1; ++kb) {
                 if (kb >= rb) break;                     // wavefront-uniform
@@ -258,8 +278,14 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 4 ?
             for (int r = 0; r < 4; ++r) {
                 sx[(rb * 4 + r) * 64 + lane] = xn[r];
                 const int row = rb * 16 + q + 4 * r;
-                if (cv && row < ns) xs[(int64_t)row * s.w] = xn[r];
+                if (cv && row < ns) xsb[(int64_t)row * s.w + col] = xn[r];
             }
+#pragma unroll
+            for (int kb = 0; kb < kTrsmMaxNb - 1; ++kb)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) ap[kb][kk] = apn[kb][kk];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) pi[kk] = pin[kk];
         }
     } else {
         // no columns: a zero block, so phase 2 may multiply every block
@@ -539,18 +565,6 @@ __global__ __launch_bounds__(NT) void elem_adjoint_kernel(int64_t nelem, const E
 
 // ---------------------------------------------------------------- SYRK
 
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-// 8 bytes per lane from a buffer descriptor covering [base, base + nbytes):
-// lanes whose bytes fall outside (a negative offset wraps to a large one)
-// read zero, so the loads need no branches.
-__device__ __forceinline__ double load8_range(const double* base, uint32_t nbytes, int lane_off)
-{
-    __amdgpu_buffer_rsrc_t r =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)nbytes, 0x00020000);
-    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, 0, 0);
-    return __hiloint2double((int)v.y, (int)v.x);
-}
 
 constexpr int ST = 64;   // output tile edge
 constexpr int SK = 16;   // rows of X per LDS stage
