@@ -246,6 +246,17 @@ def main():
         t_backward = event_time(lambda: ctx.apply_backward(g_d, lam, dl, dth, stream=stream), 10)
         log(f"apply_backward (dlambda + dtheta) {t_backward:.3f} ms")
 
+    # a plain streaming read of the same byte count (torch's sum over a
+    # resident buffer), the practical read ceiling the band kernel is set
+    # against beside the nominal 8 TB/s
+    nread = max(1, int(info["f_tri_elements"]) * {"f64": 8, "f32": 4, "bf16": 2}[args.prec] // 8)
+    rbuf = torch.ones(nread, dtype=torch.float64, device=dev)
+    rsum = torch.empty((), dtype=torch.float64, device=dev)
+    t_read = event_time(lambda: torch.sum(rbuf, dim=0, out=rsum), 20)
+    read_gbs = nread * 8 / (t_read * 1e-3) / 1e9
+    del rbuf
+    log(f"plain read of {nread * 8 / 1e9:.3f} GB (torch sum): {t_read * 1e3:.1f} us, {read_gbs:.0f} GB/s")
+
     K = args.steps
     ms = {p: v[0] for p, v in prof.items()}
     cnt = {p: max(1, v[1]) for p, v in prof.items()}
@@ -308,6 +319,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": apply_kernel, "achieved": round(band_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(band_gbs / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_launch": int(band_bytes)},
+        "plain_read_reference": {"kernel": "torch.sum over a resident buffer of the operator's bytes",
+                                 "bytes": int(nread * 8), "us": round(t_read * 1e3, 1),
+                                 "GB/s": round(read_gbs, 1), "band_kernel_vs_it": round(band_gbs / read_gbs, 4)},
     }
 
     if tune is not None:
