@@ -75,8 +75,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
-              "is described in DESIGN.md and is not run.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the subdomains would shard "
+              "over GPUs with one process each, and that path is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
