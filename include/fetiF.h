@@ -128,7 +128,9 @@ typedef struct {
  * threads, the work schedules of assembly and application, and the device
  * memory for factors, X_i, F~_i and the dual-vector maps, with the constant
  * structures copied to the device.  `device` is the HIP ordinal.  On success
- * *out owns all of it until fetiF_destroy.  Synchronous. */
+ * *out owns all of it until fetiF_destroy.  Synchronous.  FETIF_ENOTSUP if a
+ * supernode's TRSM panel (up to 96 columns of ncols + nrows entries) spans
+ * more than 2^31 bytes: the kernels address a panel with 32-bit offsets. */
 fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambda, int32_t nsub,
                           const fetiF_subdomain* subs, const fetiF_options* opt);
 

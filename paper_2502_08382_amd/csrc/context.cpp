@@ -599,6 +599,12 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         const int32_t ns = (int32_t)S.sn.size();
         for (int32_t s = 0; s < ns; ++s) {
             const Supernode& x = S.sn[s];
+            // the TRSM reads a panel (at most 96 of the supernode's columns,
+            // each of ld = ncols + nrows entries) through 32-bit byte offsets
+            if ((int64_t)std::min<int32_t>(x.ncols, 96) * (x.ncols + x.nrows) * 8 > INT32_MAX) {
+                delete c;
+                return fail(nullptr, FETIF_ENOTSUP, "a supernode's panel exceeds 2^31 bytes");
+            }
             DevSN d;
             d.lval = lb + x.val_off;
             {
