@@ -1,8 +1,15 @@
 """Python front of the oracle's C implicit apply (test infrastructure).
 
-The fill-reducing order comes from a library routine (SuperLU's multiple
-minimum degree on A^T+A, via scipy), taken only as a permutation; the
-factorisation and the solves are the oracle's own plain C code.
+TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the library.
+
+The fill-reducing order is only a permutation (the factor of the permuted
+matrix represents the same K_reg^{-1}): by default a geometric nested
+dissection of the subdomain's grid nodes written here (plane separators
+through the median of the longest axis, the order the paper's CPU solvers
+get from METIS in spirit), or a library routine (SuperLU's multiple minimum
+degree on A^T+A, via scipy).  The factorisation, the solves and the explicit
+assembly are the oracle's own plain C code.
 """
 from __future__ import annotations
 
@@ -46,8 +53,43 @@ def _load():
         L.orc_apply.argtypes = [vp, dp, dp, ip, ip]
         L.orc_nnz.restype = ctypes.c_long
         L.orc_nnz.argtypes = [vp, ip]
+        L.orc_opnorm_all.argtypes = [vp, ip, dp, ip]
+        L.orc_kappa_all.argtypes = [vp, ip, dp, ip]
+        L.orc_assemble_all.argtypes = [vp, ip]
+        L.orc_get_F.restype = ip
+        L.orc_get_F.argtypes = [vp, ip, dp]
+        L.orc_apply_explicit.argtypes = [vp, dp, dp, ip, ip]
         _lib = L
     return _lib
+
+
+def nd_order(coords, dpn, leaf=64):
+    """Nested-dissection order (new -> old DOF) of a structured grid
+    subdomain from its integer node coordinates (nnodes x dim): the nodes
+    on the grid plane through the median of the longest axis separate the
+    two halves (elements live inside grid cells, so no element couples the
+    two sides), each half is ordered recursively, the separator last; sets
+    of at most `leaf` nodes keep their natural order.  DOFs of a node stay
+    together (dof = dpn * node + component)."""
+    coords = np.asarray(coords)
+    parts = []
+
+    def rec(idx):
+        c = coords[idx]
+        ext = c.max(axis=0) - c.min(axis=0) if len(idx) else np.zeros(1)
+        ax = int(np.argmax(ext))
+        if len(idx) <= leaf or ext[ax] < 2:
+            parts.append(idx)
+            return
+        lo, hi = c[:, ax].min(), c[:, ax].max()
+        v = min(max(np.sort(c[:, ax])[len(idx) // 2], lo + 1), hi - 1)
+        rec(idx[c[:, ax] < v])
+        rec(idx[c[:, ax] > v])
+        parts.append(idx[c[:, ax] == v])
+
+    rec(np.arange(len(coords)))
+    nodes = np.concatenate(parts)
+    return (nodes[:, None] * dpn + np.arange(dpn)[None, :]).ravel().astype(np.int32)
 
 
 def mmd_order(A):
@@ -64,7 +106,10 @@ def _p(a):
 class ImplicitCPU:
     """q = sum_i D_i^T B~_i K_reg,i^{-1} B~_i^T D_i lambda on host threads."""
 
-    def __init__(self, subs, n_lambda, nthreads=None, perms=None):
+    def __init__(self, subs, n_lambda, nthreads=None, perms=None, order="nd"):
+        """perms: per-subdomain permutations (new -> old) to use as given;
+        else order "nd" (geometric nested dissection from the subdomain's
+        node coordinates) or "mmd" (SuperLU's minimum degree)."""
         L = _load()
         self.L = L
         self.n_lambda = int(n_lambda)
@@ -76,7 +121,12 @@ class ImplicitCPU:
             Ap = A.indptr.astype(np.int32)
             Ai = A.indices.astype(np.int32)
             Ax = A.data.astype(np.float64)
-            perm = perms[i] if perms is not None else mmd_order(A)
+            if perms is not None:
+                perm = perms[i]
+            elif order == "nd":
+                perm = nd_order(s.coords, s.dpn)
+            else:
+                perm = mmd_order(A)
             perm = np.ascontiguousarray(perm, dtype=np.int32)
             bd = np.ascontiguousarray(s.b_dof, dtype=np.int32)
             bs = np.ascontiguousarray(s.b_sign, dtype=np.int8)
@@ -86,6 +136,7 @@ class ImplicitCPU:
             if rc != 0:
                 raise RuntimeError("orc_set_sub failed")
         self.nsub = len(subs)
+        self.m = [len(s.b_dof) for s in subs]
 
     def factor(self):
         rc = self.L.orc_factor_all(self.h, self.nthreads)
@@ -99,6 +150,38 @@ class ImplicitCPU:
         lam = np.ascontiguousarray(lam, dtype=np.float64)
         q = out if out is not None else np.empty(self.n_lambda)
         self.L.orc_apply(self.h, _p(lam), _p(q), self.n_lambda, self.nthreads)
+        return q
+
+    def opnorms(self, iters=60):
+        """||F~_i||_2 of every subdomain (power iteration with the factors;
+        the Rayleigh quotient of the last iterate, a lower estimate)."""
+        out = np.empty(self.nsub)
+        self.L.orc_opnorm_all(self.h, int(iters), _p(out), self.nthreads)
+        return out
+
+    def kappas(self, iters=60):
+        """Condition numbers of every K_reg,i (power iteration for the
+        largest eigenvalue, inverse iteration for the smallest)."""
+        out = np.empty(self.nsub)
+        self.L.orc_kappa_all(self.h, int(iters), _p(out), self.nthreads)
+        return out
+
+    def assemble(self):
+        """Explicit F~_i of every subdomain, one unit solve per column."""
+        self.L.orc_assemble_all(self.h, self.nthreads)
+
+    def dual_operator(self, i):
+        """The assembled F~_i (m_i x m_i, local multiplier order)."""
+        out = np.empty((self.m[i], self.m[i]))
+        if self.L.orc_get_F(self.h, int(i), _p(out)) != 0:
+            raise RuntimeError("assemble() first")
+        return out
+
+    def apply_explicit(self, lam, out=None):
+        """q = sum_i D_i^T F~_i D_i lambda with the assembled dense F~_i."""
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        q = out if out is not None else np.empty(self.n_lambda)
+        self.L.orc_apply_explicit(self.h, _p(lam), _p(q), self.n_lambda, self.nthreads)
         return q
 
     def __del__(self):

@@ -13,6 +13,14 @@
  * of A), in the fill-reducing order given by the caller.  FP64 throughout.
  * Subdomains are spread over a pool of threads; the final gather runs in
  * ascending subdomain order so the result does not depend on the threads.
+ *
+ * With the same factors it also forms the explicit local dual operators the
+ * plain way (eq. localdualoperator: one unit right-hand side per local
+ * multiplier, F~_i = B~_i K_reg,i^{-1} B~_i^T column by column, stored dense)
+ * and applies them as dense matrix-vector products (eq.
+ * dualop_apply_expl); and it estimates ||F~_i||_2 by power iteration and the
+ * condition number of K_reg,i by power and inverse iteration, the scales of
+ * the rounding bounds the parity tests use.
  */
 #include <math.h>
 #include <pthread.h>
@@ -35,6 +43,8 @@ typedef struct {
     int *dual_map;
     double *work;      /* n */
     double *qloc;      /* m */
+    double *F;         /* explicit F~_i, m x m row-major (after orc_assemble_all) */
+    double est;        /* last estimate of orc_opnorm_all / orc_kappa_all */
     int status;
 } orc_sub;
 
@@ -55,7 +65,7 @@ static void sub_free(orc_sub *s)
 {
     free(s->Cp); free(s->Ci); free(s->Cx); free(s->perm); free(s->pinv);
     free(s->parent); free(s->Lp); free(s->Li); free(s->Lx); free(s->b_new);
-    free(s->b_sign); free(s->dual_map); free(s->work); free(s->qloc);
+    free(s->b_sign); free(s->dual_map); free(s->work); free(s->qloc); free(s->F);
     memset(s, 0, sizeof(*s));
 }
 
@@ -225,13 +235,27 @@ static void solve_one(const orc_sub *s, double *x)
     }
 }
 
-typedef struct {
-    orc_handle *h;
-    int next;
-    pthread_mutex_t mu;
-    int mode; /* 0 factor, 1 apply */
-    const double *lam;
-} pool_t;
+/* y = C x for the symmetric matrix whose upper triangle C holds (permuted order) */
+static void symv_upper(const orc_sub *s, const double *x, double *y)
+{
+    memset(y, 0, sizeof(double) * (size_t)s->n);
+    for (int k = 0; k < s->n; ++k)
+        for (int p = s->Cp[k]; p < s->Cp[k + 1]; ++p) {
+            int i = s->Ci[p];
+            y[i] += s->Cx[p] * x[k];
+            if (i != k) y[k] += s->Cx[p] * x[i];
+        }
+}
+
+/* y = F~_i v = B~_i K_reg,i^{-1} B~_i^T v for a local vector v (m entries) */
+static void apply_local(orc_sub *s, const double *v, double *y)
+{
+    double *x = s->work;
+    memset(x, 0, sizeof(double) * (size_t)s->n);
+    for (int j = 0; j < s->m; ++j) x[s->b_new[j]] += s->b_sign[j] * v[j];
+    solve_one(s, x);
+    for (int j = 0; j < s->m; ++j) y[j] = s->b_sign[j] * x[s->b_new[j]];
+}
 
 static void apply_one(orc_sub *s, const double *lam)
 {
@@ -242,6 +266,118 @@ static void apply_one(orc_sub *s, const double *lam)
     for (int j = 0; j < s->m; ++j) s->qloc[j] = s->b_sign[j] * x[s->b_new[j]];
 }
 
+/* deterministic start vector with no structure: entries in [0.5, 1.5) */
+static void start_vector(double *v, int n)
+{
+    unsigned long long st = 0x9e3779b97f4a7c15ULL;
+    for (int k = 0; k < n; ++k) {
+        st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+        v[k] = 0.5 + (double)(st >> 11) * (1.0 / 9007199254740992.0);
+    }
+}
+
+static double norm2(const double *v, int n)
+{
+    double t = 0.0;
+    for (int k = 0; k < n; ++k) t += v[k] * v[k];
+    return sqrt(t);
+}
+
+/* ||F~_i||_2 by power iteration (F~_i is symmetric positive semi-definite):
+ * the Rayleigh quotient of the last iterate, a lower estimate */
+static void opnorm_one(orc_sub *s, int iters)
+{
+    int m = s->m;
+    double *v = (double *)malloc(sizeof(double) * (size_t)m);
+    double *y = (double *)malloc(sizeof(double) * (size_t)m);
+    start_vector(v, m);
+    double nv = norm2(v, m), est = 0.0;
+    for (int k = 0; k < m; ++k) v[k] /= nv;
+    for (int it = 0; it < iters; ++it) {
+        apply_local(s, v, y);
+        est = 0.0;
+        for (int k = 0; k < m; ++k) est += v[k] * y[k];
+        double ny = norm2(y, m);
+        if (!(ny > 0.0)) break;
+        for (int k = 0; k < m; ++k) v[k] = y[k] / ny;
+    }
+    s->est = est;
+    free(v);
+    free(y);
+}
+
+/* condition number of K_reg,i: the largest eigenvalue by power iteration,
+ * the smallest by inverse iteration with the factor */
+static void kappa_one(orc_sub *s, int iters)
+{
+    int n = s->n;
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    start_vector(v, n);
+    double nv = norm2(v, n), lmax = 0.0, lmin = 0.0;
+    for (int k = 0; k < n; ++k) v[k] /= nv;
+    for (int it = 0; it < iters; ++it) {
+        symv_upper(s, v, y);
+        lmax = 0.0;
+        for (int k = 0; k < n; ++k) lmax += v[k] * y[k];
+        double ny = norm2(y, n);
+        for (int k = 0; k < n; ++k) v[k] = y[k] / ny;
+    }
+    start_vector(v, n);
+    nv = norm2(v, n);
+    for (int k = 0; k < n; ++k) v[k] /= nv;
+    for (int it = 0; it < iters; ++it) {
+        memcpy(y, v, sizeof(double) * (size_t)n);
+        solve_one(s, y);
+        double r = 0.0;
+        for (int k = 0; k < n; ++k) r += v[k] * y[k];   /* v^T K^{-1} v -> 1 / lambda_min */
+        lmin = 1.0 / r;
+        double ny = norm2(y, n);
+        for (int k = 0; k < n; ++k) v[k] = y[k] / ny;
+    }
+    s->est = lmax / lmin;
+    free(v);
+    free(y);
+}
+
+/* explicit F~_i (m x m, row-major): column a is B~ K_reg^{-1} (sign_a e_dof_a) */
+static void assemble_one(orc_sub *s)
+{
+    int m = s->m;
+    free(s->F);
+    s->F = (double *)malloc(sizeof(double) * (size_t)m * (size_t)m);
+    double *x = s->work;
+    for (int a = 0; a < m; ++a) {
+        memset(x, 0, sizeof(double) * (size_t)s->n);
+        x[s->b_new[a]] = s->b_sign[a];
+        solve_one(s, x);
+        for (int b = 0; b < m; ++b) s->F[(size_t)b * m + a] = s->b_sign[b] * x[s->b_new[b]];
+    }
+}
+
+/* q~_i = F~_i lambda_i with the stored dense F~_i */
+static void apply_dense_one(orc_sub *s, const double *lam)
+{
+    int m = s->m;
+    for (int a = 0; a < m; ++a) {
+        const double *row = s->F + (size_t)a * m;
+        double t = 0.0;
+        for (int b = 0; b < m; ++b) t += row[b] * lam[s->dual_map[b]];
+        s->qloc[a] = t;
+    }
+}
+
+enum { MODE_FACTOR, MODE_APPLY, MODE_OPNORM, MODE_KAPPA, MODE_ASSEMBLE, MODE_APPLY_DENSE };
+
+typedef struct {
+    orc_handle *h;
+    int next;
+    pthread_mutex_t mu;
+    int mode;
+    int iters;
+    const double *lam;
+} pool_t;
+
 static void *worker(void *arg)
 {
     pool_t *P = (pool_t *)arg;
@@ -250,20 +386,29 @@ static void *worker(void *arg)
         int i = P->next++;
         pthread_mutex_unlock(&P->mu);
         if (i >= P->h->nsub) break;
-        if (P->mode == 0) factor_one(&P->h->s[i]);
-        else apply_one(&P->h->s[i], P->lam);
+        orc_sub *s = &P->h->s[i];
+        switch (P->mode) {
+        case MODE_FACTOR: factor_one(s); break;
+        case MODE_APPLY: apply_one(s, P->lam); break;
+        case MODE_OPNORM: opnorm_one(s, P->iters); break;
+        case MODE_KAPPA: kappa_one(s, P->iters); break;
+        case MODE_ASSEMBLE: assemble_one(s); break;
+        default: apply_dense_one(s, P->lam); break;
+        }
     }
     return NULL;
 }
 
-static void run_pool(orc_handle *h, int nthreads, int mode, const double *lam)
+static void run_pool(orc_handle *h, int nthreads, int mode, const double *lam, int iters)
 {
     pool_t P;
     P.h = h;
     P.next = 0;
     P.mode = mode;
+    P.iters = iters;
     P.lam = lam;
     pthread_mutex_init(&P.mu, NULL);
+    if (nthreads > h->nsub) nthreads = h->nsub;
     if (nthreads < 1) nthreads = 1;
     pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
     for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, worker, &P);
@@ -276,7 +421,7 @@ static void run_pool(orc_handle *h, int nthreads, int mode, const double *lam)
 int orc_factor_all(void *hh, int nthreads)
 {
     orc_handle *h = (orc_handle *)hh;
-    run_pool(h, nthreads, 0, NULL);
+    run_pool(h, nthreads, MODE_FACTOR, NULL, 0);
     for (int i = 0; i < h->nsub; ++i)
         if (h->s[i].status != 0) return -(1 + i);
     return 0;
@@ -286,7 +431,7 @@ int orc_factor_all(void *hh, int nthreads)
 void orc_apply(void *hh, const double *lam, double *q, int n_lambda, int nthreads)
 {
     orc_handle *h = (orc_handle *)hh;
-    run_pool(h, nthreads, 1, lam);
+    run_pool(h, nthreads, MODE_APPLY, lam, 0);
     memset(q, 0, sizeof(double) * (size_t)n_lambda);
     for (int i = 0; i < h->nsub; ++i) {
         const orc_sub *s = &h->s[i];
@@ -298,4 +443,49 @@ long orc_nnz(void *hh, int i)
 {
     orc_handle *h = (orc_handle *)hh;
     return h->s[i].Lp ? (long)h->s[i].Lp[h->s[i].n] : -1;
+}
+
+/* ||F~_i||_2 of every subdomain (power iteration, `iters` steps) into out[nsub] */
+void orc_opnorm_all(void *hh, int iters, double *out, int nthreads)
+{
+    orc_handle *h = (orc_handle *)hh;
+    run_pool(h, nthreads, MODE_OPNORM, NULL, iters);
+    for (int i = 0; i < h->nsub; ++i) out[i] = h->s[i].est;
+}
+
+/* condition number estimates of every K_reg,i into out[nsub] */
+void orc_kappa_all(void *hh, int iters, double *out, int nthreads)
+{
+    orc_handle *h = (orc_handle *)hh;
+    run_pool(h, nthreads, MODE_KAPPA, NULL, iters);
+    for (int i = 0; i < h->nsub; ++i) out[i] = h->s[i].est;
+}
+
+/* explicit assembly: the dense F~_i of every subdomain, one unit solve per column */
+void orc_assemble_all(void *hh, int nthreads)
+{
+    orc_handle *h = (orc_handle *)hh;
+    run_pool(h, nthreads, MODE_ASSEMBLE, NULL, 0);
+}
+
+/* copy F~_i (m x m, row-major, local multiplier order); -1 before assembly */
+int orc_get_F(void *hh, int i, double *out)
+{
+    orc_handle *h = (orc_handle *)hh;
+    const orc_sub *s = &h->s[i];
+    if (!s->F) return -1;
+    memcpy(out, s->F, sizeof(double) * (size_t)s->m * (size_t)s->m);
+    return 0;
+}
+
+/* q = sum_i D_i^T F~_i D_i lam with the assembled dense F~_i */
+void orc_apply_explicit(void *hh, const double *lam, double *q, int n_lambda, int nthreads)
+{
+    orc_handle *h = (orc_handle *)hh;
+    run_pool(h, nthreads, MODE_APPLY_DENSE, lam, 0);
+    memset(q, 0, sizeof(double) * (size_t)n_lambda);
+    for (int i = 0; i < h->nsub; ++i) {
+        const orc_sub *s = &h->s[i];
+        for (int j = 0; j < s->m; ++j) q[s->dual_map[j]] += s->qloc[j];
+    }
 }

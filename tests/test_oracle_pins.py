@@ -380,3 +380,75 @@ def test_lumped_preconditioner_matches_global_product(kind):
     assert np.allclose(Mcols, Mg, rtol=1e-13, atol=1e-13 * np.abs(Mg).max())
     assert np.allclose(Mcols, Mcols.T, atol=1e-13 * np.abs(Mg).max())
     assert np.linalg.eigvalsh(0.5 * (Mcols + Mcols.T)).min() >= -1e-10 * np.abs(Mg).max()
+
+
+@pytest.mark.parametrize("kind", ["heat3d", "elast3d", "heat3d_tet"])
+def test_c_explicit_assembly_matches_python_oracle(kind):
+    """The C oracle's explicit F~_i (one unit solve per column with its own
+    sparse factor) equals the dense-LAPACK F~_i; its dense explicit apply
+    equals the Python explicit apply and the implicit one."""
+    P = tiny(kind)
+    I = orc_impl.ImplicitCPU(P.subs, P.n_lambda, nthreads=3)
+    I.factor()
+    I.assemble()
+    Fs = []
+    for i, s in enumerate(P.subs):
+        F = feti.local_dual_operator(s.Kreg, s.b_dof, s.b_sign)
+        Fc = I.dual_operator(i)
+        assert np.abs(Fc - F).max() <= 1e-12 * np.abs(F).max()
+        Fs.append(F)
+    q = feti.apply_explicit(Fs, [s.dual_map for s in P.subs], P.lam, P.n_lambda)
+    qe = I.apply_explicit(P.lam)
+    qi = I.apply(P.lam)
+    assert np.abs(qe - q).max() <= 1e-12 * np.abs(q).max()
+    assert np.abs(qi - q).max() <= 1e-12 * np.abs(q).max()
+
+
+def test_c_explicit_assembly_1d_closed_form():
+    """The C oracle's explicit F~_i of the 1D bar equal (K_reg^{-1})_{ij} =
+    1/rho + h min(i, j) entry by entry (m = 2 and m = 1 subdomains)."""
+    P = make_problem(1, "heat", [[6, 6]], 0.0, dirichlet_axis=0, seed=1)
+    I = orc_impl.ImplicitCPU(P.subs, P.n_lambda, nthreads=2)
+    I.factor()
+    I.assemble()
+    s0, s1 = P.subs
+    r0, r1 = 1.0 / s0.rho, 1.0 / s1.rho
+    assert np.allclose(I.dual_operator(0), [[r0, r0], [r0, r0 + 6 * P.h]], rtol=1e-14, atol=0)
+    assert np.allclose(I.dual_operator(1), [[r1]], rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("kind", ["heat3d", "elast3d"])
+def test_c_norm_and_condition_estimates(kind):
+    """||F~_i||_2 (power iteration) against the largest singular value of the
+    dense F~_i, and cond(K_reg,i) (power + inverse iteration) against the
+    ratio of the extreme eigenvalues of the dense K_reg,i (LAPACK)."""
+    P = tiny(kind)
+    I = orc_impl.ImplicitCPU(P.subs, P.n_lambda, nthreads=2)
+    I.factor()
+    nrm = I.opnorms(iters=300)
+    kap = I.kappas(iters=300)
+    for i, s in enumerate(P.subs):
+        F = feti.local_dual_operator(s.Kreg, s.b_dof, s.b_sign)
+        assert abs(nrm[i] - np.linalg.norm(F, 2)) <= 1e-6 * np.linalg.norm(F, 2)
+        ev = np.linalg.eigvalsh(s.Kreg.toarray())
+        # the largest eigenvalues of a stiffness matrix cluster, so the
+        # power iteration is slow there: an estimate within 1 %
+        assert abs(kap[i] - ev[-1] / ev[0]) <= 1e-2 * ev[-1] / ev[0]
+
+
+@pytest.mark.parametrize("kind", ["heat3d", "elast3d", "heat2d_tri"])
+def test_nd_order_is_a_permutation_with_the_same_operator(kind):
+    """The oracle's geometric nested-dissection order is a permutation of
+    the DOFs, keeps each node's DOFs together, and the implicit apply with
+    it equals the one with SuperLU's minimum-degree order."""
+    P = tiny(kind)
+    for s in P.subs:
+        p = orc_impl.nd_order(s.coords, s.dpn, leaf=4)
+        assert np.array_equal(np.sort(p), np.arange(s.n))
+        assert np.all(p.reshape(-1, s.dpn) // s.dpn == (p.reshape(-1, s.dpn) // s.dpn)[:, :1])
+    qs = []
+    for order in ("nd", "mmd"):
+        I = orc_impl.ImplicitCPU(P.subs, P.n_lambda, nthreads=2, order=order)
+        I.factor()
+        qs.append(I.apply(P.lam))
+    assert np.abs(qs[0] - qs[1]).max() <= 1e-12 * np.abs(qs[1]).max()
