@@ -29,6 +29,13 @@
  *    failures return FETIF_EDEVICE and are sticky for the context.  The
  *    message of the last error is fetiF_last_error(ctx).
  *  - One context is used by one host thread at a time.
+ *  - Calls on one context share its device work buffers (solve vectors,
+ *    apply partials, solver scalars): enqueue them on one stream, or order
+ *    them across streams yourself (events).  Assembly and the solves with
+ *    the factors wait for the last factor copy also when it was enqueued on
+ *    another stream; fetiF_apply waits for nothing (it must stay capturable
+ *    in a graph), so order it after fetiF_assemble when they use different
+ *    streams.
  */
 #ifndef FETIF_H
 #define FETIF_H

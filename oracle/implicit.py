@@ -59,6 +59,8 @@ def _load():
         L.orc_get_F.restype = ip
         L.orc_get_F.argtypes = [vp, ip, dp]
         L.orc_apply_explicit.argtypes = [vp, dp, dp, ip, ip]
+        L.orc_solve.restype = ip
+        L.orc_solve.argtypes = [vp, ip, dp]
         _lib = L
     return _lib
 
@@ -183,6 +185,49 @@ class ImplicitCPU:
         q = out if out is not None else np.empty(self.n_lambda)
         self.L.orc_apply_explicit(self.h, _p(lam), _p(q), self.n_lambda, self.nthreads)
         return q
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.L.orc_destroy(self.h)
+            self.h = None
+
+
+class SparseRegInverse:
+    """K_reg^{-1} of one matrix through the oracle's sparse Cholesky factor
+    (nested-dissection order from the node coordinates), with one step of
+    iterative refinement whose residual is formed in extended precision,
+    like oracle.feti.RegInverse but without the dense factorisation."""
+
+    def __init__(self, Kreg, coords, dpn):
+        L = _load()
+        self.L = L
+        A = sp.csr_matrix(Kreg)
+        self.K = A
+        self.Kl = A.astype(np.longdouble)
+        self.n = A.shape[0]
+        self.h = L.orc_create(1)
+        Ap = A.indptr.astype(np.int32)
+        Ai = A.indices.astype(np.int32)
+        Ax = A.data.astype(np.float64)
+        perm = nd_order(coords, dpn)
+        none = np.zeros(1, np.int32)
+        rc = L.orc_set_sub(self.h, 0, self.n, _p(Ap), _p(Ai), _p(Ax), _p(perm), 0, _p(none),
+                           _p(np.zeros(1, np.int8)), _p(none))
+        if rc != 0 or L.orc_factor_all(self.h, 1) != 0:
+            raise RuntimeError("oracle sparse Cholesky failed")
+
+    def _solve(self, b):
+        x = np.array(b, dtype=np.float64, copy=True, order="C")
+        self.L.orc_solve(self.h, 0, _p(x))
+        return x
+
+    def solve(self, rhs, refine=True):
+        rhs = np.asarray(rhs, dtype=np.float64)
+        x = self._solve(rhs)
+        if refine:
+            r = rhs.astype(np.longdouble) - self.Kl @ x.astype(np.longdouble)
+            x = x + self._solve(np.asarray(r, dtype=np.float64))
+        return x
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -489,3 +489,17 @@ void orc_apply_explicit(void *hh, const double *lam, double *q, int n_lambda, in
         for (int j = 0; j < s->m; ++j) q[s->dual_map[j]] += s->qloc[j];
     }
 }
+
+/* x <- K_reg,i^{-1} x for a vector in the caller's (unpermuted) DOF order */
+int orc_solve(void *hh, int i, double *x)
+{
+    orc_handle *h = (orc_handle *)hh;
+    orc_sub *s = &h->s[i];
+    if (!s->Lp || s->status != 0) return -1;
+    double *w = (double *)malloc(sizeof(double) * (size_t)s->n);
+    for (int k = 0; k < s->n; ++k) w[k] = x[s->perm[k]];
+    solve_one(s, w);
+    for (int k = 0; k < s->n; ++k) x[s->perm[k]] = w[k];
+    free(w);
+    return 0;
+}

@@ -18,7 +18,8 @@ import torch
 class FetiApply(torch.autograd.Function):
     @staticmethod
     def forward(fctx, lam, theta, feti):
-        q = torch.empty_like(lam)
+        lam = lam.contiguous()
+        q = torch.empty(lam.shape, dtype=lam.dtype, device=lam.device)
         feti.apply(lam, q)
         fctx.feti = feti
         fctx.theta_shape = theta.shape
@@ -30,7 +31,7 @@ class FetiApply(torch.autograd.Function):
         (lam,) = fctx.saved_tensors
         feti = fctx.feti
         g = g.contiguous()
-        dlam = torch.empty_like(lam)
+        dlam = torch.empty(lam.shape, dtype=lam.dtype, device=lam.device)
         dth = None
         if fctx.needs_input_grad[1]:
             dth = torch.empty(fctx.theta_shape, dtype=lam.dtype, device=lam.device)

@@ -90,6 +90,28 @@ def tune_apply(ctx, lam, q, bands=None, rows=(2, 4), nontemporal=(1,), splits=(0
     return out
 
 
+STORED_SHAPES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_apply.json")
+
+
+def stored_apply_shape(ctx, cache=STORED_SHAPES):
+    """The apply shape stored for this workload's signature, or None."""
+    try:
+        with open(cache) as f:
+            return json.load(f).get(signature(ctx))
+    except (OSError, ValueError):
+        return None
+
+
+def install_stored_apply_shape(ctx, cache=STORED_SHAPES):
+    """Install the stored apply shape of this workload (what the benchmark
+    runs when its tuner finds the workload in the store); returns it, or
+    None when the store has no entry (the context keeps its defaults)."""
+    hit = stored_apply_shape(ctx, cache)
+    if hit:
+        ctx.set_apply(hit["band"], hit["rows"], hit["nontemporal"], hit.get("split", 0), hit.get("seg", 0))
+    return hit
+
+
 def tune_assembly(ctx, panels=(32, 48, 64, 96), chunks=(16, 32, 64), reps=3, stream=None, verbose=False):
     """Try every (TRSM panel width, RHS columns per work-group) shape of the
     assembly; install and return the fastest by the TRSM phase time.  The

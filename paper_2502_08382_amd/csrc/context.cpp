@@ -1234,6 +1234,7 @@ extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, order_after_upload(c, st));
     const int32_t G = (int32_t)c->grp_first.size() - 1;
     // phase by phase over the groups (one timer per phase)
     PhaseTimer t1(c, st, 1);
@@ -1413,6 +1414,7 @@ extern "C" fetiF_status fetiF_apply_implicit(fetiF_ctx c, const double* lambda_d
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, order_after_upload(c, st));
     PhaseTimer t6(c, st, 6);
     HIPCHK(c, launch_scatter_dual(1, c->nsub, c->dSubRow, c->dSubM, c->dStartRows, c->dSignsSorted, c->dDmap,
                                   lambda_d, nullptr, c->dXv, c->total_rows, st));
@@ -1431,6 +1433,7 @@ extern "C" fetiF_status fetiF_dual_rhs(fetiF_ctx c, const double* f_d, const dou
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, order_after_upload(c, st));
     PhaseTimer t6(c, st, 6);
     HIPCHK(c, launch_permute_in(c->total_rows, c->dXperm, f_d, c->dXv, st));
     HIPCHK(c, solve_all(c, 1, st));
@@ -1452,6 +1455,7 @@ extern "C" fetiF_status fetiF_apply_backward(fetiF_ctx c, const double* g_d, con
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, order_after_upload(c, st));
     PhaseTimer t6(c, st, 6);
     HIPCHK(c, launch_scatter_dual(2, c->nsub, c->dSubRow, c->dSubM, c->dStartRows, c->dSignsSorted, c->dDmap, g_d,
                                   lambda_d, c->dXv, c->total_rows, st));

@@ -308,6 +308,19 @@ hipError_t upload(T* d, const std::vector<T>& h)
 }
 
 
+// Orders `st` after the last factor copy (its event), so a copy made on
+// another stream is complete before the factors are read; skipped while
+// `st` is being captured into a graph (the caller orders captured work).
+inline hipError_t order_after_upload(fetiF_ctx c, hipStream_t st)
+{
+    if (!c->upload_pending) return hipSuccess;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return e;
+    if (cs != hipStreamCaptureStatusNone) return hipSuccess;
+    return hipStreamWaitEvent(st, c->upload_done, 0);
+}
+
 // batched forward + backward solves with every L_i on c->dXv (context.cpp)
 hipError_t solve_all(fetiF_ctx c, int nrhs, hipStream_t st);
 // FETIF_ESTATE unless every subdomain has been factored

@@ -137,6 +137,33 @@ def _dptr(t):
     return t.data_ptr()
 
 
+def _check_vecs(named, device):
+    """Device vector arguments, name -> (value, expected length): each a raw
+    pointer (int, passed as is), None where optional, or a contiguous
+    float64 torch tensor of exactly that many elements on the context's
+    device.  The library reads or writes 8 bytes per element through the
+    pointer, so a shorter, strided, differently typed or host tensor is
+    refused here (types and lengths of all arguments first, then devices)."""
+    import torch
+    tensors = []
+    for name, (t, n) in named.items():
+        if t is None or isinstance(t, int):
+            continue
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name}: expected a torch tensor or a device pointer, got {type(t).__name__}")
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name}: dtype must be torch.float64, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: must be contiguous")
+        if t.numel() != n:
+            raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
+        tensors.append((name, t))
+    for name, t in tensors:
+        if t.device.type != "cuda" or (t.device.index if t.device.index is not None
+                                        else torch.cuda.current_device()) != device:
+            raise ValueError(f"{name}: must live on cuda:{device}, got {t.device}")
+
+
 def _stream(stream):
     if stream is None:
         try:
@@ -206,6 +233,13 @@ class FetiContext:
         self.f_storage = opt.f_storage
         self.nsub = len(self._subs)
         self.m = [len(s.b_dof) for s in self._subs]
+        self.n_dofs = sum(s.n for s in self._subs)
+        self.n_elems = sum(0 if s.elem_dofs is None else s.elem_dofs.shape[0] for s in self._subs)
+        self.n_coarse = sum(0 if s.R is None else s.R.shape[1] for s in self._subs)
+
+    def _vecs(self, **named):
+        """Validate device vector arguments: name=(tensor, expected length)."""
+        _check_vecs(named, self.device)
 
     def _check(self, st):
         if st != 0:
@@ -229,25 +263,32 @@ class FetiContext:
         self._check(self.L.fetiF_factor_assemble(self.h, ptrs, _stream(stream)))
 
     def apply(self, lam, q, stream=None):
+        self._vecs(lam=(lam, self.n_lambda), q=(q, self.n_lambda))
         self._check(self.L.fetiF_apply(self.h, _dptr(lam), _dptr(q), _stream(stream)))
 
     def apply_backward(self, g, lam, dlam, dtheta=None, stream=None):
+        self._vecs(g=(g, self.n_lambda), lam=(lam, self.n_lambda), dlam=(dlam, self.n_lambda),
+                   dtheta=(dtheta, self.n_elems))
         self._check(self.L.fetiF_apply_backward(self.h, _dptr(g), _dptr(lam), _dptr(dlam), _dptr(dtheta),
                                                 _stream(stream)))
 
     def apply_implicit(self, lam, q, stream=None):
+        self._vecs(lam=(lam, self.n_lambda), q=(q, self.n_lambda))
         self._check(self.L.fetiF_apply_implicit(self.h, _dptr(lam), _dptr(q), _stream(stream)))
 
     def dual_rhs(self, f, d, c=None, stream=None):
+        self._vecs(f=(f, self.n_dofs), d=(d, self.n_lambda), c=(c, self.n_lambda))
         self._check(self.L.fetiF_dual_rhs(self.h, _dptr(f), _dptr(c), _dptr(d), _stream(stream)))
 
     def coarse_rhs(self, f, e, stream=None):
+        self._vecs(f=(f, self.n_dofs), e=(e, self.n_coarse))
         self._check(self.L.fetiF_coarse_rhs(self.h, _dptr(f), _dptr(e), _stream(stream)))
 
     def pcpg(self, d, e, lam, tol=1e-9, max_iters=1000, fixed_iters=0, implicit=False, check_every=10,
              refine=False, inner_tol=1e-4, use_graph=True, precond=0, stream=None):
         """PCPG (Alg. 1) on the device (precond 0: M = I, 1: lumped);
         returns dict(iters, outer, rel_residual, w0)."""
+        self._vecs(d=(d, self.n_lambda), e=(e, self.n_coarse), lam=(lam, self.n_lambda))
         o = _PcpgOpt(tol, max_iters, fixed_iters, int(implicit), check_every, int(refine), inner_tol,
                      int(use_graph), int(precond))
         r = _PcpgRes()
@@ -256,6 +297,8 @@ class FetiContext:
         return {k: getattr(r, k) for k, _ in _PcpgRes._fields_}
 
     def primal(self, f, d, lam, alpha, u, stream=None):
+        self._vecs(f=(f, self.n_dofs), d=(d, self.n_lambda), lam=(lam, self.n_lambda),
+                   alpha=(alpha, self.n_coarse), u=(u, self.n_dofs))
         self._check(self.L.fetiF_primal(self.h, _dptr(f), _dptr(d), _dptr(lam), _dptr(alpha), _dptr(u),
                                         _stream(stream)))
 

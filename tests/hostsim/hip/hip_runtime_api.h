@@ -14,6 +14,7 @@ typedef struct ihipGraphExec_t* hipGraphExec_t;
 typedef struct ihipGraphNode_t* hipGraphNode_t;
 enum hipMemcpyKind { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 };
 enum hipStreamCaptureMode { hipStreamCaptureModeGlobal = 0, hipStreamCaptureModeThreadLocal = 1, hipStreamCaptureModeRelaxed = 2 };
+enum hipStreamCaptureStatus { hipStreamCaptureStatusNone = 0, hipStreamCaptureStatusActive = 1, hipStreamCaptureStatusInvalidated = 2 };
 #define hipHostMallocDefault 0
 #define hipEventDisableTiming 2
 hipError_t hipSetDevice(int);
@@ -35,9 +36,13 @@ hipError_t hipEventSynchronize(hipEvent_t);
 hipError_t hipEventDestroy(hipEvent_t);
 hipError_t hipEventElapsedTime(float*, hipEvent_t, hipEvent_t);
 hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode);
+hipError_t hipStreamIsCapturing(hipStream_t, hipStreamCaptureStatus*);
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned int);
 hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t*);
 hipError_t hipGraphInstantiate(hipGraphExec_t*, hipGraph_t, hipGraphNode_t*, char*, size_t);
 hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t);
 hipError_t hipGraphExecDestroy(hipGraphExec_t);
 hipError_t hipGraphDestroy(hipGraph_t);
 const char* hipGetErrorString(hipError_t);
+// test double only: aborts when a stream handle differs from $HOSTSIM_STREAM
+void hostsim_check_stream(hipStream_t);

@@ -152,3 +152,32 @@ def test_create_validates_arguments(bad):
     with pytest.raises(FetiError) as e:
         FetiContext(subs, nl)
     assert e.value.status == 1
+
+
+def test_binding_refuses_wrong_device_vectors():
+    """Device vectors are checked before the library is called: float64,
+    contiguous, exactly the expected length, on the context's GPU (the
+    library reads and writes 8 bytes per element through the pointer)."""
+    import torch
+    ctx = FetiContext.__new__(FetiContext)          # no library call is reached
+    ctx.h, ctx.L, ctx.device = None, None, 0
+    ctx.n_lambda, ctx.n_dofs, ctx.n_elems, ctx.n_coarse = 10, 40, 8, 2
+    good = torch.zeros(10, dtype=torch.float64)
+    cases = [
+        (lambda: ctx.apply(torch.zeros(10, dtype=torch.float32), good), TypeError, "float64"),
+        (lambda: ctx.apply(torch.zeros(20, dtype=torch.float64)[::2], good), ValueError, "contiguous"),
+        (lambda: ctx.apply(torch.zeros(9, dtype=torch.float64), good), ValueError, "expected 10"),
+        (lambda: ctx.apply(good, good.clone()), ValueError, "cuda:0"),          # host tensor
+        (lambda: ctx.apply_implicit(good, torch.zeros(11, dtype=torch.float64)), ValueError, "expected 10"),
+        (lambda: ctx.apply_backward(good, good, good, torch.zeros(7, dtype=torch.float64)), ValueError,
+         "expected 8"),
+        (lambda: ctx.dual_rhs(torch.zeros(39, dtype=torch.float64), good), ValueError, "expected 40"),
+        (lambda: ctx.coarse_rhs(torch.zeros(40, dtype=torch.float64), torch.zeros(3, dtype=torch.float64)),
+         ValueError, "expected 2"),
+        (lambda: ctx.pcpg(good, torch.zeros(2, dtype=torch.int64), good), TypeError, "float64"),
+        (lambda: ctx.primal(torch.zeros(40, dtype=torch.float64), good, good, torch.zeros(2, dtype=torch.float64),
+                            torch.zeros(41, dtype=torch.float64)), ValueError, "expected 40"),
+    ]
+    for fn, exc, text in cases:
+        with pytest.raises(exc, match=text):
+            fn()

@@ -1,5 +1,5 @@
 """The library's host code (planners, schedules, group and chunk bookkeeping,
-argument checks) under AddressSanitizer, on the CPU.
+argument checks) under AddressSanitizer and ThreadSanitizer, on the CPU.
 
 The host sources are compiled with g++ -fsanitize=address against a test
 double of the HIP runtime (tests/hostsim: device memory is host memory, no
@@ -32,11 +32,9 @@ def _libasan():
     return path if os.path.isabs(path) and os.path.exists(path) else None
 
 
-@pytest.fixture(scope="module")
-def hostsim_lib(tmp_path_factory):
-    if shutil.which("g++") is None or _libasan() is None:
-        pytest.skip("g++ with AddressSanitizer is not available")
-    out = tmp_path_factory.mktemp("hostsim")
+def _build_hostsim(out, sanitizer):
+    """The library's host sources + the runtime test double + stubbed
+    launchers, built with g++ -fsanitize=<sanitizer>."""
     # every kernel launcher declared in the two launcher headers returns
     # success without running anything
     stubs = ['#include "kernels.hpp"', '#include "solver_kernels.hpp"', "namespace fetif {"]
@@ -44,16 +42,40 @@ def hostsim_lib(tmp_path_factory):
         with open(os.path.join(CSRC, h)) as f:
             text = f.read()
         for m in re.finditer(r"hipError_t\s+(launch_\w+)\s*\(([^;]*?)\);", text, re.S):
-            stubs.append(f"hipError_t {m.group(1)}({m.group(2)}) {{ return hipSuccess; }}")
+            check = "hostsim_check_stream(st); " if re.search(r"hipStream_t\s+st\b", m.group(2)) else ""
+            stubs.append(f"hipError_t {m.group(1)}({m.group(2)}) {{ {check}return hipSuccess; }}")
     stubs.append("}")
     stub_cpp = out / "launch_stubs.cpp"
     stub_cpp.write_text("\n".join(stubs) + "\n")
-    lib = out / "libfetiF_hostsim.so"
-    cmd = (["g++", "-std=c++17", "-O1", "-g", "-fPIC", "-shared", "-fsanitize=address", "-fno-omit-frame-pointer",
+    lib = out / f"libfetiF_hostsim_{sanitizer}.so"
+    cmd = (["g++", "-std=c++17", "-O1", "-g", "-fPIC", "-shared", f"-fsanitize={sanitizer}", "-fno-omit-frame-pointer",
             "-I" + HOSTSIM, "-I" + CSRC, os.path.join(HOSTSIM, "runtime_stand_in.cpp"), str(stub_cpp)]
            + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", str(lib), "-lpthread"])
     subprocess.run(cmd, check=True)
     return str(lib)
+
+
+def _libtsan():
+    try:
+        p = subprocess.run(["g++", "-print-file-name=libtsan.so"], capture_output=True, text=True, check=True)
+    except (OSError, subprocess.CalledProcessError):
+        return None
+    path = p.stdout.strip()
+    return path if os.path.isabs(path) and os.path.exists(path) else None
+
+
+@pytest.fixture(scope="module")
+def hostsim_lib(tmp_path_factory):
+    if shutil.which("g++") is None or _libasan() is None:
+        pytest.skip("g++ with AddressSanitizer is not available")
+    return _build_hostsim(tmp_path_factory.mktemp("hostsim"), "address")
+
+
+@pytest.fixture(scope="module")
+def hostsim_tsan_lib(tmp_path_factory):
+    if shutil.which("g++") is None or _libtsan() is None:
+        pytest.skip("g++ with ThreadSanitizer is not available")
+    return _build_hostsim(tmp_path_factory.mktemp("hostsim_tsan"), "thread")
 
 
 DRIVER = r'''
@@ -128,6 +150,8 @@ def flow(prob, with_elements=False, **opts):
 
 
 flow(config_problem(1), with_elements=True)
+flow(make_problem(1, "heat", [[7]], 0.0, dirichlet_axis=0, seed=1), with_elements=True)
+flow(make_problem(1, "heat", [[5, 5, 12]], 0.0, dirichlet_axis=0, seed=1), assembly_groups=2, nthreads=1)
 flow(config_problem(5, scale=(2, 5)), with_elements=True, assembly_groups=3, nthreads=2)
 flow(config_problem(2, scale=(3, 6), elem="simplex"), assembly_groups=8, nthreads=1, f_storage="f32")
 flow(make_problem(3, "elasticity", [[3, 4, 2], [3, 2], [2, 3]], 0.3, dirichlet_axis=2, seed=3),
@@ -144,9 +168,99 @@ def test_host_code_under_address_sanitizer(hostsim_lib):
     env = dict(os.environ)
     env["LD_PRELOAD"] = _libasan()
     env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=0"
+    env["HOSTSIM_STREAM"] = "0x7f0012345670"    # the stream handle the driver passes (ST)
     code = f"ROOT = {ROOT!r}\nLIB = {hostsim_lib!r}\n" + DRIVER
     p = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
     out = p.stdout + p.stderr
     assert "AddressSanitizer" not in out, out[-4000:]
     assert p.returncode == 0, out[-4000:]
     assert "hostsim flows done" in p.stdout
+
+
+TRUNCATION = r'''
+import ctypes, sys
+sys.path.insert(0, ROOT)
+from paper_2502_08382_amd.fetif import load_library, FetiContext
+from paper_2502_08382_amd import subdomain_dict
+from synth import config_problem
+load_library(LIB)
+ST = 0x7f0012345670
+prob = config_problem(1)
+ctx = FetiContext([subdomain_dict(s) for s in prob.subs], prob.n_lambda, device=0)
+ctx.factor_upload([s.Kreg.data for s in prob.subs], stream=ST)
+ctx.assemble(stream=ST)                       # declared argument types: the handle arrives whole
+print("declared binding ok", flush=True)
+raw = ctypes.CDLL(LIB).fetiF_assemble         # the same entry point without declared argument types
+raw(ctypes.c_void_p(ctx.h.value), ST)         # ctypes passes the int as a C int: 32 bits
+print("not reached", flush=True)
+'''
+
+
+def test_stream_handle_cut_to_32_bits_is_caught(hostsim_lib):
+    """The failure behind an earlier crash of the pipelined benchmark leg: a
+    binding without declared argument types hands a 64-bit stream handle to
+    the library as a C int, and the runtime receives another value.  With
+    the declared types the handle arrives whole; through an undeclared
+    ctypes function the test double of the runtime sees the cut handle and
+    aborts (on the GPU the runtime would dereference it)."""
+    env = dict(os.environ)
+    env["LD_PRELOAD"] = _libasan()
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=0:handle_abort=0"
+    env["HOSTSIM_STREAM"] = "0x7f0012345670"
+    code = f"ROOT = {ROOT!r}\nLIB = {hostsim_lib!r}\n" + TRUNCATION
+    p = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert "declared binding ok" in p.stdout, p.stdout + p.stderr[-3000:]
+    assert "not reached" not in p.stdout
+    assert p.returncode != 0 and "reached the runtime, expected 0x7f0012345670" in p.stderr, p.stderr[-3000:]
+
+
+PIPELINE = r'''
+import sys
+sys.path.insert(0, ROOT)
+from paper_2502_08382_amd.fetif import load_library, FetiContext
+from paper_2502_08382_amd import subdomain_dict
+from synth import config_problem
+load_library(LIB)
+ST = 0x7f0012345670
+prob = config_problem(2, scale=SCALE)
+kv = [s.Kreg.data for s in prob.subs]
+ctx = FetiContext([subdomain_dict(s) for s in prob.subs], prob.n_lambda, device=0, assembly_groups=8, nthreads=16)
+assert ctx.info()["assembly_groups"] == 8
+ctx.factor_upload(kv, stream=ST)
+ctx.factor_assemble(kv, stream=ST)
+ctx.factor_upload(kv[7:107], first=7, stream=ST)
+ctx.factor_assemble(kv, stream=ST)
+ctx.assemble(stream=ST)
+ctx.close()
+print("pipeline done", flush=True)
+'''
+
+
+def _run_pipeline(lib, preload, options_var, options, scale):
+    env = dict(os.environ)
+    env["LD_PRELOAD"] = preload
+    env[options_var] = options
+    env["HOSTSIM_STREAM"] = "0x7f0012345670"
+    code = f"ROOT = {ROOT!r}\nLIB = {lib!r}\nSCALE = {scale!r}\n" + PIPELINE
+    return subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
+
+
+def test_full_size_pipelined_preprocessing_under_address_sanitizer(hostsim_lib):
+    """The benchmark's pipelined leg on the host side at full size: the
+    512-subdomain heat workload (12^3 hexes), 8 assembly groups, 16 host
+    threads, factor upload then pipelined factorisation + copy + assembly
+    (twice, with a partial upload between), under AddressSanitizer."""
+    p = _run_pipeline(hostsim_lib, _libasan(), "ASAN_OPTIONS", "detect_leaks=0:abort_on_error=0", None)
+    out = p.stdout + p.stderr
+    assert "AddressSanitizer" not in out, out[-4000:]
+    assert p.returncode == 0 and "pipeline done" in p.stdout, out[-4000:]
+
+
+def test_pipelined_preprocessing_under_thread_sanitizer(hostsim_tsan_lib):
+    """The same flow under ThreadSanitizer (data races between the host
+    threads of the factorisation, the chunk and group bookkeeping and the
+    staging writes): 512 subdomains of 6^3 hexes, 8 groups, 16 threads."""
+    p = _run_pipeline(hostsim_tsan_lib, _libtsan(), "TSAN_OPTIONS", "halt_on_error=1 report_signal_unsafe=0", (8, 6))
+    out = p.stdout + p.stderr
+    assert "ThreadSanitizer" not in out, out[-4000:]
+    assert p.returncode == 0 and "pipeline done" in p.stdout, out[-4000:]

@@ -452,3 +452,21 @@ def test_nd_order_is_a_permutation_with_the_same_operator(kind):
         I.factor()
         qs.append(I.apply(P.lam))
     assert np.abs(qs[0] - qs[1]).max() <= 1e-12 * np.abs(qs[1]).max()
+
+
+@pytest.mark.parametrize("kind", ["heat3d", "elast3d", "heat2d_tri"])
+def test_sparse_reg_inverse_matches_dense(kind):
+    """The oracle's sparse K_reg^{-1} (its own Cholesky, nested-dissection
+    order, refined) solves like the dense LAPACK one and satisfies
+    K K_reg^{-1} K = K (the generalised-inverse property, Sec. III)."""
+    P = tiny(kind)
+    rng = np.random.default_rng(3)
+    for s in P.subs:
+        inv = orc_impl.SparseRegInverse(s.Kreg, s.coords, s.dpn)
+        ref = feti.RegInverse(s.Kreg)
+        b = rng.standard_normal(s.n)
+        x, xr = inv.solve(b), ref.solve(b)
+        assert np.abs(x - xr).max() <= 1e-13 * np.abs(xr).max()
+        K = s.K.toarray()
+        KXK = K @ np.column_stack([inv.solve(K[:, j]) for j in range(s.n)])
+        assert np.abs(KXK - K).max() <= 1e-10 * np.abs(K).max()
