@@ -177,6 +177,23 @@ fetiF_status fetiF_factor_assemble(fetiF_ctx ctx, const double* const* k_vals, v
  * copy; capturable in a HIP graph.  lambda_d and q_d must not overlap. */
 fetiF_status fetiF_apply(fetiF_ctx ctx, const double* lambda_d, double* q_d, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * application as fetiF_apply (same kernels, same summation order, bitwise
+ * the same q), but the partial vectors of the band kernels live in a
+ * file-scope device array of the library, 64 MiB per device (its address is
+ * looked up once per device at fetiF_create), instead of the context's own
+ * buffer.  Allocates nothing and does no host copy.  Nothing in the array
+ * needs to start at zero: every partial the gather reads is written by the
+ * band kernels of the same call.  All contexts on one device share that
+ * array, so calls of fetiF_apply_static that overlap on one device (other
+ * streams, other contexts, other host threads) race on it: order them.
+ * FETIF_ENOTSUP (nothing enqueued) when the current apply plan's partial
+ * vectors need more than 64 MiB (sum over bands of their last row, times 8
+ * bytes for FP64 storage, 4 otherwise): larger bands (fetiF_set_apply) or
+ * fetiF_apply serve such problems. */
+fetiF_status fetiF_apply_static(fetiF_ctx ctx, const double* lambda_d, double* q_d, void* stream);
+
 /* Re-plan the application (tuning hook): band_elems > 0 sets the stored
  * elements of F~ per work-group (the band/gather tables are rebuilt, which
  * synchronises the device), rows (2 or 4; 0 keeps) the rows per pass of a

@@ -944,6 +944,9 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         hipError_t e_ = (call);                    \
         if (e_ != hipSuccess) return bail(e_, #call); \
     } while (0)
+    // the device address of the static scratch of fetiF_apply_static, looked
+    // up here once per device (with the device current)
+    CK(static_scratch_address(device, &c->dScratch));
     CK(dalloc(c, &c->dL, (size_t)c->total_L));
     CK(dalloc(c, &c->dX, (size_t)c->total_X));
     {
@@ -1294,32 +1297,68 @@ extern "C" fetiF_status fetiF_factor_assemble(fetiF_ctx c, const double* const* 
 
 // ======================================================================== apply
 
-extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double* q_d, void* stream)
+namespace {
+
+// Band kernel + gather of one apply, with the partial vectors in z.
+fetiF_status apply_with_partials(fetiF_ctx c, const double* lambda_d, double* q_d, void* z, hipStream_t st)
 {
-    if (!c) return FETIF_EINVAL;
-    if (c->sticky) return FETIF_EDEVICE;
-    if (!lambda_d || !q_d) return fail(c, FETIF_EINVAL, "lambda or q is NULL");
-    if (lambda_d == q_d) return fail(c, FETIF_EINVAL, "lambda and q must not overlap");
-    if (!c->assembled) return fail(c, FETIF_ESTATE, "apply before assemble");
-    DeviceGuard dg(c->device);
-    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
-    hipStream_t st = (hipStream_t)stream;
     PhaseTimer t4(c, st, 4);
     if (c->opt.apply_seg > 0) {
         const int32_t segw = c->opt.apply_seg * 64 * prec_vec(c->prec);
         const int32_t capp = (c->max_m + segw - 1) / segw * segw;
         HIPCHK(c, launch_apply_seg(c->prec, c->opt.apply_seg, c->opt.apply_rows, c->opt.apply_nontemporal != 0,
-                                   c->dBands, c->dSegPtr, c->ngroups, c->dF, lambda_d, c->dDmap, c->dZ, capp,
+                                   c->dBands, c->dSegPtr, c->ngroups, c->dF, lambda_d, c->dDmap, z, capp,
                                    c->apply_brmax, st));
     } else {
         HIPCHK(c, launch_apply_band(c->prec, c->apply_nch, c->opt.apply_rows, c->opt.apply_nontemporal != 0,
-                                    c->dBands, c->dSegPtr, c->ngroups, c->dF, lambda_d, c->dDmap, c->dZ, st));
+                                    c->dBands, c->dSegPtr, c->ngroups, c->dF, lambda_d, c->dDmap, z, st));
     }
     HIPCHK(c, t4.stop());
     PhaseTimer t5(c, st, 5);
-    HIPCHK(c, launch_gather(c->prec, c->n_lambda, c->dZptr, c->dZpos, c->dZ, q_d, st));
+    HIPCHK(c, launch_gather(c->prec, c->n_lambda, c->dZptr, c->dZpos, z, q_d, st));
     HIPCHK(c, t5.stop());
     return FETIF_OK;
+}
+
+fetiF_status apply_checks(fetiF_ctx c, const double* lambda_d, const double* q_d)
+{
+    if (c->sticky) return FETIF_EDEVICE;
+    if (!lambda_d || !q_d) return fail(c, FETIF_EINVAL, "lambda or q is NULL");
+    if (lambda_d == q_d) return fail(c, FETIF_EINVAL, "lambda and q must not overlap");
+    if (!c->assembled) return fail(c, FETIF_ESTATE, "apply before assemble");
+    return FETIF_OK;
+}
+
+}  // namespace
+
+extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double* q_d, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    const fetiF_status s0 = apply_checks(c, lambda_d, q_d);
+    if (s0 != FETIF_OK) return s0;
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    return apply_with_partials(c, lambda_d, q_d, c->dZ, (hipStream_t)stream);
+}
+
+extern "C" fetiF_status fetiF_apply_static(fetiF_ctx c, const double* lambda_d, double* q_d, void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    const fetiF_status s0 = apply_checks(c, lambda_d, q_d);
+    if (s0 != FETIF_OK) return s0;
+    const size_t need = (size_t)c->total_z * (c->prec == 0 ? 8 : 4);
+    if (need > kStaticScratchBytes) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg,
+                      "fetiF_apply_static: the apply partials need %zu bytes, the static scratch holds %zu "
+                      "(use fetiF_apply, or fewer, larger apply bands)",
+                      need, kStaticScratchBytes);
+        return fail(c, FETIF_ENOTSUP, msg);
+    }
+    if (!c->dScratch) return fail(c, FETIF_ESTATE, "static scratch address not set");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    return apply_with_partials(c, lambda_d, q_d, c->dScratch, (hipStream_t)stream);
 }
 
 extern "C" fetiF_status fetiF_set_assembly(fetiF_ctx c, int32_t trsm_panel, int32_t trsm_chunk)

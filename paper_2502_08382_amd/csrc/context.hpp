@@ -138,6 +138,7 @@ struct fetiF_ctx_s {
     double* dDK = nullptr;
     void* dF = nullptr;
     void* dZ = nullptr;
+    void* dScratch = nullptr;  // device address of the static scratch (fetiF_apply_static)
     DevSN* dSN = nullptr;
     int32_t* dRows = nullptr;
     DevSN* dTSN = nullptr;     // TRSM column panels

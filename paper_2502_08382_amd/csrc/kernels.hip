@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "kernels.hpp"
 
@@ -1277,6 +1278,35 @@ hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* 
     if (prec == 0) return apply_dispatch<double>(nch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, st);
     if (prec == 1) return apply_dispatch<float>(nch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, st);
     return apply_dispatch<bf16_t>(nch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, st);
+}
+
+// ---------------------------------------------------------------- static scratch
+
+namespace {
+// The apply partial vectors of the allocation-free apply.  Host code never
+// passes this name to a kernel (in host code it is a stand-in, not a device
+// address): it uses the address static_scratch_address returns.
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_address(int device, void** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_addr[device] = p;
+    }
+    *out = scratch_addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* zptr, const int64_t* zpos, const void* z,

@@ -67,6 +67,14 @@ hipError_t launch_apply_seg(int prec, int segch, int rows, bool ntl, const Band*
 hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* zptr, const int64_t* zpos, const void* z,
                          double* q, hipStream_t st);
 
+// Size of the file-scope device array `scratch` (kernels.hip) that holds the
+// apply partial vectors of the allocation-free apply: one copy per device,
+// held until the process ends.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+// Device address of `scratch` on `device`, which must be the current device:
+// looked up with hipGetSymbolAddress on the first call per device and cached.
+hipError_t static_scratch_address(int device, void** out);
+
 // elements per 16-byte vector for a storage precision
 inline int prec_vec(int prec) { return prec == 0 ? 2 : (prec == 1 ? 4 : 8); }
 inline int prec_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }

@@ -75,7 +75,8 @@ EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply
            "fetiF_last_error", "fetiF_host_factor", "fetiF_hfactor_info", "fetiF_hfactor_export",
            "fetiF_hfactor_supernodes", "fetiF_hfactor_free", "fetiF_profile_enable",
            "fetiF_profile_read", "fetiF_set_apply", "fetiF_apply_implicit", "fetiF_dual_rhs",
-           "fetiF_coarse_rhs", "fetiF_pcpg", "fetiF_primal", "fetiF_set_assembly", "fetiF_factor_assemble"]
+           "fetiF_coarse_rhs", "fetiF_pcpg", "fetiF_primal", "fetiF_set_assembly", "fetiF_factor_assemble",
+           "fetiF_apply_static"]
 
 PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "solves"]
 
@@ -98,6 +99,7 @@ def load_library(path=None):
     L.fetiF_assemble.argtypes = [vp, vp]
     L.fetiF_factor_assemble.argtypes = [vp, ctypes.POINTER(vp), vp]
     L.fetiF_apply.argtypes = [vp, vp, vp, vp]
+    L.fetiF_apply_static.argtypes = [vp, vp, vp, vp]
     L.fetiF_apply_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fetiF_download_F.argtypes = [vp, i32, vp]
     L.fetiF_query.argtypes = [vp, ctypes.POINTER(_Info)]
@@ -265,6 +267,12 @@ class FetiContext:
     def apply(self, lam, q, stream=None):
         self._vecs(lam=(lam, self.n_lambda), q=(q, self.n_lambda))
         self._check(self.L.fetiF_apply(self.h, _dptr(lam), _dptr(q), _stream(stream)))
+
+    def apply_static(self, lam, q, stream=None):
+        """fetiF_apply with the band partials in the library's static
+        device array (allocation-free; see include/fetiF.h)."""
+        self._vecs(lam=(lam, self.n_lambda), q=(q, self.n_lambda))
+        self._check(self.L.fetiF_apply_static(self.h, _dptr(lam), _dptr(q), _stream(stream)))
 
     def apply_backward(self, g, lam, dlam, dtheta=None, stream=None):
         self._vecs(g=(g, self.n_lambda), lam=(lam, self.n_lambda), dlam=(dlam, self.n_lambda),

@@ -44,6 +44,9 @@ def _build_hostsim(out, sanitizer):
         for m in re.finditer(r"hipError_t\s+(launch_\w+)\s*\(([^;]*?)\);", text, re.S):
             check = "hostsim_check_stream(st); " if re.search(r"hipStream_t\s+st\b", m.group(2)) else ""
             stubs.append(f"hipError_t {m.group(1)}({m.group(2)}) {{ {check}return hipSuccess; }}")
+    # the static scratch of the allocation-free apply: host memory here
+    stubs.append("hipError_t static_scratch_address(int, void** out) "
+                 "{ static unsigned char* buf = new unsigned char[kStaticScratchBytes]; *out = buf; return hipSuccess; }")
     stubs.append("}")
     stub_cpp = out / "launch_stubs.cpp"
     stub_cpp.write_text("\n".join(stubs) + "\n")
@@ -123,6 +126,10 @@ def flow(prob, with_elements=False, **opts):
             for band in (1, 3000, 0):
                 ctx.set_apply(band, 2, 1, split, seg)
                 ctx.apply(lam.ctypes.data, q.ctypes.data, stream=ST)
+                try:
+                    ctx.apply_static(lam.ctypes.data, q.ctypes.data, stream=ST)
+                except FetiError as e:   # partials beyond the static scratch
+                    assert e.status == 6 and "static scratch" in str(e), str(e)
     ctx.apply_implicit(lam.ctypes.data, q.ctypes.data, stream=ST)
     f = np.zeros(sum(s.n for s in prob.subs))
     e = np.zeros(sum(s.R.shape[1] for s in prob.subs))
@@ -143,6 +150,7 @@ def flow(prob, with_elements=False, **opts):
     bad[-1][np.nonzero(A.row == A.col)[0][2]] = -1.0
     expect(5, lambda: ctx.factor_assemble(bad, stream=ST))
     expect(3, lambda: ctx.apply(lam.ctypes.data, q.ctypes.data, stream=ST))
+    expect(3, lambda: ctx.apply_static(lam.ctypes.data, q.ctypes.data, stream=ST))
     expect(5, lambda: ctx.factor_upload(bad, stream=ST))
     ctx.factor_upload(kv, stream=ST)
     ctx.assemble(stream=ST)
