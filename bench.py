@@ -1,21 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the explicit FETI dual operator on one MI355X.
 
-Workload (default): 3D steady heat, 96^3 trilinear hexes torn into 8^3 = 512
-subdomains of 12^3 elements (2197 DOFs each), lognormal(0, 0.5)
-conductivity, Dirichlet on z=0; seeded synthetic data.  One step follows
-the paper's multi-step skeleton (Alg. 2): numeric factorisation of every
-K_reg,i on host threads + copy of the factor values, assembly of every F~_i
-on the GPU (RHS init, supernodal TRSM, SYRK), the dual right-hand sides
-d = B K^+ f - c and e = R^T f, then 200 iterations of the projected
-conjugate gradient solver (Alg. 1), each applying F = sum_i D_i^T F~_i D_i.
-With --prec f32/bf16 the solver instead runs to tol 1e-9 with FP64
-iterative refinement (true residual through the factors).
+Workload (default, the largest of the five): 3D linear elasticity
+(E = 1, nu = 0.3), trilinear hexes, 729 subdomains whose per-axis slab
+widths are drawn from U{6..14} elements (1029..10125 DOFs, 600..3438 local
+multipliers), rigid-body modes removed by fixing three non-collinear corner
+nodes, Dirichlet on z=0; seeded synthetic data.  `--config 2` selects the
+512-subdomain 3D heat workload (12^3 hexes, lognormal(0, 0.5)
+conductivity), `--config 4` the 216-subdomain one (16^3 hexes).  One step
+follows the paper's multi-step skeleton (Alg. 2): numeric factorisation of
+every K_reg,i on host threads + copy of the factor values, assembly of
+every F~_i on the GPU (RHS init, supernodal TRSM, SYRK), the dual
+right-hand sides d = B K^+ f - c and e = R^T f, then 200 iterations of the
+projected conjugate gradient solver (Alg. 1), each applying
+F = sum_i D_i^T F~_i D_i.  With --prec f32/bf16 the solver instead runs to
+tol 1e-9 with FP64 iterative refinement (true residual through the
+factors).
 
 Printed: one JSON line with the apply bandwidth as `value`, the assembly
 time per 1000 subdomains, the break-even iteration count against the CPU
 oracle's implicit apply, the roofline of the dominant kernel and the CPU
-oracle baseline.
+oracle baseline (implicit apply on all host threads and on one, explicit
+assembly and dense apply, the CPU model).
 """
 from __future__ import annotations
 
@@ -41,12 +47,93 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def even_sample(nsub, k):
+    """k subdomain indices spread evenly over 0..nsub-1."""
+    k = max(1, min(int(k), nsub))
+    return sorted({int(round(x)) for x in np.linspace(0, nsub - 1, k)})
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def timed(fn, min_s, min_reps):
+    """Mean seconds per call of fn over at least min_reps calls and min_s
+    seconds (after one untimed call), and the call count."""
+    fn()
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        fn()
+        reps += 1
+        if time.perf_counter() - t0 >= min_s and reps >= min_reps:
+            break
+    return (time.perf_counter() - t0) / reps, reps
+
+
+def cpu_oracle_leg(prob, sample_n):
+    """The oracle as it stands, on the host cores: its implicit apply
+    (sparse Cholesky forward + backward solves) on all threads and on one,
+    and its explicit assembly (one unit solve per local multiplier) and
+    dense apply on all threads, each on an evenly spaced sample of the
+    subdomains scaled to the whole workload by the subdomain count."""
+    from oracle import implicit as orc
+    nthreads = len(os.sched_getaffinity(0))
+    out = {"threads": nthreads, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    N = prob.nsub
+    # implicit apply, all threads
+    idx = even_sample(N, sample_n)
+    t0 = time.time()
+    I = orc.ImplicitCPU([prob.subs[i] for i in idx], prob.n_lambda, nthreads=nthreads)
+    I.factor()
+    log(f"cpu oracle: ordering + factorisation of {len(idx)} subdomains {time.time() - t0:.1f}s")
+    t, reps = timed(lambda: I.apply(prob.lam), 10.0, 3)
+    out["implicit_ms"] = t * N / len(idx) * 1e3
+    out["implicit_sample"] = (f"implicit apply (sparse Cholesky fwd+bwd solves, nested-dissection order) of "
+                              f"{len(idx)} of {N} subdomains (evenly spaced) on {nthreads} threads, {reps} "
+                              f"repetitions, scaled x{N / len(idx):.4g}")
+    # implicit apply, one thread
+    idx1 = even_sample(N, 16)
+    I1 = orc.ImplicitCPU([prob.subs[i] for i in idx1], prob.n_lambda, nthreads=1)
+    I1.factor()
+    t, reps = timed(lambda: I1.apply(prob.lam), 3.0, 2)
+    out["implicit_t1_ms"] = t * N / len(idx1) * 1e3
+    out["implicit_t1_sample"] = (f"{len(idx1)} of {N} subdomains (evenly spaced), 1 thread, {reps} repetitions, "
+                                 f"scaled x{N / len(idx1):.4g}")
+    log(f"cpu oracle implicit apply: {out['implicit_ms']:.1f} ms on {nthreads} threads, "
+        f"{out['implicit_t1_ms']:.1f} ms on 1 thread (whole workload)")
+    del I1
+    # explicit assembly and dense apply, all threads, one subdomain per thread
+    idxe = even_sample(N, nthreads)
+    Ie = orc.ImplicitCPU([prob.subs[i] for i in idxe], prob.n_lambda, nthreads=nthreads)
+    Ie.factor()
+    t0 = time.perf_counter()
+    Ie.assemble()
+    out["assembly_ms"] = (time.perf_counter() - t0) * N / len(idxe) * 1e3
+    t, reps = timed(lambda: Ie.apply_explicit(prob.lam), 3.0, 3)
+    out["explicit_apply_ms"] = t * N / len(idxe) * 1e3
+    out["explicit_sample"] = (f"{len(idxe)} of {N} subdomains (evenly spaced) on {nthreads} threads, assembly "
+                              f"once, dense apply {reps} repetitions, both scaled x{N / len(idxe):.4g}")
+    log(f"cpu oracle explicit: assembly {out['assembly_ms']:.0f} ms, dense apply {out['explicit_apply_ms']:.1f} ms "
+        f"(whole workload)")
+    del Ie
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2, help="workload 1..5")
+    ap.add_argument("--config", type=int, default=3, help="workload 1..5 (default 3, the largest)")
     ap.add_argument("--elem", default="box", choices=["box", "simplex"],
                     help="the workload's box elements, or the same grid cut into linear simplices")
     ap.add_argument("--iters", type=int, default=200,
@@ -55,7 +142,8 @@ def main():
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--precond", default="none", choices=["none", "lumped"],
                     help="M of the PCPG (Alg. 1): identity or the lumped preconditioner")
-    ap.add_argument("--cpu-sample", type=int, default=128, help="subdomains timed by the CPU oracle")
+    ap.add_argument("--cpu-sample", type=int, default=128,
+                    help="subdomains (evenly spaced) of the CPU oracle's implicit apply on all host threads")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--apply-band", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="skip the apply autotuner")
@@ -391,33 +479,27 @@ def main():
         log(f"pipelined factorisation + copy + assembly ({ngroups} groups): {tp:.1f} ms wall, host "
             f"factorisation alone {th:.1f} ms, apply equal to the one-group context: {same}")
 
-    # ---- CPU oracle: implicit apply on host threads, bounded sample
+    # ---- CPU oracle on the host cores, bounded samples of the workload
     if not args.no_cpu:
-        from oracle import implicit as orc
-        S = min(args.cpu_sample, prob.nsub)
-        sample = prob.subs[:S]
-        nthreads = len(os.sched_getaffinity(0))
-        t0 = time.time()
-        I = orc.ImplicitCPU(sample, prob.n_lambda, nthreads=nthreads)
-        I.factor()
-        log(f"cpu oracle: ordering + factorisation of {S} subdomains {time.time() - t0:.1f}s")
-        I.apply(prob.lam)
-        reps = 0
-        tc = time.perf_counter()
-        while True:
-            I.apply(prob.lam)
-            reps += 1
-            if time.perf_counter() - tc > 12.0 and reps >= 3:
-                break
-        t_cpu_sample = (time.perf_counter() - tc) / reps
-        t_cpu = t_cpu_sample * prob.nsub / S * 1e3   # ms per apply of the whole workload
+        cpu = cpu_oracle_leg(prob, args.cpu_sample)
+        t_cpu = cpu["implicit_ms"]
         cpu_gbs = apply_bytes / (t_cpu * 1e-3) / 1e9
         result["cpu_baseline"] = {
-            "value": round(cpu_gbs, 3), "unit": "GB/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"implicit apply (sparse Cholesky fwd+bwd solves, MMD order) of {S} of "
-                      f"{prob.nsub} subdomains, {reps} repetitions, scaled x{prob.nsub / S:g}; "
-                      f"value = the explicit operator's algorithmic bytes per apply / CPU time per apply",
-            "ms_per_apply": round(t_cpu, 3)}
+            "value": round(cpu_gbs, 3), "unit": "GB/s", "cores": cpu["threads"], "kind": "oracle",
+            "sample": cpu["implicit_sample"] + "; value = the explicit operator's algorithmic bytes per apply / "
+                      "CPU time per apply",
+            "ms_per_apply": round(t_cpu, 3),
+            "cpu_model": cpu["cpu_model"], "host_cpus": cpu["host_cpus"],
+            "implicit_1_thread_ms_per_apply": round(cpu["implicit_t1_ms"], 3),
+            "implicit_1_thread_sample": cpu["implicit_t1_sample"],
+            "explicit_assembly_ms": round(cpu["assembly_ms"], 1),
+            "explicit_apply_ms": round(cpu["explicit_apply_ms"], 3),
+            "explicit_sample": cpu["explicit_sample"]}
+        result["gpu_vs_cpu_explicit"] = {
+            "assembly_speedup": round(cpu["assembly_ms"] / t_asm, 1),
+            "apply_speedup": round(cpu["explicit_apply_ms"] / t_apply, 1),
+            "note": "CPU side: the oracle's explicit assembly (one unit solve per local multiplier with its "
+                    "sparse Cholesky factor) and dense apply, on all host threads"}
         denom = t_cpu - t_apply
         result["break_even_iters"] = (math.ceil((t_upload + t_asm) / denom) if denom > 0 else None)
         result["break_even_detail"] = {"t_upload_ms": round(t_upload, 3), "t_assembly_ms": round(t_asm, 3),
