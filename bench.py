@@ -128,6 +128,89 @@ def cpu_oracle_leg(prob, sample_n):
     return out
 
 
+def decision_table():
+    """The paper's assembly parameters (Sec. IV-D, Table 1) measured here,
+    per workload: assembly time of the SYRK and TRSM paths with the
+    nested-dissection order and with the Schur-complement order (multiplier
+    nodes last), each from HIP-event phase timers over 3 assemblies after one
+    warm-up (the assembly tuner's TRSM shape of each context), and the
+    host-vector apply with the scatter/gather on the GPU or on host threads
+    (wall clock, 20 applies after 3 warm-ups, the stored apply shape)."""
+    import torch
+    from synth import config_problem, make_problem
+    from paper_2502_08382_amd import FetiContext, subdomain_dict
+    from paper_2502_08382_amd.fetif import FetiError
+    from paper_2502_08382_amd.autotune import tune_assembly, install_stored_apply_shape
+    workloads = [("3D heat, 64 subdomains of 10^3 hexes", lambda: config_problem(5)),
+                 ("3D heat, 512 subdomains of 12^3 hexes", lambda: config_problem(2)),
+                 ("3D heat, 216 subdomains of 16^3 hexes", lambda: config_problem(4)),
+                 ("2D heat, 256 subdomains of 64^2 quads",
+                  lambda: make_problem(2, "heat", [[64] * 16] * 2, 0.5, dirichlet_axis=0, seed=7))]
+    stream = torch.cuda.Stream()
+    for name, make in workloads:
+        prob = make()
+        kvals = [s.Kreg.data for s in prob.subs]
+        subs = [subdomain_dict(s) for s in prob.subs]
+        out = {"decision_table": name, "subdomains": prob.nsub, "dofs_per_subdomain": int(prob.subs[0].n),
+               "m_max": int(max(s.m for s in prob.subs)), "assembly": {}, "apply_host_ms": {}}
+        for order in (0, 1):
+            t0 = time.time()
+            ctx = FetiContext(subs, prob.n_lambda, device=0, schur_order=order)
+            info = ctx.info()
+            with torch.cuda.stream(stream):
+                th = time.time()
+                ctx.factor_upload(kvals, stream=stream)
+                host_s = time.time() - th
+                tune = tune_assembly(ctx, stream=stream)
+            for path in (0, 1):
+                key = ("schur_order" if order else "nested_dissection") + ("/trsm_path" if path else "/syrk_path")
+                try:
+                    ctx.set_assembly_path(path)
+                except FetiError as e:
+                    out["assembly"][key] = {"skipped": str(e)}
+                    continue
+                with torch.cuda.stream(stream):
+                    ctx.assemble(stream=stream)
+                    torch.cuda.synchronize()
+                    ctx.profile(True)
+                    ctx.profile_read(reset=True)
+                    for _ in range(3):
+                        ctx.assemble(stream=stream)
+                    torch.cuda.synchronize()
+                    ctx.profile(False)
+                    prof = ctx.profile_read(reset=True)
+                ph = {k: round(prof[k][0] / 3, 4) for k in ("rhs_init", "trsm", "syrk", "trsm_bwd", "spmm")
+                      if prof[k][1]}
+                ms = sum(ph.values())
+                inf = ctx.info()
+                flops = inf["trsm_flops"] + (inf["trsm_bwd_flops"] if path else inf["syrk_flops"])
+                out["assembly"][key] = {"ms": round(ms, 3), "ms_per_1k_subdomains": round(1000 * ms / prob.nsub, 3),
+                                        "phases_ms": ph, "algorithmic_flops": flops,
+                                        "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+                                        "trsm_shape": [tune["panel"], tune["chunk"]],
+                                        "factor_values": info["factor_values"],
+                                        "host_factor_s": round(host_s, 3)}
+                log(f"{name}: {key}: {ms:.3f} ms ({ph})")
+            ctx.set_assembly_path(0)
+            if order == 0:
+                with torch.cuda.stream(stream):
+                    ctx.assemble(stream=stream)
+                torch.cuda.synchronize()
+                install_stored_apply_shape(ctx)
+                for sg in (0, 1):
+                    for _ in range(3):
+                        ctx.apply_host(prob.lam, cpu_scatter_gather=sg, stream=stream)
+                    tc = time.perf_counter()
+                    for _ in range(20):
+                        ctx.apply_host(prob.lam, cpu_scatter_gather=sg, stream=stream)
+                    t = (time.perf_counter() - tc) / 20 * 1e3
+                    out["apply_host_ms"]["cpu" if sg else "gpu"] = round(t, 4)
+                    log(f"{name}: host-vector apply, scatter/gather on the {'CPU' if sg else 'GPU'}: {t:.3f} ms")
+            ctx.close()
+            log(f"{name}: order {order} done in {time.time() - t0:.1f}s")
+        print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +240,11 @@ def main():
     ap.add_argument("--pmc-assemble", type=int, default=0, metavar="N",
                     help="profiling mode: upload the factors, install the TRSM shape 96/32 (the tuned one on "
                          "the 3D heat workloads), run N assemblies and exit")
+    ap.add_argument("--decision-table", action="store_true",
+                    help="measure the paper's assembly parameters instead (Sec. IV-D): SYRK vs TRSM path, "
+                         "nested-dissection vs Schur-complement order, scatter/gather on the GPU vs on host "
+                         "threads, on the 64- and 512-subdomain heat workloads, the 216-subdomain one and a 2D "
+                         "heat problem (256 subdomains of 64^2 quads); one JSON line per workload")
     ap.add_argument("--pmc-apply", type=int, default=0, metavar="N",
                     help="profiling mode: assemble, run N applies in the tuned shape, then copy a 1 GiB "
                          "buffer three times (the counter calibration) and exit")
@@ -172,6 +260,9 @@ def main():
     from paper_2502_08382_amd import FetiContext, subdomain_dict
 
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.decision_table:
+        decision_table()
+        return
     dev = torch.device("cuda:0")
     t0 = time.time()
     prob = config_problem(args.config, elem=args.elem)

@@ -128,6 +128,14 @@ typedef struct {
                                 would hold fewer subdomains than there are host threads):
                                 fetiF_factor_assemble factors group g+1 on the host while the
                                 device copies and assembles group g */
+    int32_t schur_order;  /* 1: Schur-complement route (Sec. III, eq. matrix_for_sc): the nodes
+                             that carry Lagrange multipliers are ordered after all others, so
+                             the factorisation of K_reg,i is a partial factorisation of the
+                             interior followed by the Cholesky factor of its Schur complement
+                             on those nodes, and X_i = L^{-1} P B~^T lives in that trailing
+                             block only; the same kernels then assemble F~_i = -S of the
+                             augmented matrix [K_reg B~^T; B~ 0].  0 (default): nested
+                             dissection of all nodes (the SYRK path with a sparse RHS) */
 } fetiF_options;
 
 /* Preparation (Alg. 2, "preparation"; Sec. IV-B "Preparation"): nested
@@ -193,6 +201,35 @@ fetiF_status fetiF_apply(fetiF_ctx ctx, const double* lambda_d, double* q_d, voi
  * bytes for FP64 storage, 4 otherwise): larger bands (fetiF_set_apply) or
  * fetiF_apply serve such problems. */
 fetiF_status fetiF_apply_static(fetiF_ctx ctx, const double* lambda_d, double* q_d, void* stream);
+
+/* Assembly path (Sec. IV-C; the paper's "path" parameter, Sec. IV-D):
+ * 0 (default) the SYRK path, F~_i = X_i^T X_i with X_i = L_i^{-1} P_i B~_i^T;
+ * 1 the TRSM path: the same forward solve, then the backward solve
+ * Z_i = L_i^{-T} X_i (dense, n_i x m_i, every column of every supernode
+ * panel; FP64 MFMA) and the SpMM F~_i = B~_i P_i^T Z_i (a signed row gather)
+ * into the stored triangle.  Path 1 allocates Z for all subdomains (sum n_i
+ * m_i FP64 values; FETIF_ENOMEM if that fails, and path 0 stays) and frees
+ * it when path 0 is set again.  Synchronises the device; the next
+ * fetiF_assemble uses the path (fetiF_factor_assemble supports path 0 only:
+ * FETIF_ENOTSUP).  Both paths give the same F~_i up to rounding. */
+fetiF_status fetiF_set_assembly_path(fetiF_ctx ctx, int32_t path);
+
+/* The application with host-resident cluster vectors, the setting of the
+ * paper's "scatter and gather" parameter (Sec. IV-D, Table 1): lambda_h and
+ * q_h are host arrays of n_lambda FP64 values.
+ *  cpu_scatter_gather = 0: lambda is copied to the device, scattered, applied
+ *    and gathered there (fetiF_apply), and q is copied back;
+ *  cpu_scatter_gather = 1: host threads scatter lambda into the subdomain
+ *    vectors p~_i = D_i lambda (all subdomains in one buffer, so one copy
+ *    instead of one per subdomain), the band kernels apply F~_i to them, the
+ *    band partials are copied back and host threads gather them into q in
+ *    the same fixed order as the gather kernel.
+ * Both give the fetiF_apply result bitwise.  Enqueued on `stream`; returns
+ * when q_h holds the result.  The first call allocates device buffers
+ * (2 n_lambda + sum m_i values) and pinned host staging (the same plus the
+ * band partials); a later apply plan with more partials grows the staging. */
+fetiF_status fetiF_apply_host(fetiF_ctx ctx, const double* lambda_h, double* q_h, int32_t cpu_scatter_gather,
+                              void* stream);
 
 /* Re-plan the application (tuning hook): band_elems > 0 sets the stored
  * elements of F~ per work-group (the band/gather tables are rebuilt, which
@@ -316,6 +353,8 @@ typedef struct {
     int32_t apply_groups;   /* work-groups of one apply */
     int64_t apply_elements; /* stored elements the apply streams (sum of packed triangles) */
     int32_t assembly_groups; /* groups of fetiF_factor_assemble (see fetiF_options) */
+    double trsm_bwd_flops;  /* algorithmic flops of the TRSM path's backward solve (dense RHS:
+                               sum over panels of (ns^2 + 2 ns nr) m_i); 0 on the SYRK path */
 } fetiF_info;
 
 fetiF_status fetiF_query(fetiF_ctx ctx, fetiF_info* info);
@@ -323,12 +362,13 @@ fetiF_status fetiF_query(fetiF_ctx ctx, fetiF_info* info);
 /* Phase timing with HIP events recorded on the caller's stream around each
  * device phase: 0 factor copy (H2D), 1 RHS initialisation, 2 forward TRSM
  * (all levels), 3 SYRK, 4 apply band kernel, 5 apply gather kernel,
- * 6 solves with the factors (implicit apply, dual RHS, adjoint).  fetiF_profile_enable(ctx, 1) starts
+ * 6 solves with the factors (implicit apply, dual RHS, adjoint), 7 backward
+ * TRSM and 8 SpMM of the TRSM path (fetiF_set_assembly_path).  fetiF_profile_enable(ctx, 1) starts
  * recording (it inserts event records, so keep it off inside captured
  * graphs); fetiF_profile_read waits for the recorded events and adds their
  * elapsed times into ms[phase] / counts[phase] for phase < nphases, then
  * forgets them when reset != 0. */
-#define FETIF_NPHASES 7
+#define FETIF_NPHASES 9
 fetiF_status fetiF_profile_enable(fetiF_ctx ctx, int on);
 fetiF_status fetiF_profile_read(fetiF_ctx ctx, int reset, double* ms, int64_t* counts, int32_t nphases);
 

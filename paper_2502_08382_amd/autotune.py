@@ -66,6 +66,8 @@ def tune_apply(ctx, lam, q, bands=None, rows=(2, 4), nontemporal=(1,), splits=(0
     for sg, sp, b, r, n in itertools.product(segs, splits, bands, rows, nontemporal):
         if sg == 8 and r == 4:
             continue   # no such kernel instance
+        if sg == 0 and max(ctx.m) > 4096:
+            continue   # the whole-row kernel holds at most 4096 columns
         ctx.set_apply(b, r, n, sp, sg)
         t, tb = _time_apply(ctx, lam, q, reps, stream)
         trials.append(dict(band=b, rows=r, nontemporal=n, split=sp, seg=sg, ms=t, band_ms=tb))

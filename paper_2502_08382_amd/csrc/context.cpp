@@ -47,6 +47,11 @@ bool plan_subdomain(const fetiF_subdomain& in, const fetiF_options& opt, int64_t
     }
     SymbolicOptions so;
     so.leaf_nodes = opt.leaf_nodes;
+    std::vector<char> last;
+    if (opt.schur_order) {
+        if (!multiplier_nodes(in, last)) { P.err = "b_dof out of range"; return false; }
+        so.last_nodes = &last;
+    }
     int dim = (in.coords && in.dim > 0) ? in.dim : 0;
     if (!symbolic_analysis(A, in.dofs_per_node, dim ? in.coords : nullptr, dim, so, P.sym, P.err)) return false;
     const Symbolic& S = P.sym;
@@ -220,6 +225,18 @@ void plan_apply(fetiF_ctx c, int32_t band_elems, int32_t split, ApplyPlan& A)
             }
         }
         cuts.push_back(P.m);
+        // at most kMaxBandRows rows per band (the segmented kernel keeps a
+        // band's row scalars and sums in LDS): long stretches cut evenly
+        {
+            std::vector<int32_t> capped{0};
+            for (size_t k = 1; k < cuts.size(); ++k) {
+                const int32_t a0 = capped.back(), a1 = cuts[k];
+                const int32_t np = (a1 - a0 + kMaxBandRows - 1) / kMaxBandRows;
+                for (int32_t t = 1; t < np; ++t) capped.push_back(a0 + (int32_t)((int64_t)(a1 - a0) * t / np));
+                capped.push_back(a1);
+            }
+            cuts.swap(capped);
+        }
         for (size_t k = 0; k + 1 < cuts.size(); ++k) {
             const int32_t r0 = cuts[k], r1 = cuts[k + 1];
             if (r1 <= r0) continue;
@@ -337,6 +354,8 @@ hipError_t install_apply(fetiF_ctx c, const ApplyPlan& A)
     if ((e = upload(c->dZpos, A.zpos)) != hipSuccess) return e;
     c->nbands = (int32_t)A.bands.size();
     c->total_z = A.total_z;
+    c->hZptr = A.zptr;
+    c->hZpos = A.zpos;
     c->apply_brmax = 0;
     for (const Band& bd : A.bands) c->apply_brmax = std::max(c->apply_brmax, bd.r1 - bd.r0);
     return hipSuccess;
@@ -527,6 +546,141 @@ hipError_t install_trsm(fetiF_ctx c, const TrsmPlan& T)
     return hipSuccess;
 }
 
+void free_bwd(fetiF_ctx c)
+{
+    for (void* p : c->bwd_allocs) (void)hipFree(p);
+    c->bwd_allocs.clear();
+    c->dZfull = nullptr;
+    c->dBPan = nullptr;
+    c->dBZrow = nullptr;
+    c->dBItems = nullptr;
+    c->dZbase = nullptr;
+    c->dFbase = nullptr;
+    c->blevel_off.clear();
+    c->total_zfull = 0;
+    c->trsm_bwd_flops = 0;
+}
+
+template <typename T>
+hipError_t balloc(fetiF_ctx c, T** p, size_t count)
+{
+    *p = nullptr;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(T) * std::max<size_t>(1, count));
+    if (e == hipSuccess) {
+        c->bwd_allocs.push_back(q);
+        *p = (T*)q;
+    }
+    return e;
+}
+
+// Plan and device tables of the TRSM path's backward solve (Sec. IV-C):
+// column panels of at most `panel` columns of every supernode of every
+// subdomain (Z is dense, so supernodes without RHS columns take part too),
+// levelled like the forward panels (a supernode's panels in a chain, a
+// parent above its children) and run from the top level down; one item per
+// 64 of the subdomain's m_i columns.  Z_i is n_i x m_i row-major.
+hipError_t install_bwd(fetiF_ctx c, int32_t panel)
+{
+    free_bwd(c);
+    std::vector<DevSN> pans;
+    std::vector<int64_t> zrow, zbase(c->nsub), fbase(c->nsub);
+    std::vector<int32_t> plevel;
+    int32_t maxlev = 0;
+    int64_t zb = 0;
+    double flops = 0;
+    for (int32_t i = 0; i < c->nsub; ++i) {
+        const SubPlan& P = c->subs[i];
+        const Symbolic& S = P.sym;
+        zbase[i] = zb;
+        fbase[i] = P.fbase;
+        const int32_t nsn = (int32_t)S.sn.size();
+        std::vector<int32_t> next_level(nsn, 0);
+        auto zoff = [&](int32_t row) { return zb + (int64_t)row * P.m; };
+        for (int32_t s = 0; s < nsn; ++s) {
+            const Supernode& x = S.sn[s];
+            const DevSN& d = c->hSN[P.snbase + s];
+            int32_t L = next_level[s];
+            for (int32_t o = 0; o < x.ncols; o += panel) {
+                const int32_t cw = std::min(panel, x.ncols - o);
+                DevSN t = d;
+                t.lval = d.lval + (int64_t)o * d.ld + o;
+                t.linv = d.linv + (int64_t)(o / 16) * 256;
+                t.xoff = d.xoff + (int64_t)o * P.w[s];
+                t.rowsoff = (int64_t)zrow.size();
+                t.first = x.first + o;
+                t.ncols = cw;
+                t.nrows = x.ncols - o - cw + x.nrows;
+                t.pad = P.m;
+                for (int32_t k = o; k < x.ncols; ++k) zrow.push_back(zoff(x.first + k));
+                for (int32_t k = 0; k < x.nrows; ++k) zrow.push_back(zoff(S.rows[x.row_off + k]));
+                flops += ((double)cw * cw + 2.0 * cw * t.nrows) * P.m;
+                pans.push_back(t);
+                plevel.push_back(L++);
+            }
+            if (x.parent >= 0) next_level[x.parent] = std::max(next_level[x.parent], L);
+            maxlev = std::max(maxlev, L - 1);
+        }
+        zb += (int64_t)P.n * P.m;
+    }
+    // items, level by level (within a level, subdomain by subdomain)
+    std::vector<std::vector<TrsmItem>> lv(maxlev + 1);
+    for (size_t t = 0; t < pans.size(); ++t)
+        for (int32_t c0 = 0; c0 < pans[t].pad; c0 += 64) {
+            TrsmItem it;
+            it.sn = (int32_t)t;
+            it.c0 = c0;
+            it.cw = std::min(64, pans[t].pad - c0);
+            it.pad = 0;
+            lv[plevel[t]].push_back(it);
+        }
+    std::vector<TrsmItem> items;
+    c->blevel_off.assign(maxlev + 2, 0);
+    for (int32_t L = 0; L <= maxlev; ++L) {
+        c->blevel_off[L] = (int64_t)items.size();
+        items.insert(items.end(), lv[L].begin(), lv[L].end());
+    }
+    c->blevel_off[maxlev + 1] = (int64_t)items.size();
+    hipError_t e;
+    if ((e = balloc(c, &c->dZfull, (size_t)zb)) != hipSuccess) return e;
+    if ((e = balloc(c, &c->dBPan, pans.size())) != hipSuccess) return e;
+    if ((e = balloc(c, &c->dBZrow, zrow.size())) != hipSuccess) return e;
+    if ((e = balloc(c, &c->dBItems, items.size())) != hipSuccess) return e;
+    if ((e = balloc(c, &c->dZbase, zbase.size())) != hipSuccess) return e;
+    if ((e = balloc(c, &c->dFbase, fbase.size())) != hipSuccess) return e;
+    if ((e = upload(c->dBPan, pans)) != hipSuccess) return e;
+    if ((e = upload(c->dBZrow, zrow)) != hipSuccess) return e;
+    if ((e = upload(c->dBItems, items)) != hipSuccess) return e;
+    if ((e = upload(c->dZbase, zbase)) != hipSuccess) return e;
+    if ((e = upload(c->dFbase, fbase)) != hipSuccess) return e;
+    c->total_zfull = zb;
+    c->trsm_bwd_flops = flops;
+    return hipSuccess;
+}
+
+// The TRSM path after the forward solve: backward levels from the top
+// down, then the SpMM F~ = B~ P^T Z into the packed triangles.
+hipError_t trsm_path_tail(fetiF_ctx c, hipStream_t st)
+{
+    const int32_t nlev = (int32_t)c->blevel_off.size() - 1;
+    {
+        PhaseTimer t7(c, st, 7);
+        for (int32_t L = nlev - 1; L >= 0; --L) {
+            const int32_t cnt = (int32_t)(c->blevel_off[L + 1] - c->blevel_off[L]);
+            hipError_t e = launch_trsm_bwd_level(c->dBItems + c->blevel_off[L], cnt, 4, c->dBPan, c->dL, c->dLinv,
+                                                 c->dBZrow, c->dX, c->dZfull, st);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = t7.stop();
+        if (e != hipSuccess) return e;
+    }
+    PhaseTimer t8(c, st, 8);
+    hipError_t e = launch_tri_from_z(c->prec, c->nsub, c->sum_m, c->dSubM, c->dStartRows, c->dSignsSorted, c->dZbase,
+                                     c->dFbase, c->dZfull, c->dF, st);
+    if (e != hipSuccess) return e;
+    return t8.stop();
+}
+
 }  // namespace
 
 // ======================================================================== create
@@ -684,17 +838,15 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     c->total_F = fb;
     c->total_rows = rowb;
     c->nsyrk = (int32_t)tiles.size();
-    // apply chunk count: lanes cover NCH * 64 * V columns
+    // chunk count of the whole-row apply kernel (lanes cover NCH * 64 * V
+    // columns, all held in LDS): 0 when the largest subdomain is too wide for
+    // it, and then the column-segmented kernel, which holds any m, serves
     {
         int nch = 1;
         while ((int64_t)nch * 64 * V < max_m) nch *= 2;
-        if ((int64_t)nch * 64 * V > 4096) {
-            std::string msg = "subdomain with m=" + std::to_string(max_m) + " exceeds the 4096 multipliers supported";
-            delete c;
-            return fail(nullptr, FETIF_ENOTSUP, msg);
-        }
-        c->apply_nch = nch;
+        c->apply_nch = (int64_t)nch * 64 * V > kMaxWholeRowCols ? 0 : nch;
         c->max_m = max_m;
+        if (c->apply_nch == 0 && c->opt.apply_seg == 0) c->opt.apply_seg = 4;
     }
     // host copies the TRSM planner needs again when it re-plans
     c->hSN = sns;
@@ -1094,6 +1246,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     CK(upload(c->dTiles, tiles));
     CK(upload(c->dLists, lists));
     CK(upload(c->dDmap, dmap));
+    c->hDmap = dmap;
     CK(install_apply(c, aplan));
     CK(hipHostMalloc((void**)&c->hStage, sizeof(double) * (size_t)std::max<int64_t>(1, c->total_L),
                      hipHostMallocDefault));
@@ -1246,10 +1399,38 @@ extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
     PhaseTimer t2(c, st, 2);
     for (int32_t g = 0; g < G; ++g) HIPCHK(c, trsm_group(c, g, st));
     HIPCHK(c, t2.stop());
-    PhaseTimer t3(c, st, 3);
-    for (int32_t g = 0; g < G; ++g) HIPCHK(c, syrk_group(c, g, st));
-    HIPCHK(c, t3.stop());
+    if (c->assembly_path == 1) {
+        HIPCHK(c, trsm_path_tail(c, st));
+    } else {
+        PhaseTimer t3(c, st, 3);
+        for (int32_t g = 0; g < G; ++g) HIPCHK(c, syrk_group(c, g, st));
+        HIPCHK(c, t3.stop());
+    }
     c->assembled = true;
+    return FETIF_OK;
+}
+
+extern "C" fetiF_status fetiF_set_assembly_path(fetiF_ctx c, int32_t path)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (path != 0 && path != 1) return fail(c, FETIF_EINVAL, "path must be 0 (SYRK) or 1 (TRSM)");
+    if (path == c->assembly_path) return FETIF_OK;
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    HIPCHK(c, hipDeviceSynchronize());
+    if (path == 1) {
+        const hipError_t e = install_bwd(c, c->opt.trsm_panel);
+        if (e == hipErrorOutOfMemory) {
+            free_bwd(c);
+            (void)hipGetLastError();
+            return fail(c, FETIF_ENOMEM, "the TRSM path's dense Z (sum n_i m_i FP64 values) does not fit");
+        }
+        HIPCHK(c, e);
+    } else {
+        free_bwd(c);
+    }
+    c->assembly_path = path;
     return FETIF_OK;
 }
 
@@ -1260,6 +1441,9 @@ extern "C" fetiF_status fetiF_factor_assemble(fetiF_ctx c, const double* const* 
     if (!k_vals) return fail(c, FETIF_EINVAL, "k_vals NULL");
     for (int32_t k = 0; k < c->nsub; ++k)
         if (!k_vals[k]) return fail(c, FETIF_EINVAL, "k_vals entry is NULL");
+    if (c->assembly_path != 0)
+        return fail(c, FETIF_ENOTSUP, "fetiF_factor_assemble runs the SYRK path only (set path 0, or use "
+                                      "fetiF_factor_upload + fetiF_assemble)");
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
@@ -1304,10 +1488,8 @@ fetiF_status apply_with_partials(fetiF_ctx c, const double* lambda_d, double* q_
 {
     PhaseTimer t4(c, st, 4);
     if (c->opt.apply_seg > 0) {
-        const int32_t segw = c->opt.apply_seg * 64 * prec_vec(c->prec);
-        const int32_t capp = (c->max_m + segw - 1) / segw * segw;
         HIPCHK(c, launch_apply_seg(c->prec, c->opt.apply_seg, c->opt.apply_rows, c->opt.apply_nontemporal != 0,
-                                   c->dBands, c->dSegPtr, c->ngroups, c->dF, lambda_d, c->dDmap, z, capp,
+                                   c->dBands, c->dSegPtr, c->ngroups, c->dF, lambda_d, c->dDmap, z,
                                    c->apply_brmax, st));
     } else {
         HIPCHK(c, launch_apply_band(c->prec, c->apply_nch, c->opt.apply_rows, c->opt.apply_nontemporal != 0,
@@ -1361,6 +1543,95 @@ extern "C" fetiF_status fetiF_apply_static(fetiF_ctx c, const double* lambda_d, 
     return apply_with_partials(c, lambda_d, q_d, c->dScratch, (hipStream_t)stream);
 }
 
+extern "C" fetiF_status fetiF_apply_host(fetiF_ctx c, const double* lambda_h, double* q_h, int32_t cpu_scatter_gather,
+                                         void* stream)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (!lambda_h || !q_h) return fail(c, FETIF_EINVAL, "lambda or q is NULL");
+    if (lambda_h == q_h) return fail(c, FETIF_EINVAL, "lambda and q must not overlap");
+    if (cpu_scatter_gather != 0 && cpu_scatter_gather != 1) return fail(c, FETIF_EINVAL, "cpu_scatter_gather must be 0 or 1");
+    if (!c->assembled) return fail(c, FETIF_ESTATE, "apply before assemble");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nl = c->n_lambda, sm = c->sum_m;
+    const size_t zb = (size_t)c->total_z * (c->prec == 0 ? 8 : 4);
+    // buffers on first use (and when a new apply plan needs more partials)
+    if (!c->dHostVec) {
+        HIPCHK(c, hipMalloc((void**)&c->dHostVec, sizeof(double) * (size_t)(2 * nl + sm)));
+        std::vector<int32_t> id((size_t)sm);
+        for (int64_t k = 0; k < sm; ++k) id[(size_t)k] = (int32_t)k;
+        HIPCHK(c, hipMalloc((void**)&c->dDmapId, sizeof(int32_t) * (size_t)std::max<int64_t>(1, sm)));
+        HIPCHK(c, hipMemcpy(c->dDmapId, id.data(), sizeof(int32_t) * (size_t)sm, hipMemcpyHostToDevice));
+    }
+    const size_t need = sizeof(double) * (size_t)(2 * nl + sm) + zb;
+    if (c->hPinBytes < need) {
+        if (c->hPin) HIPCHK(c, hipHostFree(c->hPin));
+        c->hPin = nullptr;
+        c->hPinBytes = 0;
+        HIPCHK(c, hipHostMalloc((void**)&c->hPin, need, hipHostMallocDefault));
+        c->hPinBytes = need;
+    }
+    double* dLam = c->dHostVec;
+    double* dQ = dLam + nl;
+    double* dP = dQ + nl;
+    double* hLam = c->hPin;
+    double* hQ = hLam + nl;
+    double* hP = hQ + nl;
+    void* hZ = hP + sm;
+    if (cpu_scatter_gather == 0) {
+        // the cluster-wide vector to the device, scatter, SYMV and gather
+        // there, the result back
+        std::memcpy(hLam, lambda_h, sizeof(double) * (size_t)nl);
+        HIPCHK(c, hipMemcpyAsync(dLam, hLam, sizeof(double) * (size_t)nl, hipMemcpyHostToDevice, st));
+        const fetiF_status s1 = apply_with_partials(c, dLam, dQ, c->dZ, st);
+        if (s1 != FETIF_OK) return s1;
+        HIPCHK(c, hipMemcpyAsync(hQ, dQ, sizeof(double) * (size_t)nl, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        std::memcpy(q_h, hQ, sizeof(double) * (size_t)nl);
+        return FETIF_OK;
+    }
+    // scatter on the host threads into the subdomain vectors p~_i (sorted
+    // local order, concatenated), one copy to the device, the band kernels
+    // with the identity map, one copy of the band partials back, gather on
+    // the host threads in the same fixed order as the gather kernel
+    const int32_t nchunk = std::max(1, std::min<int32_t>(c->nthreads * 4, (int32_t)((sm + 4095) / 4096)));
+    parallel_for(nchunk, c->nthreads, [&](int32_t k) {
+        const int64_t a = sm * k / nchunk, b = sm * (k + 1) / nchunk;
+        for (int64_t t = a; t < b; ++t) hP[t] = lambda_h[c->hDmap[(size_t)t]];
+    });
+    HIPCHK(c, hipMemcpyAsync(dP, hP, sizeof(double) * (size_t)sm, hipMemcpyHostToDevice, st));
+    {
+        PhaseTimer t4(c, st, 4);
+        if (c->opt.apply_seg > 0) {
+            HIPCHK(c, launch_apply_seg(c->prec, c->opt.apply_seg, c->opt.apply_rows, c->opt.apply_nontemporal != 0,
+                                       c->dBands, c->dSegPtr, c->ngroups, c->dF, dP, c->dDmapId, c->dZ,
+                                       c->apply_brmax, st));
+        } else {
+            HIPCHK(c, launch_apply_band(c->prec, c->apply_nch, c->opt.apply_rows, c->opt.apply_nontemporal != 0,
+                                        c->dBands, c->dSegPtr, c->ngroups, c->dF, dP, c->dDmapId, c->dZ, st));
+        }
+        HIPCHK(c, t4.stop());
+    }
+    HIPCHK(c, hipMemcpyAsync(hZ, c->dZ, zb, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const int32_t gchunk = std::max(1, std::min<int32_t>(c->nthreads * 4, (int32_t)((nl + 4095) / 4096)));
+    const bool f64 = c->prec == 0;
+    parallel_for(gchunk, c->nthreads, [&](int32_t k) {
+        const int64_t a = nl * k / gchunk, b = nl * (k + 1) / gchunk;
+        for (int64_t g = a; g < b; ++g) {
+            double acc = 0.0;
+            for (int32_t t = c->hZptr[(size_t)g]; t < c->hZptr[(size_t)g + 1]; ++t) {
+                const int64_t pos = c->hZpos[(size_t)t];
+                acc += f64 ? ((const double*)hZ)[pos] : (double)((const float*)hZ)[pos];
+            }
+            q_h[g] = acc;
+        }
+    });
+    return FETIF_OK;
+}
+
 extern "C" fetiF_status fetiF_set_assembly(fetiF_ctx c, int32_t trsm_panel, int32_t trsm_chunk)
 {
     if (!c) return FETIF_EINVAL;
@@ -1377,6 +1648,7 @@ extern "C" fetiF_status fetiF_set_assembly(fetiF_ctx c, int32_t trsm_panel, int3
     if (!plan_trsm(c, np, nc, T)) return fail(c, FETIF_ENOTSUP, "TRSM panel does not fit in LDS");
     HIPCHK(c, hipDeviceSynchronize());
     HIPCHK(c, install_trsm(c, T));
+    if (c->assembly_path == 1 && np != c->opt.trsm_panel) HIPCHK(c, install_bwd(c, np));
     c->opt.trsm_panel = np;
     c->opt.trsm_chunk = nc;
     return FETIF_OK;
@@ -1392,6 +1664,10 @@ extern "C" fetiF_status fetiF_set_apply(fetiF_ctx c, int32_t band_elems, int32_t
         return fail(c, FETIF_EINVAL,
                     "band_elems >= 0, rows in {0,2,4}, nontemporal in {-1,0,1}, split in {-1,0,1}, "
                     "seg in {-1,0,4,8}");
+    if (seg == 0 && c->apply_nch == 0)
+        return fail(c, FETIF_ENOTSUP,
+                    "the whole-row apply kernel holds at most " + std::to_string(kMaxWholeRowCols) +
+                        " columns (largest m = " + std::to_string(c->max_m) + "): use seg 4 or 8");
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     if (c->pcpg_graph) {
@@ -1568,6 +1844,7 @@ extern "C" fetiF_status fetiF_query(fetiF_ctx c, fetiF_info* info)
     info->syrk_flops = c->syrk_flops;
     info->factor_flops = c->factor_flops;
     info->trsm_levels = c->trsm_levels;
+    info->trsm_bwd_flops = c->trsm_bwd_flops;
     info->apply_groups = c->ngroups;
     info->assembly_groups = (int32_t)c->grp_first.size() - 1;
     {
@@ -1630,6 +1907,10 @@ extern "C" fetiF_status fetiF_destroy(fetiF_ctx c)
         for (void* p : c->allocations) (void)hipFree(p);
         free_apply(c);
         free_trsm(c);
+        free_bwd(c);
+        if (c->dHostVec) (void)hipFree(c->dHostVec);
+        if (c->dDmapId) (void)hipFree(c->dDmapId);
+        if (c->hPin) (void)hipHostFree(c->hPin);
         if (c->hStage) (void)hipHostFree(c->hStage);
         if (c->hLbKval) (void)hipHostFree(c->hLbKval);
         if (c->upload_done) (void)hipEventDestroy(c->upload_done);

@@ -139,6 +139,15 @@ struct fetiF_ctx_s {
     void* dF = nullptr;
     void* dZ = nullptr;
     void* dScratch = nullptr;  // device address of the static scratch (fetiF_apply_static)
+    // host-vector application (fetiF_apply_host): host copies of the sorted
+    // dual map and of the gather map, and buffers made on first use
+    std::vector<int32_t> hDmap;       // sum m_i: global multiplier of sorted local row (dDmap on the host)
+    std::vector<int32_t> hZptr;       // gather map of the current apply plan (dZptr, dZpos on the host)
+    std::vector<int64_t> hZpos;
+    int32_t* dDmapId = nullptr;       // identity map 0 .. sum m_i - 1
+    double* dHostVec = nullptr;       // device: lambda (n_lambda) | q (n_lambda) | p (sum m_i)
+    double* hPin = nullptr;           // pinned: lambda | q | p (as above), then the partials
+    size_t hPinBytes = 0;
     DevSN* dSN = nullptr;
     int32_t* dRows = nullptr;
     DevSN* dTSN = nullptr;     // TRSM column panels
@@ -162,6 +171,19 @@ struct fetiF_ctx_s {
     std::vector<void*> allocations;
     std::vector<void*> apply_allocs;  // buffers of the current apply plan
     std::vector<void*> trsm_allocs;   // buffers of the current TRSM plan
+    // TRSM path of the assembly (assembly_path 1): backward solve Z = L^{-T} X
+    // over column panels of every supernode, then F~ = B~ P^T Z
+    int32_t assembly_path = 0;
+    std::vector<void*> bwd_allocs;    // Z, its panel tables and the F gather tables
+    double* dZfull = nullptr;         // sum n_i m_i, row-major per subdomain
+    DevSN* dBPan = nullptr;
+    int64_t* dBZrow = nullptr;
+    TrsmItem* dBItems = nullptr;
+    int64_t* dZbase = nullptr;        // per subdomain: offset of Z_i
+    int64_t* dFbase = nullptr;        // per subdomain: offset of F~_i
+    std::vector<int64_t> blevel_off;  // backward items of panel level L: [blevel_off[L], blevel_off[L + 1])
+    int64_t total_zfull = 0;
+    double trsm_bwd_flops = 0;
     // phase timing
     struct Rec {
         int phase;

@@ -39,6 +39,17 @@ bool pattern_from_sub(const fetiF_subdomain& s, Pattern& A, std::string& err)
     return true;
 }
 
+bool multiplier_nodes(const fetiF_subdomain& s, std::vector<char>& flags)
+{
+    if (s.dofs_per_node <= 0 || s.n % s.dofs_per_node) return false;
+    flags.assign((size_t)(s.n / s.dofs_per_node), 0);
+    for (int32_t j = 0; j < s.m; ++j) {
+        if (!s.b_dof || s.b_dof[j] < 0 || s.b_dof[j] >= s.n) return false;
+        flags[(size_t)(s.b_dof[j] / s.dofs_per_node)] = 1;
+    }
+    return true;
+}
+
 void options_defaults(const fetiF_options* in, fetiF_options& o)
 {
     std::memset(&o, 0, sizeof(o));
@@ -53,6 +64,7 @@ void options_defaults(const fetiF_options* in, fetiF_options& o)
     if (o.trsm_panel <= 0) o.trsm_panel = 48;
     o.trsm_panel = std::max(16, std::min(96, (o.trsm_panel + 15) / 16 * 16));
     if (o.assembly_groups <= 0) o.assembly_groups = 1;
+    o.schur_order = o.schur_order != 0 ? 1 : 0;
 }
 
 }  // namespace fetif
@@ -73,6 +85,14 @@ extern "C" fetiF_status fetiF_host_factor(const fetiF_subdomain* sub, const doub
     if (!h) return FETIF_ENOMEM;
     SymbolicOptions so;
     so.leaf_nodes = o.leaf_nodes;
+    std::vector<char> last;
+    if (o.schur_order) {
+        if (!multiplier_nodes(*sub, last)) {
+            delete h;
+            return FETIF_EINVAL;
+        }
+        so.last_nodes = &last;
+    }
     int dim = sub->coords ? sub->dim : 0;
     if (!symbolic_analysis(A, sub->dofs_per_node, dim > 0 ? sub->coords : nullptr, dim, so, h->sym, err)) {
         delete h;

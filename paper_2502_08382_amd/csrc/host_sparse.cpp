@@ -185,7 +185,7 @@ static void nd_rec(NDState& st, std::vector<int32_t> nodes, int depth)
 }  // namespace
 
 std::vector<int32_t> nested_dissection(const Pattern& A, int dpn, const double* coords, int dim,
-                                       int leaf_nodes)
+                                       int leaf_nodes, const std::vector<char>* last)
 {
     NodeGraph g = node_graph(A, dpn);
     NDState st;
@@ -194,9 +194,14 @@ std::vector<int32_t> nested_dissection(const Pattern& A, int dpn, const double* 
     st.dim = dim;
     st.leaf = std::max(1, leaf_nodes);
     st.side.assign(g.n, 0);
-    std::vector<int32_t> all(g.n);
-    std::iota(all.begin(), all.end(), 0);
+    std::vector<int32_t> all, tail;
+    all.reserve(g.n);
+    for (int32_t v = 0; v < g.n; ++v) {
+        if (last && (*last)[v]) tail.push_back(v);
+        else all.push_back(v);
+    }
     nd_rec(st, std::move(all), 0);
+    st.order.insert(st.order.end(), tail.begin(), tail.end());
     std::vector<int32_t> perm((size_t)A.n);
     for (int32_t k = 0; k < g.n; ++k)
         for (int c = 0; c < dpn; ++c) perm[(size_t)k * dpn + c] = st.order[k] * dpn + c;
@@ -309,7 +314,11 @@ bool symbolic_analysis(const Pattern& A, int dpn, const double* coords, int dim,
                 err = "column index out of range";
                 return false;
             }
-    std::vector<int32_t> perm = nested_dissection(A, dpn, coords, dim, opt.leaf_nodes);
+    if (opt.last_nodes && (int64_t)opt.last_nodes->size() != n / dpn) {
+        err = "node flag count does not match the pattern";
+        return false;
+    }
+    std::vector<int32_t> perm = nested_dissection(A, dpn, coords, dim, opt.leaf_nodes, opt.last_nodes);
     std::vector<int32_t> pinv(n);
     for (int32_t k = 0; k < n; ++k) pinv[perm[k]] = k;
     std::vector<int32_t> cptr, crow, csrc;

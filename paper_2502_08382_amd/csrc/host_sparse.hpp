@@ -22,8 +22,10 @@ struct Pattern {
 // vertex separator of the graph; without coordinates the separator is the
 // middle level of a breadth-first level structure.  DOFs of one node
 // (dof = dpn*node + comp) stay together.
+// With `last` (one flag per node), the flagged nodes are left out of the
+// dissection and ordered after all others, ascending.
 std::vector<int32_t> nested_dissection(const Pattern& A, int dpn, const double* coords, int dim,
-                                       int leaf_nodes);
+                                       int leaf_nodes, const std::vector<char>* last = nullptr);
 
 struct Supernode {
     int32_t first = 0;   // first column (permuted order)
@@ -62,6 +64,11 @@ struct SymbolicOptions {
     // column range of the smaller one in the sparse-RHS triangular solve.
     int relax_cols[4] = {4, 16, 48, 96};
     double relax_zeros[3] = {0.8, 0.2, 0.05};
+    // nodes ordered last (one flag per node), or none: the Schur-complement
+    // route orders the nodes that carry Lagrange multipliers last, so the
+    // trailing block of L is the Cholesky factor of the Schur complement of
+    // the interior and the RHS columns of B~^T start in it
+    const std::vector<char>* last_nodes = nullptr;
 };
 
 bool symbolic_analysis(const Pattern& A, int dpn, const double* coords, int dim,

@@ -353,6 +353,151 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 4 ?
     }
 }
 
+// ---------------------------------------------------------------- TRSM path
+
+// Backward supernodal solve of the TRSM path (Sec. IV-C, two TRSMs and an
+// SpMM): Z_i = L_i^{-T} X_i with X_i the forward solution, Z_i dense
+// (n_i x m_i, row-major, columns in the sorted multiplier order).  One
+// work-group takes 16 W of the m_i columns of one column panel p (record
+// `pans[it.sn]`: ncols panel columns, nrows rows below them -- the later
+// columns of its supernode, then the supernode's below rows --, ld, the
+// panel's L and inverse offsets, its compact X block (xoff, j0, w: X is
+// zero outside the RHS range [j0, j0 + w)), zrow[rowsoff + k] the Z offset
+// of row k of the panel (the ncols panel rows, then the below rows), and
+// pad = m_i); wavefront wv owns 16 of them.  Levels run from the root
+// down, so every row below the panel is solved already:
+//   acc = X[panel rows] - L[below, panel]^T Z[below]   (MFMA over the below rows, 16 at a time)
+//   rb = nb-1 .. 0:  Z[rb] = inv(L[rb,rb])^T (acc[rb] - sum_{kb > rb} L[kb,rb]^T Z[kb])
+// With the accumulator layout (register r holds rows q + 4r), register r
+// of a solved block is the B operand of k-step r of the next product.
+template <int W>
+__global__ __launch_bounds__(64 * W) void trsm_bwd_level_kernel(const TrsmItem* __restrict__ items,
+                                                                const DevSN* __restrict__ pans,
+                                                                const double* __restrict__ L,
+                                                                const double* __restrict__ Linv,
+                                                                const int64_t* __restrict__ zrow,
+                                                                const double* __restrict__ X,
+                                                                double* __restrict__ Z)
+{
+    const TrsmItem it = items[blockIdx.x];
+    if (it.cw == 0) return;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int q = lane >> 4, j = lane & 15;
+    if (wv * 16 >= it.cw) return;
+    const DevSN s = pans[it.sn];
+    const int ns = s.ncols, nr = s.nrows, d = s.ld;
+    const int nb = (ns + 15) >> 4;
+    const double* __restrict__ P = L + s.lval;
+    const int64_t* __restrict__ zr = zrow + s.rowsoff;
+    const int col = it.c0 + wv * 16 + j;               // column of Z (sorted multiplier order)
+    const bool cv = wv * 16 + j < it.cw;
+    const bool xin = cv && col >= s.j0 && col < s.j0 + s.w;
+    d4 acc[kTrsmMaxNb];
+#pragma unroll
+    for (int kb = 0; kb < kTrsmMaxNb; ++kb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = kb * 16 + q + 4 * r;
+            acc[kb][r] = (kb < nb && xin && row < ns) ? X[s.xoff + (int64_t)row * s.w + (col - s.j0)] : 0.0;
+        }
+    // below rows, 16 per step (4 k-steps of 4): the next step's Z rows and
+    // L operands are requested before the current step's MFMAs
+    auto load_step = [&](int k0, double (&zb)[4], double (&a)[kTrsmMaxNb][4]) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = k0 + 4 * kk + q;
+            zb[kk] = (k < nr && cv) ? Z[zr[ns + k] + col] : 0.0;
+#pragma unroll
+            for (int kb = 0; kb < kTrsmMaxNb; ++kb)
+                a[kb][kk] = (kb < nb && k < nr && kb * 16 + j < ns) ? -P[(int64_t)(kb * 16 + j) * d + ns + k] : 0.0;
+        }
+    };
+    if (nr > 0) {
+        double zb[4], a[kTrsmMaxNb][4];
+        load_step(0, zb, a);
+        for (int k0 = 0; k0 < nr; k0 += 16) {
+            double zbn[4], an[kTrsmMaxNb][4];
+            load_step(k0 + 16, zbn, an);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                for (int kb = 0; kb < kTrsmMaxNb; ++kb) {
+                    if (kb >= nb) break;                 // wavefront-uniform
+                    acc[kb] = mfma16(a[kb][kk], zb[kk], acc[kb]);
+                }
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                zb[kk] = zbn[kk];
+#pragma unroll
+                for (int kb = 0; kb < kTrsmMaxNb; ++kb) a[kb][kk] = an[kb][kk];
+            }
+        }
+    }
+    // the panel's own rows, last row block first
+    const double* __restrict__ PI = Linv + s.linv;
+    d4 zs[kTrsmMaxNb];
+#pragma unroll
+    for (int rb = kTrsmMaxNb - 1; rb >= 0; --rb) {
+        if (rb >= nb) continue;                          // wavefront-uniform
+        d4 t = acc[rb];
+#pragma unroll
+        for (int kb = rb + 1; kb < kTrsmMaxNb; ++kb) {
+            if (kb >= nb) break;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = kb * 16 + q + 4 * r, cl = rb * 16 + j;
+                const double av = (row < ns && cl < ns) ? -P[(int64_t)cl * d + row] : 0.0;
+                t = mfma16(av, zs[kb][r], t);
+            }
+        }
+        d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z = mfma16(PI[rb * 256 + j * 16 + q + 4 * r], t[r], z);
+        zs[rb] = z;
+    }
+    if (cv) {
+#pragma unroll
+        for (int rb = 0; rb < kTrsmMaxNb; ++rb) {
+            if (rb >= nb) break;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rb * 16 + q + 4 * r;
+                if (row < ns) Z[zr[row] + col] = zs[rb][r];
+            }
+        }
+    }
+}
+
+// F~_i = B~_i P_i^T Z_i, the SpMM of the TRSM path: row a (sorted order) of
+// F~_i is sign_a times row start_a of Z_i; its columns 0..a go to the packed
+// triangle in the storage precision.  One wavefront per row of every F~_i
+// (global sorted row g of subdomain i: sub_m[i] <= g < sub_m[i + 1]).
+template <typename T>
+__global__ __launch_bounds__(NT) void tri_from_z_kernel(int32_t nsub, int64_t nrows, const int32_t* __restrict__ sub_m,
+                                                        const int32_t* __restrict__ start_rows,
+                                                        const int8_t* __restrict__ signs,
+                                                        const int64_t* __restrict__ zbase,
+                                                        const int64_t* __restrict__ fbase,
+                                                        const double* __restrict__ Z, T* __restrict__ F)
+{
+    const int64_t g = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= nrows) return;
+    int lo = 0, hi = nsub;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sub_m[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    const int a = (int)(g - sub_m[lo]);
+    const int m = sub_m[lo + 1] - sub_m[lo];
+    constexpr int RA = kRowAlignBytes / sizeof(T);
+    const double sg = (double)signs[g];
+    const double* __restrict__ zrw = Z + zbase[lo] + (int64_t)start_rows[g] * m;
+    T* __restrict__ fr = F + fbase[lo] + packed_row_offset(a, RA);
+    for (int b = lane; b <= a; b += 64) store_f<T>(fr + b, sg * zrw[b]);
+}
+
 // ---------------------------------------------------------------- TRSV
 
 // x <- P B~^T D v for every subdomain (one work-group per subdomain).  The
@@ -702,6 +847,12 @@ struct Acc<bf16_t> {
     using type = float;
 };
 
+template <typename T>
+constexpr int prec_of()
+{
+    return sizeof(T) == 8 ? 0 : (sizeof(T) == 4 ? 1 : 2);
+}
+
 template <typename T, int VEC>
 __device__ __forceinline__ void unpack(const uint4& raw, typename Acc<T>::type (&v)[VEC]);
 template <>
@@ -769,7 +920,8 @@ __device__ __forceinline__ uint4 load16(const void* p)
 // partials, added in a fixed order at the end.  Row padding is zero (F is
 // cleared at creation and only c <= r is ever stored) and so is p beyond r1,
 // so the inner loop needs no per-element test except keeping the diagonal
-// out of the column partials.
+// out of the column partials, and that only in the chunks that reach the
+// pass's first row.
 template <typename T, int NCH, int ROWS, bool NTL>
 __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__ bands,
                                                         const int32_t* __restrict__ seg_ptr,
@@ -836,14 +988,29 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
             A pc[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) pc[e] = sp[col + e];
+            // only a chunk reaching column r can hold a diagonal element of
+            // the pass's rows (wavefront-uniform test); the others need no mask
+            if ((ch + 1) * CH <= r) {
 #pragma unroll
-            for (int k = 0; k < ROWS; ++k) {
-                A v[VEC];
-                unpack<T, VEC>(raw[k][c2], v);
+                for (int k = 0; k < ROWS; ++k) {
+                    A v[VEC];
+                    unpack<T, VEC>(raw[k][c2], v);
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) {
-                    dot[k] += v[e] * pc[e];
-                    y[c2][e] += (col + e == rr[k] ? (A)0 : v[e]) * pr[k];
+                    for (int e = 0; e < VEC; ++e) {
+                        dot[k] += v[e] * pc[e];
+                        y[c2][e] += v[e] * pr[k];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < ROWS; ++k) {
+                    A v[VEC];
+                    unpack<T, VEC>(raw[k][c2], v);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        dot[k] += v[e] * pc[e];
+                        y[c2][e] += (col + e == rr[k] ? (A)0 : v[e]) * pr[k];
+                    }
                 }
             }
         }
@@ -903,18 +1070,22 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
 // segment, the band rows that reach into it are spread over the four
 // wavefronts, ROWS consecutive rows per pass, each wavefront reading whole
 // row pieces (no pair split), so the per-lane column partials and load
-// buffers are bounded by the segment, not by m.  Row dots add up across
-// segments in `sband` (LDS, one entry per band row); after a segment its
-// column sums are complete: columns left of the band go to z at once, the
-// band's own columns are added to `sband`.  Every sum has a fixed order.
-// Dynamic LDS: sp[capp] (p, zero past r1), sseg[SEGW], sband[brmax].
+// buffers are bounded by the segment, not by m.  p = lambda[D_i] is held in
+// LDS for the band's own rows (`spr`, their row scalars) and for the
+// current segment's columns (`spc`, refilled per segment, zero past r1), so
+// the LDS a work-group needs is bounded by the segment width and the rows
+// of a band, whatever m is.  Row dots add up across segments in `sband`
+// (one entry per band row); after a segment its column sums are complete:
+// columns left of the band go to z at once, the band's own columns are
+// added to `sband`.  Every sum has a fixed order.
+// Dynamic LDS: spr[brmax], sband[brmax], spc[SEGW], sseg[SEGW].
 template <typename T, int SEGCH, int ROWS, bool NTL>
 __global__ __launch_bounds__(NT) void apply_seg_kernel(const Band* __restrict__ bands,
                                                        const int32_t* __restrict__ seg_ptr,
                                                        const T* __restrict__ F,
                                                        const double* __restrict__ lam,
                                                        const int32_t* __restrict__ dmap,
-                                                       typename Acc<T>::type* __restrict__ z, int32_t capp)
+                                                       typename Acc<T>::type* __restrict__ z, int32_t brmax)
 {
     using A = typename Acc<T>::type;
     constexpr int VEC = 16 / sizeof(T);
@@ -922,20 +1093,24 @@ __global__ __launch_bounds__(NT) void apply_seg_kernel(const Band* __restrict__ 
     constexpr int CH = 64 * VEC;          // columns per chunk
     constexpr int SEGW = SEGCH * CH;      // columns per segment
     extern __shared__ double smem_d[];
-    A* __restrict__ sp = reinterpret_cast<A*>(smem_d);
-    A* __restrict__ sseg = sp + capp;
-    A* __restrict__ sband = sseg + SEGW;
+    A* __restrict__ spc = reinterpret_cast<A*>(smem_d);
+    A* __restrict__ sseg = spc + SEGW;
+    A* __restrict__ spr = sseg + SEGW;
+    A* __restrict__ sband = spr + brmax;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int seg = seg_ptr[blockIdx.x]; seg < seg_ptr[blockIdx.x + 1]; ++seg) {
     const Band b = bands[seg];
-    for (int c = tid; c < capp; c += NT) sp[c] = c < b.r1 ? (A)lam[dmap[b.dbase + c]] : (A)0;
-    for (int c = tid; c < b.r1 - b.r0; c += NT) sband[c] = (A)0;
-    __syncthreads();
+    for (int c = tid; c < b.r1 - b.r0; c += NT) {
+        spr[c] = (A)lam[dmap[b.dbase + b.r0 + c]];
+        sband[c] = (A)0;
+    }
     const char* __restrict__ tri = reinterpret_cast<const char*>(F + b.fbase);
     const int nseg = (b.r1 + SEGW - 1) / SEGW;
     for (int cs = 0; cs < nseg; ++cs) {
         const int c0 = cs * SEGW;
+        for (int c = tid; c < SEGW; c += NT) spc[c] = c0 + c < b.r1 ? (A)lam[dmap[b.dbase + c0 + c]] : (A)0;
+        __syncthreads();
         A y[SEGCH][VEC];
 #pragma unroll
         for (int ch = 0; ch < SEGCH; ++ch)
@@ -964,7 +1139,7 @@ __global__ __launch_bounds__(NT) void apply_seg_kernel(const Band* __restrict__ 
             for (int k = 0; k < ROWS; ++k) {
                 rr[k] = (r + k < b.r1) ? r + k : -1;
                 rmax = rr[k] > rmax ? rr[k] : rmax;
-                pr[k] = rr[k] >= 0 ? sp[rr[k]] : (A)0;
+                pr[k] = rr[k] >= 0 ? spr[rr[k] - b.r0] : (A)0;
                 dot[k] = (A)0;
             }
 #pragma unroll
@@ -973,15 +1148,30 @@ __global__ __launch_bounds__(NT) void apply_seg_kernel(const Band* __restrict__ 
                 const int col = c0 + ch * CH + lane * VEC;
                 A pc[VEC];
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) pc[e] = sp[col + e];
+                for (int e = 0; e < VEC; ++e) pc[e] = spc[ch * CH + lane * VEC + e];
+                // only a chunk reaching column r can hold a diagonal element
+                // of the pass's rows (wavefront-uniform test)
+                if (c0 + (ch + 1) * CH <= r) {
 #pragma unroll
-                for (int k = 0; k < ROWS; ++k) {
-                    A v[VEC];
-                    unpack<T, VEC>(raw[k][ch], v);
+                    for (int k = 0; k < ROWS; ++k) {
+                        A v[VEC];
+                        unpack<T, VEC>(raw[k][ch], v);
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) {
-                        dot[k] += v[e] * pc[e];
-                        y[ch][e] += (col + e == rr[k] ? (A)0 : v[e]) * pr[k];
+                        for (int e = 0; e < VEC; ++e) {
+                            dot[k] += v[e] * pc[e];
+                            y[ch][e] += v[e] * pr[k];
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < ROWS; ++k) {
+                        A v[VEC];
+                        unpack<T, VEC>(raw[k][ch], v);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            dot[k] += v[e] * pc[e];
+                            y[ch][e] += (col + e == rr[k] ? (A)0 : v[e]) * pr[k];
+                        }
                     }
                 }
             }
@@ -1092,6 +1282,38 @@ hipError_t launch_trsm_level(const TrsmItem* items, int32_t nitems, int32_t wave
         hipLaunchKernelGGL(trsm_level_kernel<2>, dim3(nitems), dim3(128), lds, st, items, nbmax, sns, L, Linv, rowoff, X);
     else
         hipLaunchKernelGGL(trsm_level_kernel<1>, dim3(nitems), dim3(64), lds, st, items, nbmax, sns, L, Linv, rowoff, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm_bwd_level(const TrsmItem* items, int32_t nitems, int32_t waves, const DevSN* pans,
+                                 const double* L, const double* Linv, const int64_t* zrow, const double* X, double* Z,
+                                 hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (waves == 4)
+        hipLaunchKernelGGL(trsm_bwd_level_kernel<4>, dim3(nitems), dim3(256), 0, st, items, pans, L, Linv, zrow, X, Z);
+    else if (waves == 2)
+        hipLaunchKernelGGL(trsm_bwd_level_kernel<2>, dim3(nitems), dim3(128), 0, st, items, pans, L, Linv, zrow, X, Z);
+    else
+        hipLaunchKernelGGL(trsm_bwd_level_kernel<1>, dim3(nitems), dim3(64), 0, st, items, pans, L, Linv, zrow, X, Z);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_from_z(int prec, int32_t nsub, int64_t nrows, const int32_t* sub_m, const int32_t* start_rows,
+                             const int8_t* signs, const int64_t* zbase, const int64_t* fbase, const double* Z,
+                             void* F, hipStream_t st)
+{
+    if (nrows <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((nrows + NT / 64 - 1) / (NT / 64)));
+    if (prec == 0)
+        hipLaunchKernelGGL(tri_from_z_kernel<double>, grid, dim3(NT), 0, st, nsub, nrows, sub_m, start_rows, signs,
+                           zbase, fbase, Z, (double*)F);
+    else if (prec == 1)
+        hipLaunchKernelGGL(tri_from_z_kernel<float>, grid, dim3(NT), 0, st, nsub, nrows, sub_m, start_rows, signs,
+                           zbase, fbase, Z, (float*)F);
+    else
+        hipLaunchKernelGGL(tri_from_z_kernel<bf16_t>, grid, dim3(NT), 0, st, nsub, nrows, sub_m, start_rows, signs,
+                           zbase, fbase, Z, (bf16_t*)F);
     return hipGetLastError();
 }
 
@@ -1227,47 +1449,46 @@ static hipError_t apply_dispatch(int nch, int rows, bool ntl, const Band* bands,
 
 template <typename T, int SEGCH, int ROWS, bool NTL>
 static hipError_t seg_launch(const Band* bands, const int32_t* seg_ptr, int32_t ngroups, const void* F,
-                             const double* lam, const int32_t* dmap, void* z, int32_t capp, int32_t brmax,
-                             hipStream_t st)
+                             const double* lam, const int32_t* dmap, void* z, int32_t brmax, hipStream_t st)
 {
     using A = typename Acc<T>::type;
-    constexpr int SEGW = SEGCH * 64 * (16 / (int)sizeof(T));
-    const size_t lds = sizeof(A) * ((size_t)capp + SEGW + brmax);
+    const size_t lds = apply_seg_lds_bytes(prec_of<T>(), SEGCH, brmax);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)apply_seg_kernel<T, SEGCH, ROWS, NTL>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((apply_seg_kernel<T, SEGCH, ROWS, NTL>), dim3(ngroups), dim3(NT), lds, st, bands, seg_ptr,
-                       (const T*)F, lam, dmap, (A*)z, capp);
+                       (const T*)F, lam, dmap, (A*)z, brmax);
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t seg_dispatch(int segch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
                                int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
-                               int32_t capp, int32_t brmax, hipStream_t st)
+                               int32_t brmax, hipStream_t st)
 {
     // instances: (4 chunks, 2 or 4 rows) and (8 chunks, 2 rows); 8 chunks
     // with 4 rows would not fit two wavefronts per SIMD
     if (segch == 8)
-        return ntl ? seg_launch<T, 8, 2, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st)
-                   : seg_launch<T, 8, 2, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
+        return ntl ? seg_launch<T, 8, 2, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st)
+                   : seg_launch<T, 8, 2, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
     if (rows == 4)
-        return ntl ? seg_launch<T, 4, 4, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st)
-                   : seg_launch<T, 4, 4, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
-    return ntl ? seg_launch<T, 4, 2, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st)
-               : seg_launch<T, 4, 2, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
+        return ntl ? seg_launch<T, 4, 4, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st)
+                   : seg_launch<T, 4, 4, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
+    return ntl ? seg_launch<T, 4, 2, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st)
+               : seg_launch<T, 4, 2, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
 }
 
 hipError_t launch_apply_seg(int prec, int segch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
                             int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
-                            int32_t capp, int32_t brmax, hipStream_t st)
+                            int32_t brmax, hipStream_t st)
 {
     if (ngroups <= 0) return hipSuccess;
-    if (prec == 0) return seg_dispatch<double>(segch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
-    if (prec == 1) return seg_dispatch<float>(segch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
-    return seg_dispatch<bf16_t>(segch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, capp, brmax, st);
+    if (brmax <= 0 || brmax > kMaxBandRows) return hipErrorInvalidValue;
+    if (prec == 0) return seg_dispatch<double>(segch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
+    if (prec == 1) return seg_dispatch<float>(segch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
+    return seg_dispatch<bf16_t>(segch, rows, ntl, bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
 }
 
 hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,

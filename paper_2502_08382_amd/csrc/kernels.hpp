@@ -23,6 +23,16 @@ hipError_t launch_diag_inverse(const InvItem* items, int32_t nitems, const DevSN
 hipError_t launch_trsm_level(const TrsmItem* items, int32_t nitems, int32_t waves, int32_t max_ns,
                              const DevSN* sns, const double* L, const double* Linv, const int64_t* rowoff,
                              double* X, hipStream_t st);
+// TRSM path (two TRSMs + SpMM): one level of the backward solve Z = L^{-T} X
+// over column panels of every supernode (dense RHS, all m_i columns;
+// pans[].pad = m_i, zrow = Z offsets of each panel's rows then below rows)
+hipError_t launch_trsm_bwd_level(const TrsmItem* items, int32_t nitems, int32_t waves, const DevSN* pans,
+                                 const double* L, const double* Linv, const int64_t* zrow, const double* X, double* Z,
+                                 hipStream_t st);
+// F~_i = B~_i P^T Z_i into the packed triangles (nrows = sum m_i)
+hipError_t launch_tri_from_z(int prec, int32_t nsub, int64_t nrows, const int32_t* sub_m, const int32_t* start_rows,
+                             const int8_t* signs, const int64_t* zbase, const int64_t* fbase, const double* Z,
+                             void* F, hipStream_t st);
 // dynamic LDS bytes of a TRSM level launch
 inline size_t trsm_lds_bytes(int32_t waves, int32_t max_ns) { return (size_t)waves * ((max_ns + 15) / 16) * 2048; }
 // ---- batched supernodal solves with L (nrhs = 1 or 2, vectors interleaved:
@@ -57,12 +67,25 @@ hipError_t launch_syrk(int prec, const SyrkTile* tiles, int32_t ntiles, const in
 hipError_t launch_apply_band(int prec, int nch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
                              int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
                              hipStream_t st);
-// column-segmented apply: segch chunks per segment (4 or 8); capp = LDS
-// columns of p (a multiple of the segment width, >= every r1), brmax = most
-// rows of a band
+// column-segmented apply: segch chunks per segment (4 or 8); brmax = most
+// rows of a band (1 .. kMaxBandRows); any m
 hipError_t launch_apply_seg(int prec, int segch, int rows, bool ntl, const Band* bands, const int32_t* seg_ptr,
                             int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
-                            int32_t capp, int32_t brmax, hipStream_t st);
+                            int32_t brmax, hipStream_t st);
+// most rows of one apply band: the segmented kernel keeps p and the row
+// sums of a band's rows in LDS (with FP64 partials and 8-chunk segments,
+// 2 * 8 * 3072 + 2 * 8 * 1024 bytes = 64 KiB)
+constexpr int32_t kMaxBandRows = 3072;
+// columns the whole-row kernel can hold (its LDS keeps p for all of them)
+constexpr int32_t kMaxWholeRowCols = 4096;
+// dynamic LDS of the segmented kernel: p and the sums of the segment's
+// columns and of the band's rows, in the accumulation type
+inline size_t apply_seg_lds_bytes(int prec, int segch, int32_t brmax)
+{
+    const size_t acc = prec == 0 ? 8 : 4;
+    const size_t segw = (size_t)segch * 64 * (16 / (prec == 0 ? 8 : (prec == 1 ? 4 : 2)));
+    return acc * (2 * segw + 2 * (size_t)brmax);
+}
 // q[g] = sum of z[zpos[k]] for k in [zptr[g], zptr[g+1]), in that order
 hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* zptr, const int64_t* zpos, const void* z,
                          double* q, hipStream_t st);

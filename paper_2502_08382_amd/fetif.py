@@ -46,7 +46,7 @@ class _Opt(ctypes.Structure):
                 ("trsm_chunk", ctypes.c_int32), ("apply_rows", ctypes.c_int32),
                 ("apply_nontemporal", ctypes.c_int32), ("apply_split", ctypes.c_int32),
                 ("trsm_panel", ctypes.c_int32), ("apply_seg", ctypes.c_int32),
-                ("assembly_groups", ctypes.c_int32)]
+                ("assembly_groups", ctypes.c_int32), ("schur_order", ctypes.c_int32)]
 
 
 class _PcpgOpt(ctypes.Structure):
@@ -67,7 +67,7 @@ class _Info(ctypes.Structure):
                 ("trsm_flops", ctypes.c_double), ("syrk_flops", ctypes.c_double),
                 ("factor_flops", ctypes.c_double), ("trsm_levels", ctypes.c_int32),
                 ("apply_groups", ctypes.c_int32), ("apply_elements", ctypes.c_int64),
-                ("assembly_groups", ctypes.c_int32)]
+                ("assembly_groups", ctypes.c_int32), ("trsm_bwd_flops", ctypes.c_double)]
 
 
 EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply",
@@ -76,9 +76,9 @@ EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply
            "fetiF_hfactor_supernodes", "fetiF_hfactor_free", "fetiF_profile_enable",
            "fetiF_profile_read", "fetiF_set_apply", "fetiF_apply_implicit", "fetiF_dual_rhs",
            "fetiF_coarse_rhs", "fetiF_pcpg", "fetiF_primal", "fetiF_set_assembly", "fetiF_factor_assemble",
-           "fetiF_apply_static"]
+           "fetiF_apply_static", "fetiF_set_assembly_path", "fetiF_apply_host"]
 
-PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "solves"]
+PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "solves", "trsm_bwd", "spmm"]
 
 _lib = None
 
@@ -100,6 +100,7 @@ def load_library(path=None):
     L.fetiF_factor_assemble.argtypes = [vp, ctypes.POINTER(vp), vp]
     L.fetiF_apply.argtypes = [vp, vp, vp, vp]
     L.fetiF_apply_static.argtypes = [vp, vp, vp, vp]
+    L.fetiF_apply_host.argtypes = [vp, vp, vp, i32, vp]
     L.fetiF_apply_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fetiF_download_F.argtypes = [vp, i32, vp]
     L.fetiF_query.argtypes = [vp, ctypes.POINTER(_Info)]
@@ -115,6 +116,7 @@ def load_library(path=None):
     L.fetiF_profile_read.argtypes = [vp, ctypes.c_int, vp, vp, i32]
     L.fetiF_set_apply.argtypes = [vp, i32, i32, i32, i32, i32]
     L.fetiF_set_assembly.argtypes = [vp, i32, i32]
+    L.fetiF_set_assembly_path.argtypes = [vp, i32]
     L.fetiF_apply_implicit.argtypes = [vp, vp, vp, vp]
     L.fetiF_dual_rhs.argtypes = [vp, vp, vp, vp, vp]
     L.fetiF_coarse_rhs.argtypes = [vp, vp, vp, vp]
@@ -209,10 +211,10 @@ class _SubArrays:
 
 
 def _options(f_storage="f64", leaf_nodes=0, nthreads=0, apply_band=0, trsm_chunk=0, apply_rows=0,
-             apply_nontemporal=-1, apply_split=-1, trsm_panel=0, apply_seg=-1, assembly_groups=0):
+             apply_nontemporal=-1, apply_split=-1, trsm_panel=0, apply_seg=-1, assembly_groups=0, schur_order=0):
     prec = _PREC[f_storage] if isinstance(f_storage, str) else int(f_storage)
     return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk, apply_rows, apply_nontemporal, apply_split,
-                trsm_panel, apply_seg, assembly_groups)
+                trsm_panel, apply_seg, assembly_groups, int(schur_order))
 
 
 class FetiContext:
@@ -274,6 +276,19 @@ class FetiContext:
         self._vecs(lam=(lam, self.n_lambda), q=(q, self.n_lambda))
         self._check(self.L.fetiF_apply_static(self.h, _dptr(lam), _dptr(q), _stream(stream)))
 
+    def apply_host(self, lam, q=None, cpu_scatter_gather=0, stream=None):
+        """q = F lam with host (numpy) vectors; scatter/gather on the GPU (0)
+        or on host threads (1).  Returns q."""
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        if lam.shape != (self.n_lambda,):
+            raise ValueError(f"lam: expected {self.n_lambda} values, got shape {lam.shape}")
+        if q is None:
+            q = np.empty(self.n_lambda)
+        if q.dtype != np.float64 or q.shape != (self.n_lambda,) or not q.flags.c_contiguous:
+            raise ValueError("q: a contiguous float64 array of n_lambda values")
+        self._check(self.L.fetiF_apply_host(self.h, _ptr(lam), _ptr(q), int(cpu_scatter_gather), _stream(stream)))
+        return q
+
     def apply_backward(self, g, lam, dlam, dtheta=None, stream=None):
         self._vecs(g=(g, self.n_lambda), lam=(lam, self.n_lambda), dlam=(dlam, self.n_lambda),
                    dtheta=(dtheta, self.n_elems))
@@ -326,6 +341,10 @@ class FetiContext:
         kernel: 0 whole rows, 4/8 column segments of that many chunks)."""
         self._check(self.L.fetiF_set_apply(self.h, int(band_elems), int(rows), int(nontemporal), int(split),
                                            int(seg)))
+
+    def set_assembly_path(self, path):
+        """0: SYRK path (default); 1: TRSM path (backward solve + SpMM)."""
+        self._check(self.L.fetiF_set_assembly_path(self.h, int(path)))
 
     def set_assembly(self, trsm_panel=0, trsm_chunk=0):
         """Re-plan the assembly TRSM (supernode columns per panel, RHS columns per work-group)."""

@@ -44,5 +44,6 @@ hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t);
 hipError_t hipGraphExecDestroy(hipGraphExec_t);
 hipError_t hipGraphDestroy(hipGraph_t);
 const char* hipGetErrorString(hipError_t);
+hipError_t hipGetLastError();
 // test double only: aborts when a stream handle differs from $HOSTSIM_STREAM
 void hostsim_check_stream(hipStream_t);

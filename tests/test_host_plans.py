@@ -118,10 +118,19 @@ def flow(prob, with_elements=False, **opts):
         ctx.set_assembly(panel, chunk)
         ctx.assemble(stream=ST)
         ctx.factor_assemble(kv, stream=ST)
+    # the TRSM path (backward solve + SpMM), re-planned with the panel width
+    ctx.set_assembly_path(1)
+    ctx.assemble(stream=ST)
+    expect(6, lambda: ctx.factor_assemble(kv, stream=ST))
+    ctx.set_assembly(32, 0)
+    ctx.assemble(stream=ST)
+    ctx.set_assembly_path(0)
+    ctx.set_assembly(96, 32)
+    ctx.assemble(stream=ST)
     n = prob.n_lambda
     lam = np.zeros(n)
     q = np.zeros(n)
-    for seg in (0, 4, 8):
+    for seg in ((0, 4, 8) if max(s.m for s in prob.subs) <= 4096 else (4, 8)):
         for split in (0, 1):
             for band in (1, 3000, 0):
                 ctx.set_apply(band, 2, 1, split, seg)
@@ -131,6 +140,8 @@ def flow(prob, with_elements=False, **opts):
                 except FetiError as e:   # partials beyond the static scratch
                     assert e.status == 6 and "static scratch" in str(e), str(e)
     ctx.apply_implicit(lam.ctypes.data, q.ctypes.data, stream=ST)
+    for sg in (0, 1, 0):
+        ctx.apply_host(lam, q, cpu_scatter_gather=sg, stream=ST)
     f = np.zeros(sum(s.n for s in prob.subs))
     e = np.zeros(sum(s.R.shape[1] for s in prob.subs))
     d = np.zeros(n)
@@ -165,9 +176,19 @@ flow(config_problem(2, scale=(3, 6), elem="simplex"), assembly_groups=8, nthread
 flow(make_problem(3, "elasticity", [[3, 4, 2], [3, 2], [2, 3]], 0.3, dirichlet_axis=2, seed=3),
      assembly_groups=5, nthreads=2, f_storage="bf16")
 flow(make_problem(2, "heat", [[7, 13, 5], [9, 11]], 0.5, dirichlet_axis=0, seed=9), assembly_groups=100)
-# more than 4096 multipliers in a subdomain: refused at create
-big = make_problem(3, "elasticity", [[20, 20], [20, 20], [20, 20]], 0.0, dirichlet_axis=2, seed=1)
-expect(6, lambda: FetiContext([subdomain_dict(s) for s in big.subs], big.n_lambda, device=0))
+# the Schur-complement order (multiplier nodes last)
+flow(config_problem(2, scale=(2, 6)), schur_order=1, assembly_groups=2)
+flow(make_problem(3, "elasticity", [[3, 4], [3, 2], [2, 3]], 0.3, dirichlet_axis=2, seed=3), schur_order=1,
+     f_storage="bf16")
+# more than 4096 multipliers in a subdomain (flat slabs, m = 8450 and 4225):
+# the segmented apply serves it, the whole-row kernel is refused
+wide = make_problem(3, "heat", [[64], [64], [2, 2]], 0.0, dirichlet_axis=2, seed=1)
+assert max(s.m for s in wide.subs) > 8192
+flow(wide)
+wctx = FetiContext([subdomain_dict(s) for s in wide.subs], wide.n_lambda, device=0)
+expect(6, lambda: wctx.set_apply(0, 2, 1, 0, 0))
+wctx.set_apply(3000, 2, 1, 1, 8)
+wctx.close()
 print("hostsim flows done")
 '''
 
