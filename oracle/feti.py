@@ -123,6 +123,40 @@ def lumped_preconditioner(prob):
     return apply
 
 
+def scaled_jump_operator(prob, scaling="stiffness", K="K"):
+    """The scaled jump operator B_D = (B W B^T)^{-1} B W (dense, n_lambda x
+    sum n_i, subdomain blocks side by side) with W diagonal per subdomain
+    DOF: 1 / K_i[d, d] (stiffness scaling) or 1 (multiplicity scaling).
+    Alg. 1 leaves M open; with the non-redundant chain gluing a node shared
+    by k subdomains carries k - 1 multipliers, so weights applied row by row
+    cannot satisfy B_D B^T = I there, while this B_D does for any diagonal
+    W > 0 (B has full row rank).  Also returns B."""
+    nn = [s.n for s in prob.subs]
+    off = np.concatenate([[0], np.cumsum(nn)])
+    B = np.zeros((prob.n_lambda, off[-1]))
+    wv = np.zeros(off[-1])
+    for i, sub in enumerate(prob.subs):
+        B[sub.dual_map, off[i] + sub.b_dof] = sub.b_sign
+        Ki = sub.K if K == "K" else sub.Kreg
+        wv[off[i]:off[i + 1]] = 1.0 / Ki.diagonal() if scaling == "stiffness" else 1.0
+    A = (B * wv[None, :]) @ B.T
+    return np.linalg.solve(A, B * wv[None, :]), B
+
+
+def scaled_lumped_preconditioner(prob, scaling="stiffness", K="K"):
+    """The lumped preconditioner with the scaled jump operator,
+    M = B_D blockdiag(K_i) B_D^T (B_D from scaled_jump_operator; K_i the
+    unregularised stiffness, or K_reg,i).  Returns a function w -> M w."""
+    BD, _ = scaled_jump_operator(prob, scaling, K)
+    Kb = sp.block_diag([(sub.K if K == "K" else sub.Kreg) for sub in prob.subs], format="csr")
+    M = BD @ (Kb @ BD.T)
+
+    def apply(w):
+        return M @ w
+
+    return apply
+
+
 def e_vector(prob):
     """e = R^T f."""
     return np.concatenate([s.R.T @ s.f for s in prob.subs])
