@@ -223,8 +223,9 @@ def main():
                     help="solver iterations per step (FP64); 0: run to --tol")
     ap.add_argument("--tol", type=float, default=1e-9, help="solver tolerance with --prec f32/bf16")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
-    ap.add_argument("--precond", default="none", choices=["none", "lumped"],
-                    help="M of the PCPG (Alg. 1): identity or the lumped preconditioner")
+    ap.add_argument("--precond", default="none", choices=["none", "lumped", "scaled"],
+                    help="M of the PCPG (Alg. 1): identity, the lumped preconditioner, or the lumped one on the "
+                         "scaled jump operator (stiffness scaling, unregularised K)")
     ap.add_argument("--cpu-sample", type=int, default=128,
                     help="subdomains (evenly spaced) of the CPU oracle's implicit apply on all host threads")
     ap.add_argument("--no-cpu", action="store_true")
@@ -286,7 +287,10 @@ def main():
     sol = torch.empty_like(lam)
     stream = torch.cuda.Stream()
     refine = args.prec != "f64"
-    pc = 1 if args.precond == "lumped" else 0
+    pc = {"none": 0, "lumped": 1, "scaled": 2}[args.precond]
+    if pc:
+        from paper_2502_08382_amd import values_in_pattern
+        ctx.precond_values([values_in_pattern(s.K, s.Kreg) for s in prob.subs])
     tune_cache = os.path.join(ROOT, "paper_2502_08382_amd", "tuned_apply.json")
 
     def shape_key(t):
@@ -480,7 +484,8 @@ def main():
                               "syrk": round(ms["syrk"] / K, 4)},
         "assembly_tflops": round(asm_flops / (t_asm * 1e-3) / 1e12, 3),
         "assembly_mfma_frac": round(asm_flops / (t_asm * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
-        "solver": {"kind": "PCPG (Alg. 1), M = " + ("lumped" if pc else "I") + (", FP64 refinement" if refine else ""),
+        "solver": {"kind": "PCPG (Alg. 1), M = " + ("I", "lumped", "lumped on the scaled jump operator")[pc] +
+                           (", FP64 refinement" if refine else ""),
                    "iters": solver[-1]["iters"], "outer": solver[-1]["outer"],
                    "rel_residual": solver[-1]["rel_residual"],
                    "ms_per_iter": None},

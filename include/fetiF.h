@@ -303,8 +303,15 @@ typedef struct {
     double inner_tol;    /* relative tolerance of each inner solve (default 1e-4) */
     int32_t use_graph;   /* 1: replay captured iterations (needs a non-NULL stream) */
     int32_t precond;     /* M of Alg. 1: 0 identity; 1 lumped,
-                            M = sum_i D_i^T B~_i K_reg,i B~_i^T D_i with the
-                            values of the last fetiF_factor_upload */
+                            M = sum_i D_i^T B~_i K_i B~_i^T D_i; 2 lumped with the
+                            scaled jump operator, M = B_D K B_D^T with
+                            B_D = (B W B^T)^{-1} B W and W_i = diag(K_i)^{-1} on
+                            the multiplier DOFs (stiffness scaling; B W B^T is
+                            block diagonal over the multipliers that share a
+                            DOF of some subdomain, inverted on the host when
+                            the values change).  K_i: the values given by
+                            fetiF_precond_values, else the K_reg,i values of
+                            the last fetiF_factor_upload */
 } fetiF_pcpg_options;
 
 typedef struct {
@@ -315,8 +322,17 @@ typedef struct {
     double w0;            /* ||w_0|| */
 } fetiF_pcpg_result;
 
+/* Stiffness values for the lumped preconditioners (fetiF_pcpg_options
+ * precond 1 and 2) of subdomains [first, first+count): k_vals[k] holds the
+ * values of K_i (normally the unregularised stiffness; the rows and columns
+ * that carry multipliers are used) in the CSR pattern of K_reg,i given at
+ * create (zero where K_i has no entry).  They are used instead of the K_reg
+ * values of later factor uploads until given again.  Synchronises the
+ * device.  FETIF_ESTATE without kernel bases (no solver). */
+fetiF_status fetiF_precond_values(fetiF_ctx ctx, int32_t first, int32_t count, const double* const* k_vals);
+
 /* Solve the dual problem (eq. tfetidualproblem) for lambda by PCPG with
- * M = I or the lumped preconditioner (options.precond) and
+ * M = I or a lumped preconditioner (options.precond) and
  * lambda_0 = G (G^T G)^{-1} e (Alg. 1).  d_d (n_lambda) from
  * fetiF_dual_rhs, e_d from fetiF_coarse_rhs; lambda_d receives the result.
  * Enqueued on `stream`; the call waits for the stream to report the

@@ -6,4 +6,4 @@ host analysis + HIP kernels for gfx950) behind the C-ABI of
 """
 from .fetif import (FetiContext, FetiError, HostFactor, load_library, LIB_PATH,  # noqa: F401
                     F64, F32, BF16)
-from .problem import subdomain_dict  # noqa: F401
+from .problem import subdomain_dict, values_in_pattern  # noqa: F401

@@ -107,14 +107,17 @@ bool plan_subdomain(const fetiF_subdomain& in, const fetiF_options& opt, int64_t
         for (int32_t k = 0; k < in.m; ++k) P.lb_uk[fill[P.lb_mb[k]]++] = k;
     }
     P.lb_kptr.assign(nb + 1, 0);
+    P.lb_kdiag.assign(nb, -1);
     for (int32_t u = 0; u < nb; ++u) {
         const int32_t row = P.lb_dofs[u];
         for (int64_t e = A.ptr[row]; e < A.ptr[row + 1]; ++e)
             if (bpos[A.idx[e]] >= 0) {
+                if (A.idx[e] == row) P.lb_kdiag[u] = (int32_t)P.lb_kcol.size();
                 P.lb_kcol.push_back(bpos[A.idx[e]]);
                 P.lb_ksrc.push_back(e);
             }
         P.lb_kptr[u + 1] = (int32_t)P.lb_kcol.size();
+        if (P.lb_kdiag[u] < 0) { P.err = "pattern lacks the diagonal of a boundary DOF"; return false; }
     }
     return true;
 }
@@ -1158,12 +1161,12 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
         CK(upload(c->dR, Rcat));
         CK(dalloc(c, &c->dAinv, (size_t)(nc * nc)));
         CK(upload(c->dAinv, GtG));
-        CK(dalloc(c, &c->dVec, (size_t)(8 * n_lambda)));
+        CK(dalloc(c, &c->dVec, (size_t)(9 * n_lambda)));
         // lumped preconditioner tables (global slots; see LumpSub)
         {
             std::vector<LumpSub> ls(nsub);
             std::vector<int32_t> uptr{0}, uk, kptr{0}, kcol, mb(c->sum_m), gptr(n_lambda + 1, 0), gpos(c->sum_m);
-            std::vector<int8_t> sg(c->sum_m);
+            std::vector<double> sg(c->sum_m);
             int32_t bb = 0;
             int64_t kb = 0;
             for (int32_t i = 0; i < nsub; ++i) {
@@ -1219,6 +1222,64 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
             CK(upload(c->dLbGpos, gpos));
             CK(dalloc(c, &c->dLbKval, (size_t)std::max<int64_t>(1, kb)));
             CK(dalloc(c, &c->dLbY, (size_t)c->sum_m));
+            // groups of multipliers coupled through a shared (subdomain, DOF):
+            // the diagonal blocks of A = B W B^T (union-find over multipliers)
+            {
+                std::vector<int32_t> uf((size_t)n_lambda);
+                for (int64_t g = 0; g < n_lambda; ++g) uf[(size_t)g] = (int32_t)g;
+                auto root = [&](int32_t x) {
+                    while (uf[(size_t)x] != x) {
+                        uf[(size_t)x] = uf[(size_t)uf[(size_t)x]];
+                        x = uf[(size_t)x];
+                    }
+                    return x;
+                };
+                for (int32_t i = 0; i < nsub; ++i) {
+                    const SubPlan& P = c->subs[i];
+                    for (size_t u = 0; u + 1 < P.lb_uptr.size(); ++u)
+                        for (int32_t e = P.lb_uptr[u] + 1; e < P.lb_uptr[u + 1]; ++e) {
+                            const int32_t a = root(P.dual_map[P.sigma[P.lb_uk[P.lb_uptr[u]]]]);
+                            const int32_t b = root(P.dual_map[P.sigma[P.lb_uk[e]]]);
+                            if (a != b) uf[(size_t)std::max(a, b)] = std::min(a, b);
+                        }
+                }
+                std::vector<int32_t> bid((size_t)n_lambda, -1);
+                c->hSbOf.assign((size_t)n_lambda, 0);
+                c->hSbPos.assign((size_t)n_lambda, 0);
+                std::vector<int32_t> cnt;
+                for (int64_t g = 0; g < n_lambda; ++g) {   // blocks numbered by their smallest member
+                    const int32_t r = root((int32_t)g);
+                    if (bid[(size_t)r] < 0) {
+                        bid[(size_t)r] = (int32_t)cnt.size();
+                        cnt.push_back(0);
+                    }
+                    c->hSbOf[(size_t)g] = bid[(size_t)r];
+                    c->hSbPos[(size_t)g] = cnt[(size_t)bid[(size_t)r]]++;
+                }
+                const size_t nbk = cnt.size();
+                c->hSbPtr.assign(nbk + 1, 0);
+                c->hSbOff.assign(nbk + 1, 0);
+                for (size_t b = 0; b < nbk; ++b) {
+                    c->hSbPtr[b + 1] = c->hSbPtr[b] + cnt[b];
+                    c->hSbOff[b + 1] = c->hSbOff[b] + (int64_t)cnt[b] * cnt[b];
+                }
+                c->hSbMem.assign((size_t)n_lambda, 0);
+                for (int64_t g = 0; g < n_lambda; ++g)
+                    c->hSbMem[(size_t)(c->hSbPtr[(size_t)c->hSbOf[(size_t)g]] + c->hSbPos[(size_t)g])] = (int32_t)g;
+                CK(dalloc(c, &c->dSbOf, c->hSbOf.size()));
+                CK(upload(c->dSbOf, c->hSbOf));
+                CK(dalloc(c, &c->dSbPos, c->hSbPos.size()));
+                CK(upload(c->dSbPos, c->hSbPos));
+                CK(dalloc(c, &c->dSbPtr, c->hSbPtr.size()));
+                CK(upload(c->dSbPtr, c->hSbPtr));
+                CK(dalloc(c, &c->dSbMem, c->hSbMem.size()));
+                CK(upload(c->dSbMem, c->hSbMem));
+                CK(dalloc(c, &c->dSbOff, c->hSbOff.size()));
+                CK(upload(c->dSbOff, c->hSbOff));
+                CK(dalloc(c, &c->dSbInv, (size_t)std::max<int64_t>(1, c->hSbOff.back())));
+                CK(dalloc(c, &c->dLbCoef, (size_t)c->sum_m));
+                c->lb_given.assign((size_t)nsub, 0);
+            }
             CK(hipHostMalloc((void**)&c->hLbKval, sizeof(double) * (size_t)std::max<int64_t>(1, kb),
                              hipHostMallocDefault));
         }
@@ -1283,7 +1344,9 @@ fetiF_status upload_range(fetiF_ctx c, int32_t first, int32_t count, const doubl
         parallel_for(k1 - k0, c->nthreads, [&](int32_t k) {
             const SubPlan& P = c->subs[first + k0 + k];
             bad[k] = numeric_cholesky(P.sym, k_vals[k0 + k], c->hStage + P.lbase);
-            if (c->hLbKval)   // the K_reg entries among boundary DOFs, for the lumped preconditioner
+            // the K_reg entries among boundary DOFs, for the lumped
+            // preconditioners (unless fetiF_precond_values gave other values)
+            if (c->hLbKval && !c->lb_given[(size_t)(first + k0 + k)])
                 for (size_t e = 0; e < P.lb_ksrc.size(); ++e) c->hLbKval[P.lb_kbase + e] = k_vals[k0 + k][P.lb_ksrc[e]];
         });
         for (int32_t k = 0; k < k1 - k0; ++k)
@@ -1308,6 +1371,7 @@ fetiF_status upload_range(fetiF_ctx c, int32_t first, int32_t count, const doubl
         HIPCHK(c, hipMemcpyAsync(c->dL + P0.lbase, c->hStage + P0.lbase, sizeof(double) * (size_t)n,
                                  hipMemcpyHostToDevice, st));
         if (c->hLbKval) {
+            c->sb_dirty = true;
             const int64_t kb0 = P0.lb_kbase, kb1 = P1.lb_kbase + (int64_t)P1.lb_ksrc.size();
             if (kb1 > kb0)
                 HIPCHK(c, hipMemcpyAsync(c->dLbKval + kb0, c->hLbKval + kb0, sizeof(double) * (size_t)(kb1 - kb0),

@@ -74,6 +74,7 @@ struct SubPlan {
     // each boundary DOF, the K_reg entries among boundary DOFs (CSR over
     // boundary indices; lb_ksrc = position in the caller's value array)
     std::vector<int32_t> lb_dofs, lb_mb, lb_uptr, lb_uk, lb_kptr, lb_kcol;
+    std::vector<int32_t> lb_kdiag;   // per boundary DOF: position of its diagonal entry among the K_bb entries
     int64_t lb_kbase = 0;        // first K_bb entry of this subdomain (global)
     std::vector<int8_t> lb_ms;
     std::vector<int64_t> lb_ksrc;
@@ -209,7 +210,18 @@ struct fetiF_ctx_s {
     LumpSub* dLump = nullptr;
     int32_t *dLbUptr = nullptr, *dLbUk = nullptr, *dLbKptr = nullptr, *dLbKcol = nullptr, *dLbMb = nullptr;
     int32_t *dLbGptr = nullptr, *dLbGpos = nullptr;
-    int8_t* dLbSgn = nullptr;
+    double* dLbSgn = nullptr;      // sign of each sorted multiplier (the lumped M)
+    // scaled lumped preconditioner (precond 2): M = A^{-1} (sum_i D_i^T B~_i W_i K_bb,i W_i B~_i^T D_i) A^{-1},
+    // A = sum_i D_i^T B~_i W_i B~_i^T D_i, W_i = diag(K_bb,i)^{-1}; A is block diagonal over the
+    // groups of multipliers that share a (subdomain, DOF): dense inverses of those blocks
+    double* dLbCoef = nullptr;     // sign * weight of each sorted multiplier
+    int32_t *dSbOf = nullptr, *dSbPos = nullptr, *dSbPtr = nullptr, *dSbMem = nullptr;
+    int64_t* dSbOff = nullptr;
+    double* dSbInv = nullptr;
+    std::vector<int32_t> hSbOf, hSbPos, hSbPtr, hSbMem;
+    std::vector<int64_t> hSbOff;
+    std::vector<char> lb_given;    // per subdomain: K_bb values from fetiF_precond_values
+    bool sb_dirty = true;          // K_bb values changed since the weights and A^{-1} were formed
     double* dLbKval = nullptr;
     double* dLbY = nullptr;    // sum m_i partial results
     double* hLbKval = nullptr; // pinned staging of the K_bb values

@@ -8,7 +8,7 @@
 namespace {
 
 struct Work {
-    double *r, *w, *y, *p, *q, *rt, *dl, *mz;
+    double *r, *w, *y, *p, *q, *rt, *dl, *mz, *mz2;
     double *t, *s;
 };
 
@@ -24,6 +24,7 @@ Work work_of(fetiF_ctx c)
     W.rt = c->dVec + 5 * n;
     W.dl = c->dVec + 6 * n;
     W.mz = c->dVec + 7 * n;
+    W.mz2 = c->dVec + 8 * n;
     W.t = c->dCvec;
     W.s = c->dCvec + c->ncoarse;
     return W;
@@ -44,16 +45,106 @@ hipError_t project(fetiF_ctx c, const Work& W, const double* in, double* out, hi
     return launch_gs(c->n_lambda, 1.0, -1.0, c->dGptr2, c->dGent2, c->dGv, W.s, in, out, st);
 }
 
-// y = P M w with M = I (precond 0) or the lumped preconditioner (precond 1)
+// y = P M w with M = I (precond 0), the lumped preconditioner (precond 1)
+// or the lumped preconditioner with the scaled jump operator (precond 2:
+// M = B_D K B_D^T, B_D = A^{-1} B W, A = B W B^T block diagonal)
 hipError_t precondition(fetiF_ctx c, const Work& W, int precond, const double* w, double* y, hipStream_t st)
 {
     if (!precond) return project(c, W, w, y, st);
     hipError_t e;
-    if ((e = launch_lumped_local(c->nsub, c->lb_nbmax, c->dLump, c->dLbUptr, c->dLbUk, c->dLbSgn, c->dLbKptr,
-                                 c->dLbKcol, c->dLbKval, c->dLbMb, c->dDmap, w, c->dLbY, st)) != hipSuccess)
+    const int64_t n = c->n_lambda;
+    if (precond == 1) {
+        if ((e = launch_lumped_local(c->nsub, c->lb_nbmax, c->dLump, c->dLbUptr, c->dLbUk, c->dLbSgn, c->dLbKptr,
+                                     c->dLbKcol, c->dLbKval, c->dLbMb, c->dDmap, w, c->dLbY, st)) != hipSuccess)
+            return e;
+        if ((e = launch_lumped_gather(n, c->dLbGptr, c->dLbGpos, c->dLbY, W.mz, st)) != hipSuccess) return e;
+        return project(c, W, W.mz, y, st);
+    }
+    if ((e = launch_block_apply(n, c->dSbOf, c->dSbPos, c->dSbPtr, c->dSbMem, c->dSbOff, c->dSbInv, w, W.mz, st)) !=
+        hipSuccess)
         return e;
-    if ((e = launch_lumped_gather(c->n_lambda, c->dLbGptr, c->dLbGpos, c->dLbY, W.mz, st)) != hipSuccess) return e;
+    if ((e = launch_lumped_local(c->nsub, c->lb_nbmax, c->dLump, c->dLbUptr, c->dLbUk, c->dLbCoef, c->dLbKptr,
+                                 c->dLbKcol, c->dLbKval, c->dLbMb, c->dDmap, W.mz, c->dLbY, st)) != hipSuccess)
+        return e;
+    if ((e = launch_lumped_gather(n, c->dLbGptr, c->dLbGpos, c->dLbY, W.mz2, st)) != hipSuccess) return e;
+    if ((e = launch_block_apply(n, c->dSbOf, c->dSbPos, c->dSbPtr, c->dSbMem, c->dSbOff, c->dSbInv, W.mz2, W.mz,
+                                st)) != hipSuccess)
+        return e;
     return project(c, W, W.mz, y, st);
+}
+
+// Weights W = diag(K_bb)^{-1} of the scaled jump operator from the current
+// K_bb values (host copy), sign * weight per sorted multiplier, and the
+// dense inverses of the diagonal blocks of A = B W B^T (Cholesky of each
+// small SPD block, then its inverse), copied to the device.
+fetiF_status build_scaled_lumped(fetiF_ctx c)
+{
+    const int32_t nb = (int32_t)c->hSbPtr.size() - 1;
+    std::vector<double> coef((size_t)c->sum_m);
+    std::vector<double> A((size_t)c->hSbOff.back(), 0.0);
+    for (int32_t i = 0; i < c->nsub; ++i) {
+        const SubPlan& P = c->subs[i];
+        for (size_t u = 0; u + 1 < P.lb_uptr.size(); ++u) {
+            const double kd = c->hLbKval[P.lb_kbase + P.lb_kdiag[u]];
+            if (!(kd > 0.0))
+                return fail(c, FETIF_ENOTSPD, "subdomain " + std::to_string(i) +
+                                                  ": non-positive stiffness diagonal on a multiplier DOF");
+            const double wgt = 1.0 / kd;
+            for (int32_t e1 = P.lb_uptr[u]; e1 < P.lb_uptr[u + 1]; ++e1) {
+                const int32_t k1 = P.lb_uk[e1];
+                const double s1 = P.lb_ms[k1];
+                coef[(size_t)(P.dbase + k1)] = s1 * wgt;
+                const int32_t g1 = P.dual_map[P.sigma[k1]];
+                const int32_t b = c->hSbOf[(size_t)g1], sz = c->hSbPtr[(size_t)b + 1] - c->hSbPtr[(size_t)b];
+                for (int32_t e2 = P.lb_uptr[u]; e2 < P.lb_uptr[u + 1]; ++e2) {
+                    const int32_t k2 = P.lb_uk[e2];
+                    const int32_t g2 = P.dual_map[P.sigma[k2]];
+                    A[(size_t)(c->hSbOff[(size_t)b] + (int64_t)c->hSbPos[(size_t)g1] * sz + c->hSbPos[(size_t)g2])] +=
+                        s1 * P.lb_ms[k2] * wgt;
+                }
+            }
+        }
+    }
+    // invert every block: Cholesky A = R^T R, then A^{-1} column by column
+    std::vector<double> inv(A.size());
+    std::vector<double> Rm, x;
+    for (int32_t b = 0; b < nb; ++b) {
+        const int32_t s = c->hSbPtr[(size_t)b + 1] - c->hSbPtr[(size_t)b];
+        const double* a = A.data() + c->hSbOff[(size_t)b];
+        Rm.assign((size_t)s * s, 0.0);
+        for (int32_t j = 0; j < s; ++j) {
+            double d = a[j * s + j];
+            for (int32_t k = 0; k < j; ++k) d -= Rm[(size_t)(k * s + j)] * Rm[(size_t)(k * s + j)];
+            if (!(d > 0.0)) return fail(c, FETIF_ENOTSPD, "a block of B W B^T is not positive definite");
+            const double r = std::sqrt(d);
+            Rm[(size_t)(j * s + j)] = r;
+            for (int32_t t = j + 1; t < s; ++t) {
+                double v = a[j * s + t];
+                for (int32_t k = 0; k < j; ++k) v -= Rm[(size_t)(k * s + j)] * Rm[(size_t)(k * s + t)];
+                Rm[(size_t)(j * s + t)] = v / r;
+            }
+        }
+        double* out = inv.data() + c->hSbOff[(size_t)b];
+        x.assign((size_t)s, 0.0);
+        for (int32_t col = 0; col < s; ++col) {
+            // R^T y = e_col, then R x = y
+            for (int32_t t = 0; t < s; ++t) {
+                double v = t == col ? 1.0 : 0.0;
+                for (int32_t k = 0; k < t; ++k) v -= Rm[(size_t)(k * s + t)] * x[(size_t)k];
+                x[(size_t)t] = v / Rm[(size_t)(t * s + t)];
+            }
+            for (int32_t t = s - 1; t >= 0; --t) {
+                double v = x[(size_t)t];
+                for (int32_t k = t + 1; k < s; ++k) v -= Rm[(size_t)(t * s + k)] * x[(size_t)k];
+                x[(size_t)t] = v / Rm[(size_t)(t * s + t)];
+            }
+            for (int32_t t = 0; t < s; ++t) out[t * s + col] = x[(size_t)t];
+        }
+    }
+    HIPCHK(c, hipMemcpy(c->dLbCoef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->dSbInv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice));
+    c->sb_dirty = false;
+    return FETIF_OK;
 }
 
 // one iteration of Alg. 1 (the loop body), all scalars on the device
@@ -99,7 +190,7 @@ hipError_t run_iters(fetiF_ctx c, const Work& W, int implicit, int precond, doub
 {
     hipError_t e;
     if (graph && st != nullptr && count >= chunk) {
-        const int32_t key = (implicit ? 1 : 0) | (precond ? 2 : 0) | (chunk << 2);
+        const int32_t key = (implicit ? 1 : 0) | (precond << 1) | (chunk << 3);
         const bool reuse = c->pcpg_graph && c->pcpg_graph_key == key && c->pcpg_graph_stream == st &&
                            c->pcpg_lam == lam;
         if (!reuse) {
@@ -220,6 +311,38 @@ extern "C" fetiF_status fetiF_coarse_rhs(fetiF_ctx c, const double* f_d, double*
     return FETIF_OK;
 }
 
+extern "C" fetiF_status fetiF_precond_values(fetiF_ctx c, int32_t first, int32_t count, const double* const* k_vals)
+{
+    if (!c) return FETIF_EINVAL;
+    if (c->sticky) return FETIF_EDEVICE;
+    if (fetiF_status s0 = need_coarse(c)) return s0;
+    if (first < 0 || count <= 0 || first + count > c->nsub || !k_vals)
+        return fail(c, FETIF_EINVAL, "subdomain range out of bounds or k_vals NULL");
+    for (int32_t k = 0; k < count; ++k)
+        if (!k_vals[k]) return fail(c, FETIF_EINVAL, "k_vals entry is NULL");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
+    // a factor upload may still copy from the staging of these values
+    if (c->upload_pending) {
+        HIPCHK(c, hipEventSynchronize(c->upload_done));
+        c->upload_pending = false;
+    }
+    HIPCHK(c, hipDeviceSynchronize());   // the lumped preconditioners may be reading them
+    for (int32_t k = 0; k < count; ++k) {
+        const SubPlan& P = c->subs[first + k];
+        for (size_t e = 0; e < P.lb_ksrc.size(); ++e) c->hLbKval[P.lb_kbase + e] = k_vals[k][P.lb_ksrc[e]];
+        c->lb_given[(size_t)(first + k)] = 1;
+    }
+    const SubPlan& P0 = c->subs[first];
+    const SubPlan& P1 = c->subs[first + count - 1];
+    const int64_t kb0 = P0.lb_kbase, kb1 = P1.lb_kbase + (int64_t)P1.lb_ksrc.size();
+    if (kb1 > kb0)
+        HIPCHK(c, hipMemcpy(c->dLbKval + kb0, c->hLbKval + kb0, sizeof(double) * (size_t)(kb1 - kb0),
+                            hipMemcpyHostToDevice));
+    c->sb_dirty = true;
+    return FETIF_OK;
+}
+
 extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double* e_d, double* lambda_d,
                                    const fetiF_pcpg_options* opt_in, fetiF_pcpg_result* res, void* stream)
 {
@@ -235,7 +358,8 @@ extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double*
     if (o.check_every <= 0) o.check_every = 10;
     if (!(o.inner_tol > 0.0)) o.inner_tol = 1e-4;
     if (o.fixed_iters < 0) return fail(c, FETIF_EINVAL, "fixed_iters < 0");
-    if (o.precond != 0 && o.precond != 1) return fail(c, FETIF_EINVAL, "precond must be 0 (none) or 1 (lumped)");
+    if (o.precond < 0 || o.precond > 2)
+        return fail(c, FETIF_EINVAL, "precond must be 0 (none), 1 (lumped) or 2 (lumped, scaled jump operator)");
     if (o.implicit || o.refine || o.precond) {
         if (fetiF_status s1 = need_factors(c)) return s1;
     }
@@ -243,6 +367,11 @@ extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double*
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
+    if (o.precond == 2 && c->sb_dirty) {
+        // the device may still read the previous weights and inverses
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (fetiF_status s2 = build_scaled_lumped(c)) return s2;
+    }
     fetiF_pcpg_result R;
     std::memset(&R, 0, sizeof(R));
     const bool graph = o.use_graph != 0;

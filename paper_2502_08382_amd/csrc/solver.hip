@@ -177,14 +177,16 @@ __global__ __launch_bounds__(NT) void dot_kernel(int64_t n, const double* __rest
 }
 
 // Lumped preconditioner, local part: one work-group per subdomain.  x lives
-// on the subdomain's boundary DOFs (x_u = sum of sign_k w[D k] over the
+// on the subdomain's boundary DOFs (x_u = sum of coef_k w[D k] over the
 // multipliers k on DOF u, in a fixed order), t = K_bb x row by row, and
-// every multiplier k takes sign_k t[b_k].  uk and mb hold global sorted
-// multiplier positions / boundary slots; kcol global boundary slots.
+// every multiplier k takes coef_k t[b_k].  coef is the sign of B~ (lumped
+// M) or the sign times the weight of the scaled jump operator.  uk and mb
+// hold global sorted multiplier positions / boundary slots; kcol global
+// boundary slots.
 __global__ __launch_bounds__(NT) void lumped_local_kernel(const LumpSub* __restrict__ ls,
                                                           const int32_t* __restrict__ uptr,
                                                           const int32_t* __restrict__ uk,
-                                                          const int8_t* __restrict__ sgn,
+                                                          const double* __restrict__ sgn,
                                                           const int32_t* __restrict__ kptr,
                                                           const int32_t* __restrict__ kcol,
                                                           const double* __restrict__ kval,
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(NT) void lumped_local_kernel(const LumpSub* __restr
     for (int u = threadIdx.x; u < S.nb; u += NT) {
         const int32_t g = S.bbase + u;
         double a = 0.0;
-        for (int32_t e = uptr[g]; e < uptr[g + 1]; ++e) a += (double)sgn[uk[e]] * w[dmap[uk[e]]];
+        for (int32_t e = uptr[g]; e < uptr[g + 1]; ++e) a += sgn[uk[e]] * w[dmap[uk[e]]];
         x[u] = a;
     }
     __syncthreads();
@@ -213,8 +215,30 @@ __global__ __launch_bounds__(NT) void lumped_local_kernel(const LumpSub* __restr
     __syncthreads();
     for (int k = threadIdx.x; k < S.m; k += NT) {
         const int32_t p = S.dbase + k;
-        ylocal[p] = (double)sgn[p] * t[mb[p] - S.bbase];
+        ylocal[p] = sgn[p] * t[mb[p] - S.bbase];
     }
+}
+
+// y = A^{-1} x for the block-diagonal A of the scaled jump operator: every
+// multiplier g takes the row of its block's dense inverse times the block's
+// entries of x (one thread per multiplier; blocks hold a handful of
+// multipliers: those sharing a DOF of some subdomain).
+__global__ __launch_bounds__(NT) void block_apply_kernel(int64_t n, const int32_t* __restrict__ sb_of,
+                                                         const int32_t* __restrict__ sb_pos,
+                                                         const int32_t* __restrict__ sb_ptr,
+                                                         const int32_t* __restrict__ sb_mem,
+                                                         const int64_t* __restrict__ sb_off,
+                                                         const double* __restrict__ inv,
+                                                         const double* __restrict__ x, double* __restrict__ y)
+{
+    const int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (g >= n) return;
+    const int32_t b = sb_of[g];
+    const int32_t p0 = sb_ptr[b], s = sb_ptr[b + 1] - p0;
+    const double* __restrict__ row = inv + sb_off[b] + (int64_t)sb_pos[g] * s;
+    double a = 0.0;
+    for (int32_t j = 0; j < s; ++j) a += row[j] * x[sb_mem[p0 + j]];
+    y[g] = a;
 }
 
 __global__ __launch_bounds__(NT) void lumped_gather_kernel(int64_t n, const int32_t* __restrict__ gptr,
@@ -397,7 +421,7 @@ hipError_t launch_dot(int64_t n, const double* x, const double* y, const double*
 }
 
 hipError_t launch_lumped_local(int32_t nsub, int32_t nbmax, const LumpSub* ls, const int32_t* uptr,
-                               const int32_t* uk, const int8_t* sgn, const int32_t* kptr, const int32_t* kcol,
+                               const int32_t* uk, const double* sgn, const int32_t* kptr, const int32_t* kcol,
                                const double* kval, const int32_t* mb, const int32_t* dmap, const double* w,
                                double* ylocal, hipStream_t st)
 {
@@ -410,6 +434,16 @@ hipError_t launch_lumped_local(int32_t nsub, int32_t nbmax, const LumpSub* ls, c
     }
     hipLaunchKernelGGL(lumped_local_kernel, dim3(nsub), dim3(NT), lds, st, ls, uptr, uk, sgn, kptr, kcol, kval, mb,
                        dmap, w, ylocal, nbmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_apply(int64_t n, const int32_t* sb_of, const int32_t* sb_pos, const int32_t* sb_ptr,
+                              const int32_t* sb_mem, const int64_t* sb_off, const double* inv, const double* x,
+                              double* y, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(block_apply_kernel, dim3(blocks(n)), dim3(NT), 0, st, n, sb_of, sb_pos, sb_ptr, sb_mem, sb_off,
+                       inv, x, y);
     return hipGetLastError();
 }
 

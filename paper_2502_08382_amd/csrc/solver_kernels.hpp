@@ -66,9 +66,15 @@ struct LumpSub {
 // ylocal[dbase + k] = sign_k (K_bb x)[b_k] with x = B~^T D w on the boundary
 // DOFs; one work-group per subdomain, 2 * nbmax doubles of LDS
 hipError_t launch_lumped_local(int32_t nsub, int32_t nbmax, const LumpSub* ls, const int32_t* uptr,
-                               const int32_t* uk, const int8_t* sgn, const int32_t* kptr, const int32_t* kcol,
+                               const int32_t* uk, const double* sgn, const int32_t* kptr, const int32_t* kcol,
                                const double* kval, const int32_t* mb, const int32_t* dmap, const double* w,
                                double* ylocal, hipStream_t st);
+// y = A^{-1} x with the dense inverses of the diagonal blocks of A (the
+// scaled jump operator's B W B^T): block sb_of[g], members sb_mem[sb_ptr[b] ..
+// sb_ptr[b+1]), inverse (row-major) at sb_off[b]
+hipError_t launch_block_apply(int64_t n, const int32_t* sb_of, const int32_t* sb_pos, const int32_t* sb_ptr,
+                              const int32_t* sb_mem, const int64_t* sb_off, const double* inv, const double* x,
+                              double* y, hipStream_t st);
 // y[g] = sum of ylocal over the sorted positions of multiplier g (fixed order)
 hipError_t launch_lumped_gather(int64_t n, const int32_t* gptr, const int32_t* gpos, const double* ylocal,
                                 double* y, hipStream_t st);

@@ -76,7 +76,7 @@ EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply
            "fetiF_hfactor_supernodes", "fetiF_hfactor_free", "fetiF_profile_enable",
            "fetiF_profile_read", "fetiF_set_apply", "fetiF_apply_implicit", "fetiF_dual_rhs",
            "fetiF_coarse_rhs", "fetiF_pcpg", "fetiF_primal", "fetiF_set_assembly", "fetiF_factor_assemble",
-           "fetiF_apply_static", "fetiF_set_assembly_path", "fetiF_apply_host"]
+           "fetiF_apply_static", "fetiF_set_assembly_path", "fetiF_apply_host", "fetiF_precond_values"]
 
 PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "solves", "trsm_bwd", "spmm"]
 
@@ -101,6 +101,7 @@ def load_library(path=None):
     L.fetiF_apply.argtypes = [vp, vp, vp, vp]
     L.fetiF_apply_static.argtypes = [vp, vp, vp, vp]
     L.fetiF_apply_host.argtypes = [vp, vp, vp, i32, vp]
+    L.fetiF_precond_values.argtypes = [vp, i32, i32, ctypes.POINTER(vp)]
     L.fetiF_apply_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fetiF_download_F.argtypes = [vp, i32, vp]
     L.fetiF_query.argtypes = [vp, ctypes.POINTER(_Info)]
@@ -257,6 +258,13 @@ class FetiContext:
     def assemble(self, stream=None):
         self._check(self.L.fetiF_assemble(self.h, _stream(stream)))
 
+    def precond_values(self, k_vals, first=0):
+        """Stiffness values (in each subdomain's K_reg pattern) for the lumped
+        preconditioners (the C call fetiF_precond_values)."""
+        arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in k_vals]
+        ptrs = (ctypes.c_void_p * len(arrs))(*[_ptr(a) for a in arrs])
+        self._check(self.L.fetiF_precond_values(self.h, int(first), len(arrs), ptrs))
+
     def factor_assemble(self, k_vals, stream=None):
         """Factorisation, copy and assembly of every subdomain, pipelined by
         the context's assembly groups (the C call fetiF_factor_assemble)."""
@@ -309,7 +317,8 @@ class FetiContext:
 
     def pcpg(self, d, e, lam, tol=1e-9, max_iters=1000, fixed_iters=0, implicit=False, check_every=10,
              refine=False, inner_tol=1e-4, use_graph=True, precond=0, stream=None):
-        """PCPG (Alg. 1) on the device (precond 0: M = I, 1: lumped);
+        """PCPG (Alg. 1) on the device (precond 0: M = I, 1: lumped, 2: lumped with the
+        scaled jump operator);
         returns dict(iters, outer, rel_residual, w0)."""
         self._vecs(d=(d, self.n_lambda), e=(e, self.n_coarse), lam=(lam, self.n_lambda))
         o = _PcpgOpt(tol, max_iters, fixed_iters, int(implicit), check_every, int(refine), inner_tol,

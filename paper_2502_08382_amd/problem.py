@@ -21,3 +21,12 @@ def subdomain_dict(sub, with_elements=False, with_kernel=True):
         d["elem_dofs"] = sub.elem_dofs()
         d["dK"] = sub.Ke_ref
     return d
+
+
+def values_in_pattern(K, pattern):
+    """The entries of the sparse matrix K at the positions of the CSR matrix
+    `pattern` (zero where K has none), in pattern's value order: the layout
+    fetiF_precond_values takes (K_i in the pattern of K_reg,i)."""
+    P = pattern.tocsr()
+    rows = np.repeat(np.arange(P.shape[0]), np.diff(P.indptr))
+    return np.asarray(K.tocsr()[rows, P.indices]).ravel().astype(np.float64)

@@ -86,7 +86,7 @@ import sys
 import numpy as np
 sys.path.insert(0, ROOT)
 from paper_2502_08382_amd.fetif import load_library, FetiContext, FetiError
-from paper_2502_08382_amd import subdomain_dict
+from paper_2502_08382_amd import subdomain_dict, values_in_pattern
 from synth import config_problem, make_problem
 load_library(LIB)
 ST = 0x7f0012345670           # any 64-bit stream handle: the test double ignores it
@@ -149,6 +149,9 @@ def flow(prob, with_elements=False, **opts):
     ctx.dual_rhs(f.ctypes.data, d.ctypes.data, stream=ST)
     ctx.pcpg(d.ctypes.data, e.ctypes.data, lam.ctypes.data, fixed_iters=3, use_graph=True, stream=ST)
     ctx.pcpg(d.ctypes.data, e.ctypes.data, lam.ctypes.data, fixed_iters=2, precond=1, stream=ST)
+    ctx.pcpg(d.ctypes.data, e.ctypes.data, lam.ctypes.data, fixed_iters=2, precond=2, use_graph=True, stream=ST)
+    ctx.precond_values([values_in_pattern(s.K, s.Kreg) for s in prob.subs[:2]], first=0)
+    ctx.pcpg(d.ctypes.data, e.ctypes.data, lam.ctypes.data, fixed_iters=2, precond=2, stream=ST)
     if with_elements:
         ne = sum(len(s.theta) for s in prob.subs)
         dth = np.zeros(ne)
@@ -226,9 +229,9 @@ print("not reached", flush=True)
 
 
 def test_stream_handle_cut_to_32_bits_is_caught(hostsim_lib):
-    """The failure behind an earlier crash of the pipelined benchmark leg: a
-    binding without declared argument types hands a 64-bit stream handle to
-    the library as a C int, and the runtime receives another value.  With
+    """A failure mode that would crash a GPU run: a binding without
+    declared argument types hands a 64-bit stream handle to the library as
+    a C int, and the runtime receives another value.  With
     the declared types the handle arrives whole; through an undeclared
     ctypes function the test double of the runtime sees the cut handle and
     aborts (on the GPU the runtime would dereference it)."""
