@@ -47,6 +47,18 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def calibration_copies(torch, dev):
+    """Three copies of a 1 GiB buffer: the reference the HBM byte counters
+    of a profiling run are scaled by."""
+    a = torch.empty(COPY_CAL_BYTES // 8, dtype=torch.float64, device=dev)
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("calibration copies done")
+
+
 def even_sample(nsub, k):
     """k subdomain indices spread evenly over 0..nsub-1."""
     k = max(1, min(int(k), nsub))
@@ -306,6 +318,7 @@ def main():
             torch.cuda.synchronize()
         log(f"{args.pmc_assemble} assemblies done; trsm flops {info['trsm_flops']:.6g}, "
             f"syrk flops {info['syrk_flops']:.6g}")
+        calibration_copies(torch, dev)
         ctx.close()
         return
 
@@ -319,13 +332,7 @@ def main():
                 ctx.apply(lam, q, stream=stream)
             torch.cuda.synchronize()
         log(f"{args.pmc_apply} applies done; key {shape_key(tune)}")
-        a = torch.empty(COPY_CAL_BYTES // 8, dtype=torch.float64, device=dev)
-        a.fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log("calibration copies done")
+        calibration_copies(torch, dev)
         ctx.close()
         return
 
@@ -437,8 +444,20 @@ def main():
     rsum = torch.empty((), dtype=torch.float64, device=dev)
     t_read = event_time(lambda: torch.sum(rbuf, dim=0, out=rsum), 20)
     read_gbs = nread * 8 / (t_read * 1e-3) / 1e9
-    del rbuf
     log(f"plain read of {nread * 8 / 1e9:.3f} GB (torch sum): {t_read * 1e3:.1f} us, {read_gbs:.0f} GB/s")
+    # the same bytes read by the library's streaming probe, each work-group
+    # one contiguous region (the access pattern of the apply's bands)
+    from paper_2502_08382_amd.fetif import read_probe
+    nprobe = nread - nread % 2
+    probe = {}
+    for region in (256 << 10, 1 << 20, 4 << 20):
+        pout = torch.empty(-(-nprobe * 8 // region), dtype=torch.float64, device=dev)
+        t_p = event_time(lambda: read_probe(rbuf[:nprobe], region, pout, stream=stream), 20)
+        probe[f"{region >> 10} KiB"] = round(nprobe * 8 / (t_p * 1e-3) / 1e9, 1)
+        del pout
+    probe_best = max(probe.values())
+    del rbuf
+    log(f"contiguous-region read probe (GB/s by region size): {probe}")
 
     K = args.steps
     ms = {p: v[0] for p, v in prof.items()}
@@ -506,6 +525,9 @@ def main():
         "plain_read_reference": {"kernel": "torch.sum over a resident buffer of the operator's bytes",
                                  "bytes": int(nread * 8), "us": round(t_read * 1e3, 1),
                                  "GB/s": round(read_gbs, 1), "band_kernel_vs_it": round(band_gbs / read_gbs, 4)},
+        "contiguous_read_probe": {"kernel": "fetiF_read_probe: each work-group streams one contiguous region of "
+                                            "the same bytes (16-byte non-temporal loads)",
+                                  "GB/s_by_region": probe, "band_kernel_vs_best": round(band_gbs / probe_best, 4)},
     }
 
     if tune is not None:

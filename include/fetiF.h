@@ -120,9 +120,9 @@ typedef struct {
     int32_t apply_split;  /* apply work split: 0 bands per triangle, largest first (default);
                              1 equal shares of all stored elements, one per work-group */
     int32_t trsm_panel;   /* most supernode columns per TRSM panel, a multiple of 16 up to 96 (default 48) */
-    int32_t apply_seg;    /* apply kernel: 0 whole rows per wavefront pair; 4 or 8 column segments
-                             of that many 1 KiB chunks (default 4; with 8 the rows per pass
-                             are 2 whatever apply_rows says) */
+    int32_t apply_seg;    /* apply kernel: 0 whole rows per wavefront pair (m <= 4096); 2, 3, 4
+                             or 8 column segments of that many 1 KiB chunks (default 4; with 8
+                             the rows per pass are 2 whatever apply_rows says) */
     int32_t assembly_groups; /* contiguous subdomain groups of about equal factor size, each
                                 with its own assembly schedule (default 1; fewer when a group
                                 would hold fewer subdomains than there are host threads):
@@ -235,8 +235,8 @@ fetiF_status fetiF_apply_host(fetiF_ctx ctx, const double* lambda_h, double* q_h
  * elements of F~ per work-group (the band/gather tables are rebuilt, which
  * synchronises the device), rows (2 or 4; 0 keeps) the rows per pass of a
  * wavefront pair, nontemporal (0/1; -1 keeps) the load policy for F~, split
- * (0/1; -1 keeps) the work split of fetiF_options.apply_split, seg (0, 4 or
- * 8; -1 keeps) the kernel of fetiF_options.apply_seg.  The result of
+ * (0/1; -1 keeps) the work split of fetiF_options.apply_split, seg (0, 2, 3,
+ * 4 or 8; -1 keeps) the kernel of fetiF_options.apply_seg.  The result of
  * fetiF_apply does not depend on these up to summation order.  A new band
  * size or split frees the previous apply tables: HIP graphs the caller
  * captured around fetiF_apply must be captured again (the library's own
@@ -387,6 +387,16 @@ fetiF_status fetiF_query(fetiF_ctx ctx, fetiF_info* info);
 #define FETIF_NPHASES 9
 fetiF_status fetiF_profile_enable(fetiF_ctx ctx, int on);
 fetiF_status fetiF_profile_read(fetiF_ctx ctx, int reset, double* ms, int64_t* counts, int32_t nphases);
+
+/* Measurement aid, no part of the method: a streaming read of buf_d (bytes,
+ * a multiple of 16) in which work-group g reads the contiguous region
+ * [g region_bytes, (g+1) region_bytes) with 16-byte non-temporal loads and
+ * writes the sum of its FP64 values to out_d[g] (ceil(bytes / region_bytes)
+ * entries, caller-owned).  It gives the read rate of the access pattern of
+ * the apply's bands (each work-group streams one contiguous stretch of a
+ * packed triangle).  region_bytes: a multiple of 16384.  Asynchronous on the
+ * current device; errors via fetiF_last_error(NULL). */
+fetiF_status fetiF_read_probe(const void* buf_d, int64_t bytes, int64_t region_bytes, double* out_d, void* stream);
 
 /* Release everything owned by the context (synchronises its device). */
 fetiF_status fetiF_destroy(fetiF_ctx ctx);

@@ -42,12 +42,12 @@ def group_candidates(ctx, per_cu=(2, 3, 4, 6, 8, 12)):
     return tuple(max(1, -(-total // (ncu * k))) for k in per_cu)
 
 
-def tune_apply(ctx, lam, q, bands=None, rows=(2, 4), nontemporal=(1,), splits=(0, 1), segs=(0, 4, 8), reps=20,
+def tune_apply(ctx, lam, q, bands=None, rows=(2, 4), nontemporal=(1,), splits=(0, 1), segs=(0, 2, 3, 4, 8), reps=20,
                stream=None, cache=None, verbose=False):
     """Try every (kernel, split, band, rows, nontemporal) shape; install and
     return the best.  bands: candidate elements per work-group (default:
-    group_candidates); segs: 0 the whole-row kernel, 4/8 the column-segmented
-    kernel with that many chunks per segment.
+    group_candidates); segs: 0 the whole-row kernel, 2/3/4/8 the
+    column-segmented kernel with that many chunks per segment.
 
     Returns dict(band=..., rows=..., nontemporal=..., split=..., seg=..., ms=..., trials=[...])."""
     if bands is None:

@@ -1696,6 +1696,17 @@ extern "C" fetiF_status fetiF_apply_host(fetiF_ctx c, const double* lambda_h, do
     return FETIF_OK;
 }
 
+extern "C" fetiF_status fetiF_read_probe(const void* buf_d, int64_t bytes, int64_t region_bytes, double* out_d,
+                                         void* stream)
+{
+    if (!buf_d || !out_d || bytes <= 0 || bytes % 16 != 0 || region_bytes <= 0 || region_bytes % 16384 != 0 ||
+        (bytes + region_bytes - 1) / region_bytes > INT32_MAX)
+        return fail(nullptr, FETIF_EINVAL, "fetiF_read_probe: buf and out set, bytes a positive multiple of 16, "
+                                           "region a positive multiple of 16384");
+    const hipError_t e = launch_read_probe(buf_d, bytes, region_bytes, out_d, (hipStream_t)stream);
+    return e == hipSuccess ? FETIF_OK : hip_fail(nullptr, e, "read probe launch");
+}
+
 extern "C" fetiF_status fetiF_set_assembly(fetiF_ctx c, int32_t trsm_panel, int32_t trsm_chunk)
 {
     if (!c) return FETIF_EINVAL;
@@ -1724,10 +1735,10 @@ extern "C" fetiF_status fetiF_set_apply(fetiF_ctx c, int32_t band_elems, int32_t
     if (!c) return FETIF_EINVAL;
     if (c->sticky) return FETIF_EDEVICE;
     if (band_elems < 0 || (rows != 0 && rows != 2 && rows != 4) || nontemporal < -1 || nontemporal > 1 ||
-        split < -1 || split > 1 || (seg != -1 && seg != 0 && seg != 4 && seg != 8))
+        split < -1 || split > 1 || (seg != -1 && seg != 0 && seg != 2 && seg != 3 && seg != 4 && seg != 8))
         return fail(c, FETIF_EINVAL,
                     "band_elems >= 0, rows in {0,2,4}, nontemporal in {-1,0,1}, split in {-1,0,1}, "
-                    "seg in {-1,0,4,8}");
+                    "seg in {-1,0,2,3,4,8}");
     if (seg == 0 && c->apply_nch == 0)
         return fail(c, FETIF_ENOTSUP,
                     "the whole-row apply kernel holds at most " + std::to_string(kMaxWholeRowCols) +

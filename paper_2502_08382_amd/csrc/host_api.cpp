@@ -60,7 +60,8 @@ void options_defaults(const fetiF_options* in, fetiF_options& o)
     if (o.apply_rows != 2 && o.apply_rows != 4) o.apply_rows = 4;
     if (o.apply_nontemporal < 0 || o.apply_nontemporal > 1) o.apply_nontemporal = 1;
     if (o.apply_split < 0 || o.apply_split > 1) o.apply_split = 0;
-    if (o.apply_seg != 0 && o.apply_seg != 4 && o.apply_seg != 8) o.apply_seg = 4;
+    if (o.apply_seg != 0 && o.apply_seg != 2 && o.apply_seg != 3 && o.apply_seg != 4 && o.apply_seg != 8)
+        o.apply_seg = 4;
     if (o.trsm_panel <= 0) o.trsm_panel = 48;
     o.trsm_panel = std::max(16, std::min(96, (o.trsm_panel + 15) / 16 * 16));
     if (o.assembly_groups <= 0) o.assembly_groups = 1;

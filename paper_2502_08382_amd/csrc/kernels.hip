@@ -1218,6 +1218,42 @@ __global__ __launch_bounds__(NT) void apply_seg_kernel(const Band* __restrict__ 
     }
 }
 
+// Streaming-read probe (a measurement aid, no part of the method): work-group
+// g reads bytes [g * region, min((g + 1) * region, bytes)) of buf as FP64
+// values with 16-byte non-temporal buffer loads, four per lane in flight,
+// and writes their sum to out[g].  It measures the read rate the chip gives
+// a kernel that streams contiguous regions per work-group, the access
+// pattern of the apply's bands.
+__global__ __launch_bounds__(NT) void read_probe_kernel(const char* __restrict__ buf, int64_t bytes, int64_t region,
+                                                        double* __restrict__ out)
+{
+    const int64_t beg = (int64_t)blockIdx.x * region;
+    const int64_t len = (bytes - beg) < region ? (bytes - beg) : region;
+    const char* base = buf + beg;
+    double acc = 0.0;
+    constexpr int64_t step = (int64_t)NT * 16 * 4;
+    for (int64_t o = 0; o < len; o += step) {
+        // the window [o, o + step) through a descriptor that ends at the
+        // region's end: loads past it read zero
+        const char* w = base + o;
+        const uint32_t nb = (uint32_t)((len - o) < step ? (len - o) : step);
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = load16_range<true>(w, nb, (k * NT + (int)threadIdx.x) * 16);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double d[2];
+            unpack<double, 2>(v[k], d);
+            acc += d[0] + d[1];
+        }
+    }
+    acc = wave_sum(acc);
+    __shared__ double part[NT / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
 // q[g]: the partial sums of every band that holds a term of multiplier g,
 // read straight from their positions in the partial vectors, in a fixed
 // order (one thread per multiplier; two dependent loads per term).
@@ -1468,11 +1504,26 @@ static hipError_t seg_dispatch(int segch, int rows, bool ntl, const Band* bands,
                                int32_t ngroups, const void* F, const double* lam, const int32_t* dmap, void* z,
                                int32_t brmax, hipStream_t st)
 {
-    // instances: (4 chunks, 2 or 4 rows) and (8 chunks, 2 rows); 8 chunks
-    // with 4 rows would not fit two wavefronts per SIMD
+    // instances: (2, 3 or 4 chunks, 2 or 4 rows) and (8 chunks, 2 rows);
+    // 8 chunks with 4 rows would not fit two wavefronts per SIMD
     if (segch == 8)
         return ntl ? seg_launch<T, 8, 2, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st)
                    : seg_launch<T, 8, 2, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
+    if (segch == 2) {
+        if (rows == 4)
+            return ntl ? seg_launch<T, 2, 4, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st)
+                       : seg_launch<T, 2, 4, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
+        return ntl ? seg_launch<T, 2, 2, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st)
+                   : seg_launch<T, 2, 2, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
+    }
+    if (segch == 3) {
+        if (rows == 4)
+            return ntl ? seg_launch<T, 3, 4, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st)
+                       : seg_launch<T, 3, 4, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
+        return ntl ? seg_launch<T, 3, 2, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st)
+                   : seg_launch<T, 3, 2, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
+    }
+    if (segch != 4) return hipErrorInvalidValue;
     if (rows == 4)
         return ntl ? seg_launch<T, 4, 4, true>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st)
                    : seg_launch<T, 4, 4, false>(bands, seg_ptr, ngroups, F, lam, dmap, z, brmax, st);
@@ -1528,6 +1579,14 @@ hipError_t static_scratch_address(int device, void** out)
     }
     *out = scratch_addr[device];
     return hipSuccess;
+}
+
+hipError_t launch_read_probe(const void* buf, int64_t bytes, int64_t region, double* out, hipStream_t st)
+{
+    if (bytes <= 0) return hipSuccess;
+    const int64_t groups = (bytes + region - 1) / region;
+    hipLaunchKernelGGL(read_probe_kernel, dim3((unsigned)groups), dim3(NT), 0, st, (const char*)buf, bytes, region, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* zptr, const int64_t* zpos, const void* z,

@@ -90,6 +90,10 @@ inline size_t apply_seg_lds_bytes(int prec, int segch, int32_t brmax)
 hipError_t launch_gather(int prec, int64_t n_lambda, const int32_t* zptr, const int64_t* zpos, const void* z,
                          double* q, hipStream_t st);
 
+// streaming-read probe: work-group g sums bytes [g region, (g+1) region) of
+// buf as FP64 values into out[g] (ceil(bytes / region) work-groups)
+hipError_t launch_read_probe(const void* buf, int64_t bytes, int64_t region, double* out, hipStream_t st);
+
 // Size of the file-scope device array `scratch` (kernels.hip) that holds the
 // apply partial vectors of the allocation-free apply: one copy per device,
 // held until the process ends.

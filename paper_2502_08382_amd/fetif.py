@@ -76,7 +76,8 @@ EXPORTS = ["fetiF_create", "fetiF_factor_upload", "fetiF_assemble", "fetiF_apply
            "fetiF_hfactor_supernodes", "fetiF_hfactor_free", "fetiF_profile_enable",
            "fetiF_profile_read", "fetiF_set_apply", "fetiF_apply_implicit", "fetiF_dual_rhs",
            "fetiF_coarse_rhs", "fetiF_pcpg", "fetiF_primal", "fetiF_set_assembly", "fetiF_factor_assemble",
-           "fetiF_apply_static", "fetiF_set_assembly_path", "fetiF_apply_host", "fetiF_precond_values"]
+           "fetiF_apply_static", "fetiF_set_assembly_path", "fetiF_apply_host", "fetiF_precond_values",
+           "fetiF_read_probe"]
 
 PHASES = ["factor_copy", "rhs_init", "trsm", "syrk", "apply_band", "apply_gather", "solves", "trsm_bwd", "spmm"]
 
@@ -102,6 +103,7 @@ def load_library(path=None):
     L.fetiF_apply_static.argtypes = [vp, vp, vp, vp]
     L.fetiF_apply_host.argtypes = [vp, vp, vp, i32, vp]
     L.fetiF_precond_values.argtypes = [vp, i32, i32, ctypes.POINTER(vp)]
+    L.fetiF_read_probe.argtypes = [vp, i64, i64, vp, vp]
     L.fetiF_apply_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fetiF_download_F.argtypes = [vp, i32, vp]
     L.fetiF_query.argtypes = [vp, ctypes.POINTER(_Info)]
@@ -216,6 +218,20 @@ def _options(f_storage="f64", leaf_nodes=0, nthreads=0, apply_band=0, trsm_chunk
     prec = _PREC[f_storage] if isinstance(f_storage, str) else int(f_storage)
     return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk, apply_rows, apply_nontemporal, apply_split,
                 trsm_panel, apply_seg, assembly_groups, int(schur_order))
+
+
+def read_probe(buf, region_bytes, out, stream=None):
+    """Streaming-read probe (measurement aid, fetiF_read_probe): every
+    work-group sums one contiguous region of the device tensor buf into out
+    (a float64 device tensor of ceil(bytes / region_bytes) entries)."""
+    L = load_library()
+    nbytes = buf.numel() * buf.element_size()
+    ngroups = -(-nbytes // region_bytes)
+    if out.numel() < ngroups or out.dtype.itemsize != 8:
+        raise ValueError(f"out needs {ngroups} float64 entries")
+    st = L.fetiF_read_probe(_dptr(buf), int(nbytes), int(region_bytes), _dptr(out), _stream(stream))
+    if st != 0:
+        raise FetiError(st, L.fetiF_last_error(None).decode())
 
 
 class FetiContext:

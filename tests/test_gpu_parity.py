@@ -182,7 +182,7 @@ def test_apply_every_launch_shape(torch_cuda, prec, tol, ktol):
                                 prob.lam, prob.n_lambda)
     total = ctx.info()["apply_elements"]
     ref = None
-    for seg in (0, 4, 8):
+    for seg in (0, 2, 3, 4, 8):
         for split in (0, 1):
             for band in (1, 3000, total // 5, total):
                 for rows in (2, 4):

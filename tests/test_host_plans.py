@@ -130,7 +130,7 @@ def flow(prob, with_elements=False, **opts):
     n = prob.n_lambda
     lam = np.zeros(n)
     q = np.zeros(n)
-    for seg in ((0, 4, 8) if max(s.m for s in prob.subs) <= 4096 else (4, 8)):
+    for seg in ((0, 2, 3, 4, 8) if max(s.m for s in prob.subs) <= 4096 else (2, 4, 8)):
         for split in (0, 1):
             for band in (1, 3000, 0):
                 ctx.set_apply(band, 2, 1, split, seg)
