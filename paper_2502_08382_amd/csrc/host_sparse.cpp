@@ -467,6 +467,70 @@ bool symbolic_analysis(const Pattern& A, int dpn, const double* coords, int dim,
 
 // ---------------------------------------------------------------- numeric
 
+namespace {
+
+// out[i] -= sum_{t < nk} l[t] * col[t][i] for i in [i0, i1); nk <= 16,
+// the sum in t order for each i.  The same code is compiled twice: for the
+// baseline x86-64 target and for AVX2 + FMA, chosen once at run time.
+#define FETIF_AXPY_BLOCK_BODY                                                                                      \
+    switch (nk) {                                                                                                  \
+    case 16:                                                                                                       \
+        for (int32_t i = i0; i < i1; ++i)                                                                          \
+            out[i] -= ((l[0] * col[0][i] + l[1] * col[1][i] + l[2] * col[2][i] + l[3] * col[3][i]) +              \
+                       (l[4] * col[4][i] + l[5] * col[5][i] + l[6] * col[6][i] + l[7] * col[7][i])) +             \
+                      ((l[8] * col[8][i] + l[9] * col[9][i] + l[10] * col[10][i] + l[11] * col[11][i]) +          \
+                       (l[12] * col[12][i] + l[13] * col[13][i] + l[14] * col[14][i] + l[15] * col[15][i]));      \
+        return;                                                                                                    \
+    case 8:                                                                                                        \
+        for (int32_t i = i0; i < i1; ++i)                                                                          \
+            out[i] -= (l[0] * col[0][i] + l[1] * col[1][i] + l[2] * col[2][i] + l[3] * col[3][i]) +               \
+                      (l[4] * col[4][i] + l[5] * col[5][i] + l[6] * col[6][i] + l[7] * col[7][i]);                \
+        return;                                                                                                    \
+    default:                                                                                                       \
+        for (int32_t i = i0; i < i1; ++i) {                                                                        \
+            double a = 0.0;                                                                                        \
+            for (int32_t t = 0; t < nk; ++t) a += l[t] * col[t][i];                                                \
+            out[i] -= a;                                                                                           \
+        }                                                                                                          \
+    }
+
+void axpy_block_base(double* out, int32_t i0, int32_t i1, const double* l, const double* const* col, int32_t nk)
+{
+    FETIF_AXPY_BLOCK_BODY
+}
+
+__attribute__((target("avx2,fma"))) void axpy_block_avx2(double* out, int32_t i0, int32_t i1, const double* l,
+                                                          const double* const* col, int32_t nk)
+{
+    FETIF_AXPY_BLOCK_BODY
+}
+#undef FETIF_AXPY_BLOCK_BODY
+
+using AxpyFn = void (*)(double*, int32_t, int32_t, const double*, const double* const*, int32_t);
+const AxpyFn axpy_block = (__builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma")) ? axpy_block_avx2
+                                                                                          : axpy_block_base;
+
+// Columns j in [j0, j1) of the column-major front F (leading dimension d)
+// take the rank-(k1 - k0) update of factored columns [k0, k1): F[i][j] -=
+// sum_k F[i][k] F[j][k] for rows i >= j.
+void rank_update(double* F, int32_t d, int32_t k0, int32_t k1, int32_t j0, int32_t j1, int32_t)
+{
+    for (int32_t j = j0; j < j1; ++j) {
+        double l[16];
+        const double* lk[16];
+        int32_t nk = 0;
+        for (int32_t k = k0; k < k1; ++k) {
+            const double v = F[(size_t)k * d + j];
+            if (v == 0.0) continue;
+            l[nk] = v;
+            lk[nk++] = F + (size_t)k * d;
+        }
+        if (nk) axpy_block(F + (size_t)j * d, j, d, l, lk, nk);
+    }
+}
+
+}  // namespace
+
 int32_t numeric_cholesky(const Symbolic& S, const double* vals, double* panels)
 {
     const int32_t n = S.n;
@@ -502,23 +566,32 @@ int32_t numeric_cholesky(const Symbolic& S, const double* vals, double* panels)
             }
             std::vector<double>().swap(upd[c]);
         }
-        // partial dense Cholesky of the front: the nc pivot columns
-        for (int32_t k = 0; k < nc; ++k) {
-            double* ck = &F[(size_t)k * d];
-            double piv = ck[k];
-            if (!(piv > 0.0) || !std::isfinite(piv)) return x.first + k;
-            double r = std::sqrt(piv);
-            ck[k] = r;
-            double inv = 1.0 / r;
-            for (int32_t i = k + 1; i < d; ++i) ck[i] *= inv;
-            for (int32_t j = k + 1; j < nc; ++j) {
-                double l = ck[j];
-                if (l == 0.0) continue;
-                double* cj = &F[(size_t)j * d];
-                for (int32_t i = j; i < d; ++i) cj[i] -= ck[i] * l;
+        // partial dense Cholesky of the front, the nc pivot columns, by
+        // blocks of kBlk columns: a block is factored column by column, then
+        // the front's later pivot columns take its kBlk columns at once (one
+        // pass over each target column per block instead of one per column)
+        constexpr int32_t kBlk = 16;
+        for (int32_t k0 = 0; k0 < nc; k0 += kBlk) {
+            const int32_t k1 = std::min(nc, k0 + kBlk);
+            for (int32_t k = k0; k < k1; ++k) {
+                double* ck = &F[(size_t)k * d];
+                double piv = ck[k];
+                if (!(piv > 0.0) || !std::isfinite(piv)) return x.first + k;
+                double r = std::sqrt(piv);
+                ck[k] = r;
+                double inv = 1.0 / r;
+                for (int32_t i = k + 1; i < d; ++i) ck[i] *= inv;
+                for (int32_t j = k + 1; j < k1; ++j) {
+                    double l = ck[j];
+                    if (l == 0.0) continue;
+                    double* cj = &F[(size_t)j * d];
+                    for (int32_t i = j; i < d; ++i) cj[i] -= ck[i] * l;
+                }
             }
+            rank_update(F.data(), d, k0, k1, k1, nc, k1);
         }
-        // update matrix for the parent: F22 - L21 L21^T (lower part)
+        // update matrix for the parent: F22 - L21 L21^T (lower part), by
+        // blocks of kBlk columns of L21
         const int32_t m = x.nrows;
         if (m > 0 && x.parent >= 0) {
             std::vector<double>& U = upd[s];
@@ -528,13 +601,22 @@ int32_t numeric_cholesky(const Symbolic& S, const double* vals, double* panels)
                 const double* fcol = &F[(size_t)(nc + b) * d + nc];
                 for (int32_t a = b; a < m; ++a) ucol[a] = fcol[a];
             }
-            for (int32_t k = 0; k < nc; ++k) {
-                const double* l21 = &F[(size_t)k * d + nc];
+            for (int32_t k0 = 0; k0 < nc; k0 += kBlk) {
+                const int32_t k1 = std::min(nc, k0 + kBlk);
+                // U[a][b] -= sum_k L21[a][k] L21[b][k], L21 column k at F + k d + nc
                 for (int32_t b = 0; b < m; ++b) {
-                    double l = l21[b];
-                    if (l == 0.0) continue;
+                    double l[kBlk] = {0};
+                    const double* lk[kBlk] = {nullptr};
+                    int32_t nk = 0;
+                    for (int32_t k = k0; k < k1; ++k) {
+                        const double v = F[(size_t)k * d + nc + b];
+                        if (v == 0.0) continue;
+                        l[nk] = v;
+                        lk[nk++] = &F[(size_t)k * d + nc];
+                    }
+                    if (!nk) continue;
                     double* ucol = &U[(size_t)b * m];
-                    for (int32_t a = b; a < m; ++a) ucol[a] -= l21[a] * l;
+                    axpy_block(ucol, b, m, l, lk, nk);
                 }
             }
         }
