@@ -180,3 +180,24 @@ def test_host_vector_apply_scatter_gather_on_gpu_or_cpu(torch_cuda, prec):
         say(f"host-vector apply {prec}: n_lambda {prob.n_lambda}: GPU and CPU scatter/gather bitwise equal "
             f"to fetiF_apply")
         ctx.close()
+
+
+def test_read_probe_sums_every_region(torch_cuda):
+    """The streaming-read probe (a measurement aid) reads every byte once:
+    region sums of a buffer of k = 0, 1, 2, ... equal the closed form, also
+    for a ragged last region."""
+    t = torch_cuda
+    from paper_2502_08382_amd.fetif import read_probe
+    n = 3 * (1 << 20) + 4098                 # FP64 values; bytes not a multiple of the region
+    buf = t.arange(n, dtype=t.float64, device="cuda")
+    for region in (16384, 1 << 20):
+        per = region // 8
+        ng = -(-n // per)
+        out = t.full((ng,), float("nan"), dtype=t.float64, device="cuda")
+        read_probe(buf, region, out)
+        t.cuda.synchronize()
+        lo = np.arange(ng) * per
+        hi = np.minimum(lo + per, n)
+        expect = (hi * (hi - 1) - lo * (lo - 1)) / 2.0
+        got = out.cpu().numpy()
+        assert np.allclose(got, expect, rtol=1e-12, atol=0), (region, np.abs(got - expect).max())
