@@ -724,7 +724,11 @@ constexpr int SP = ST + 2;
 // pipeline: the global loads of a 16-row stage are requested two stages
 // ahead (two register sets), and the two LDS buffers alternate, so each
 // stage needs one barrier.  On diagonal tiles the two column ranges
-// coincide and one buffer serves both operands.
+// coincide and one buffer serves both operands.  A wavefront skips the MFMAs
+// whose operands are zero throughout: a 16-column block that misses the
+// stage's RHS range, the k-steps past the supernode's last row, and on a
+// diagonal tile the quadrant above the diagonal (never stored).  The tests
+// are uniform over the wavefront and leave every sum unchanged.
 template <typename T>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void syrk_kernel(const SyrkTile* __restrict__ tiles,
                                                   const int32_t* __restrict__ lists,
@@ -757,8 +761,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sy
     // and for the B operand of a diagonal tile, so every load is issued
     // unconditionally and the compiler waits only for the stage it stages.
     static_assert(ST == 64 && NT == 256, "one X row per wavefront and load");
-    auto fetch = [&](double (&ra)[U], double (&rb)[U]) {
+    // what the multiply of a fetched stage needs: its RHS range [j0, j1) and rows
+    struct StageInfo {
+        int j0, j1, rows;
+    };
+    auto fetch = [&](double (&ra)[U], double (&rb)[U], StageInfo& si) {
         const DevSN s = sns[lists[fl]];
+        si.j0 = s.j0;
+        si.j1 = s.j0 + s.w;
+        si.rows = s.ncols - fk < SK ? s.ncols - fk : SK;
         const int la = (ca0 + lane - s.j0) * 8, lb = (cb0 + lane - s.j0) * 8;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -787,32 +798,44 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sy
         }
         __syncthreads();
     };
-    auto multiply = [&](int st) {
+    const int ra0 = ca0 + 32 * wi, rb0 = cb0 + 32 * wj;   // first columns of the quadrant's blocks
+    const bool upper = diag && wi < wj;                    // quadrant above the diagonal
+    auto multiply = [&](int st, const StageInfo& si) {
         const int buf = st & 1;
         const double(*pb)[SP] = diag ? sa[buf] : sb[buf];
+        // 16-column blocks of the quadrant that meet the stage's range
+        const bool ia0 = !upper && ra0 < si.j1 && ra0 + 16 > si.j0;
+        const bool ia1 = !upper && ra0 + 16 < si.j1 && ra0 + 32 > si.j0;
+        const bool ib0 = rb0 < si.j1 && rb0 + 16 > si.j0;
+        const bool ib1 = rb0 + 16 < si.j1 && rb0 + 32 > si.j0;
+        if (!((ia0 || ia1) && (ib0 || ib1))) return;
 #pragma unroll
         for (int k4 = 0; k4 < SK / 4; ++k4) {
+            if (4 * k4 >= si.rows) break;
             const int kr = 4 * k4 + q;
             const double a0 = sa[buf][kr][32 * wi + j], a1 = sa[buf][kr][32 * wi + 16 + j];
             const double b0 = pb[kr][32 * wj + j], b1 = pb[kr][32 * wj + 16 + j];
-            acc[0][0] = mfma16(a0, b0, acc[0][0]);
-            acc[0][1] = mfma16(a0, b1, acc[0][1]);
-            acc[1][0] = mfma16(a1, b0, acc[1][0]);
-            acc[1][1] = mfma16(a1, b1, acc[1][1]);
+            if (ia0 && ib0) acc[0][0] = mfma16(a0, b0, acc[0][0]);
+            if (ia0 && ib1) acc[0][1] = mfma16(a0, b1, acc[0][1]);
+            if (ia1 && ib0) acc[1][0] = mfma16(a1, b0, acc[1][0]);
+            if (ia1 && ib1) acc[1][1] = mfma16(a1, b1, acc[1][1]);
         }
     };
     // two register sets: stage st's values were requested two stages earlier
     double r0a[U], r0b[U], r1a[U], r1b[U];
-    if (nst > 0) fetch(r0a, r0b);
-    if (nst > 1) fetch(r1a, r1b);
+    StageInfo f0{}, f1{}, cur{};
+    if (nst > 0) fetch(r0a, r0b, f0);
+    if (nst > 1) fetch(r1a, r1b, f1);
     for (int st = 0; st < nst; st += 2) {
         stage(st, r0a, r0b);
-        if (st + 2 < nst) fetch(r0a, r0b);
-        multiply(st);
+        cur = f0;
+        if (st + 2 < nst) fetch(r0a, r0b, f0);
+        multiply(st, cur);
         if (st + 1 >= nst) break;
         stage(st + 1, r1a, r1b);
-        if (st + 3 < nst) fetch(r1a, r1b);
-        multiply(st + 1);
+        cur = f1;
+        if (st + 3 < nst) fetch(r1a, r1b, f1);
+        multiply(st + 1, cur);
     }
     constexpr int64_t V = kRowAlignBytes / sizeof(T);
 #pragma unroll
