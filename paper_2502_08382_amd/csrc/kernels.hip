@@ -919,6 +919,21 @@ __device__ __forceinline__ uint4 load16_range(const void* base, uint32_t nbytes,
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+// A descriptor over one padded row [base, base + nbytes) and 16-byte loads at
+// byte offsets into it: an offset at or past nbytes reads zero.  One
+// descriptor serves every chunk of the row (the chunk's position is part of
+// the per-lane offset), so the scalar work is per row, not per load.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* base, uint32_t nbytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nbytes, 0x00020000);
+}
+template <bool NTL>
+__device__ __forceinline__ uint4 load16_at(__amdgpu_buffer_rsrc_t r, int off)
+{
+    u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, NTL ? 2 : 0);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 template <bool NTL>
 __device__ __forceinline__ uint4 load16(const void* p)
 {
@@ -978,17 +993,19 @@ __global__ __launch_bounds__(NT) void apply_band_kernel(const Band* __restrict__
     const char* __restrict__ tri = reinterpret_cast<const char*>(F + b.fbase);
     // loads of the ROWS rows from r on; rows at or past r1 read zero (empty range)
     auto issue = [&](int r, uint4 (&raw)[ROWS][NH]) {
+        // padded row r + k: bytes [row_start, row_start + len); a row's
+        // successor starts len bytes later
+        int64_t row_start = packed_row_offset(r, RA) * (int64_t)sizeof(T);
 #pragma unroll
         for (int k = 0; k < ROWS; ++k) {
-            // padded row r + k: bytes [row_start, row_start + row_bytes)
-            const int64_t row_start = packed_row_offset(r + k, RA) * (int64_t)sizeof(T);
-            const int row_bytes = r + k < b.r1 ? (int)(RA * ((r + k) / RA + 1) * sizeof(T)) : 0;
+            const int len = (int)(RA * ((r + k) / RA + 1) * sizeof(T));
+            const int row_bytes = r + k < b.r1 ? len : 0;
+            const __amdgpu_buffer_rsrc_t rs = row_rsrc(tri + row_start, (uint32_t)row_bytes);
+            row_start += len;
 #pragma unroll
             for (int c2 = 0; c2 < NH; ++c2) {
                 const int ch = 2 * c2 + half;
-                const int cbyte = ch * CH * (int)sizeof(T);
-                const int nbytes = (ch < NCH && row_bytes > cbyte) ? row_bytes - cbyte : 0;
-                raw[k][c2] = load16_range<NTL>(tri + row_start + cbyte, (uint32_t)nbytes, lane * 16);
+                raw[k][c2] = ch < NCH ? load16_at<NTL>(rs, ch * CH * (int)sizeof(T) + lane * 16) : make_uint4(0, 0, 0, 0);
             }
         }
     };
@@ -1142,16 +1159,16 @@ __global__ __launch_bounds__(NT) void apply_seg_kernel(const Band* __restrict__ 
         // the ROWS rows from r on, this segment's chunks; rows at or past r1
         // and chunks past a row's end read zero (empty range)
         auto issue = [&](int r, uint4 (&raw)[ROWS][SEGCH]) {
+            int64_t row_start = packed_row_offset(r, RA) * (int64_t)sizeof(T);
 #pragma unroll
             for (int k = 0; k < ROWS; ++k) {
-                const int64_t row_start = packed_row_offset(r + k, RA) * (int64_t)sizeof(T);
-                const int row_bytes = r + k < b.r1 ? (int)(RA * ((r + k) / RA + 1) * sizeof(T)) : 0;
+                const int len = (int)(RA * ((r + k) / RA + 1) * sizeof(T));
+                const int row_bytes = r + k < b.r1 ? len : 0;
+                const __amdgpu_buffer_rsrc_t rs = row_rsrc(tri + row_start, (uint32_t)row_bytes);
+                row_start += len;
 #pragma unroll
-                for (int ch = 0; ch < SEGCH; ++ch) {
-                    const int cbyte = (c0 + ch * CH) * (int)sizeof(T);
-                    const int nbytes = row_bytes > cbyte ? row_bytes - cbyte : 0;
-                    raw[k][ch] = load16_range<NTL>(tri + row_start + cbyte, (uint32_t)nbytes, lane * 16);
-                }
+                for (int ch = 0; ch < SEGCH; ++ch)
+                    raw[k][ch] = load16_at<NTL>(rs, (c0 + ch * CH) * (int)sizeof(T) + lane * 16);
             }
         };
         auto consume = [&](int r, const uint4 (&raw)[ROWS][SEGCH]) {
