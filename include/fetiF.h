@@ -318,8 +318,10 @@ typedef struct {
     int32_t iters;        /* operator applications in PCPG iterations (all inner solves) */
     int32_t outer;        /* refinement steps (0 without refinement) */
     double rel_residual;  /* ||w|| / ||w_0|| at exit: recursive (no refinement) or
-                             true FP64 projected residual (refinement) */
-    double w0;            /* ||w_0|| */
+                             true FP64 projected residual (refinement); NaN when a
+                             residual was not finite (NaN or Inf in d, e or the initial
+                             lambda, or an operator that broke down), never 0 */
+    double w0;            /* ||w_0|| (NaN when not finite) */
 } fetiF_pcpg_result;
 
 /* Stiffness values for the lumped preconditioners (fetiF_pcpg_options

@@ -2,6 +2,7 @@
 // M = I or lumped), FP64 iterative refinement around a reduced-precision operator, and
 // the primal recovery of alpha and u (Sec. II).
 #include <cmath>
+#include <limits>
 
 #include "context.hpp"
 
@@ -286,8 +287,13 @@ fetiF_status pcpg_core(fetiF_ctx c, const double* d, const double* e, double* la
         }
     }
     if (iters_out) *iters_out = it;
-    if (w0_out) *w0_out = std::sqrt(std::max(0.0, h0));
-    if (rel_out) *rel_out = h0 > 0.0 ? std::sqrt(std::max(0.0, hk) / h0) : 0.0;
+    if (w0_out) *w0_out = std::isfinite(h0) ? std::sqrt(std::max(0.0, h0)) : std::numeric_limits<double>::quiet_NaN();
+    // a residual that is not finite (NaN or Inf in the inputs, or an
+    // operator that broke down) is reported as NaN, never as converged
+    if (rel_out)
+        *rel_out = !(std::isfinite(h0) && std::isfinite(hk)) ? std::numeric_limits<double>::quiet_NaN()
+                   : h0 > 0.0                                 ? std::sqrt(std::max(0.0, hk) / h0)
+                                                              : 0.0;
     return FETIF_OK;
 }
 
@@ -400,6 +406,10 @@ extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double*
             double ww = 0.0;
             HIPCHK(c, hipMemcpyAsync(&ww, c->dSc + SC_TMP, sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));
+            if (outer == 0 && !std::isfinite(ww)) {
+                w0 = wk = std::numeric_limits<double>::quiet_NaN();
+                break;
+            }
             wk = std::sqrt(std::max(0.0, ww));
             if (outer == 0) w0 = wk;
             if (outer > 0 && !(wk < wprev)) {
@@ -419,7 +429,7 @@ extern "C" fetiF_status fetiF_pcpg(fetiF_ctx c, const double* d_d, const double*
         }
         R.iters = total;
         R.w0 = w0;
-        R.rel_residual = w0 > 0.0 ? wk / w0 : 0.0;
+        R.rel_residual = !std::isfinite(w0) ? std::numeric_limits<double>::quiet_NaN() : w0 > 0.0 ? wk / w0 : 0.0;
     }
     if (res) *res = R;
     return FETIF_OK;

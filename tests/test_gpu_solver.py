@@ -262,3 +262,31 @@ def test_pcpg_scaled_lumped_preconditioner(torch_cuda, case):
     assert r["rel_residual"] <= 1e-12 and err <= 1e-8
     assert r["iters"] < r0["iters"]
     ctx.close()
+
+
+@pytest.mark.parametrize("refine", [False, True])
+def test_pcpg_reports_nan_for_non_finite_input(torch_cuda, refine):
+    """A NaN in d makes the projected residual NaN: the solver reports
+    rel_residual (and w0) as NaN, not as a converged 0, and the same context
+    solves a finite right-hand side normally afterwards."""
+    t = torch_cuda
+    prob = _cases()["heat3d"]()
+    ctx = make_context(prob)
+    ctx.factor_upload([s.Kreg.data for s in prob.subs])
+    ctx.assemble()
+    f = _dev(t, np.concatenate([s.f for s in prob.subs]))
+    e = t.empty(ctx.n_coarse, dtype=t.float64, device="cuda")
+    d = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+    lam = t.empty(prob.n_lambda, dtype=t.float64, device="cuda")
+    ctx.coarse_rhs(f, e)
+    ctx.dual_rhs(f, d)
+    d[3] = float("nan")
+    r = ctx.pcpg(d, e, lam, tol=1e-9, max_iters=200, refine=refine)
+    t.cuda.synchronize()
+    say("NaN in d, refine", refine, r)
+    assert np.isnan(r["rel_residual"]) and np.isnan(r["w0"]), r
+    ctx.dual_rhs(f, d)
+    r2 = ctx.pcpg(d, e, lam, tol=1e-9, max_iters=3000, refine=refine)
+    t.cuda.synchronize()
+    say("finite d afterwards", r2)
+    assert r2["rel_residual"] <= 1e-9 and np.isfinite(lam.cpu().numpy()).all(), r2
