@@ -1325,23 +1325,35 @@ namespace {
 
 // Host factorisation of subdomains [first, first+count) and the asynchronous
 // copy of their values on st (no wait for earlier copies: every subdomain has
-// its own staging area).  Chunks of at least 64 MiB of factor values and at
-// least one subdomain per host thread (a shorter rest joins the last chunk):
-// the copy of a chunk and its diagonal-block inverses run on the stream while
-// the host factors the next chunk.
-fetiF_status upload_range(fetiF_ctx c, int32_t first, int32_t count, const double* const* k_vals, hipStream_t st)
+// its own staging area).  Chunks of at least 64 MiB of factor values and of
+// at least 4 subdomains per host thread, but no more than a quarter of the
+// range (a shorter rest joins the last chunk): the copy of a chunk and its
+// diagonal-block inverses run on the stream while the host factors the next
+// chunk.  With `one_chunk` the whole range is one chunk (an assembly group,
+// whose copy and assembly already overlap the factorisation of the next
+// group).  Within a chunk the threads take the subdomains largest
+// factorisation first, so that uneven subdomains still end together.
+fetiF_status upload_range(fetiF_ctx c, int32_t first, int32_t count, const double* const* k_vals, hipStream_t st,
+                          bool one_chunk = false)
 {
     // any upload replaces factor values: F~ must be assembled again, and on
     // failure the whole range counts as not uploaded
     c->assembled = false;
     constexpr int64_t kChunkVals = int64_t(8) << 20;
+    const int32_t min_subs = one_chunk ? count : std::max(c->nthreads, std::min(4 * c->nthreads, count / 4));
     for (int32_t k0 = 0; k0 < count;) {
         int32_t k1 = k0;
         int64_t vals = 0;
-        while (k1 < count && (k1 - k0 < c->nthreads || vals < kChunkVals)) vals += c->subs[first + k1++].sym.nvals;
-        if (count - k1 < c->nthreads) k1 = count;
+        while (k1 < count && (k1 - k0 < min_subs || vals < kChunkVals)) vals += c->subs[first + k1++].sym.nvals;
+        if (count - k1 < min_subs) k1 = count;
         std::vector<int32_t> bad(k1 - k0, -1);
-        parallel_for(k1 - k0, c->nthreads, [&](int32_t k) {
+        std::vector<int32_t> order(k1 - k0);
+        for (int32_t k = 0; k < k1 - k0; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return c->subs[first + k0 + a].sym.flops_factor > c->subs[first + k0 + b].sym.flops_factor;
+        });
+        parallel_for(k1 - k0, c->nthreads, [&](int32_t kk) {
+            const int32_t k = order[kk];
             const SubPlan& P = c->subs[first + k0 + k];
             bad[k] = numeric_cholesky(P.sym, k_vals[k0 + k], c->hStage + P.lbase);
             // the K_reg entries among boundary DOFs, for the lumped
@@ -1518,7 +1530,7 @@ extern "C" fetiF_status fetiF_factor_assemble(fetiF_ctx c, const double* const* 
     const int32_t G = (int32_t)c->grp_first.size() - 1;
     for (int32_t g = 0; g < G; ++g) {
         const int32_t s0 = c->grp_first[g], s1 = c->grp_first[g + 1];
-        fetiF_status s = upload_range(c, s0, s1 - s0, k_vals + s0, st);
+        fetiF_status s = upload_range(c, s0, s1 - s0, k_vals + s0, st, true);
         if (s != FETIF_OK) {
             // earlier groups were uploaded and assembled from this call's
             // values, later ones hold older factors: nothing counts as uploaded
