@@ -56,7 +56,8 @@ typedef enum {
     FETIF_ESTATE = 3,  /* call not valid in the current lifecycle state */
     FETIF_EDEVICE = 4, /* HIP runtime error or no usable device (sticky) */
     FETIF_ENOTSPD = 5, /* numeric factorisation met a non-positive pivot */
-    FETIF_ENOTSUP = 6  /* option not supported */
+    FETIF_ENOTSUP = 6, /* option not supported */
+    FETIF_ENONFINITE = 7 /* debug checks (fetiF_options.debug_checks) found a NaN or Inf */
 } fetiF_status;
 
 /* Storage precision of the assembled F~_i.  Assembly always computes in
@@ -136,6 +137,14 @@ typedef struct {
                              block only; the same kernels then assemble F~_i = -S of the
                              augmented matrix [K_reg B~^T; B~ 0].  0 (default): nested
                              dissection of all nodes (the SYRK path with a sparse RHS) */
+    int32_t debug_checks; /* 1: fetiF_assemble, fetiF_apply, fetiF_apply_static,
+                             fetiF_apply_implicit and fetiF_apply_backward wait for their
+                             work and scan their device inputs and outputs (lambda, g, q,
+                             dlambda, dtheta, the stored F~) for NaN or Inf, returning
+                             FETIF_ENONFINITE with the vector and the first bad index in
+                             fetiF_last_error.  These calls then synchronise their stream
+                             and must not be captured in a graph.  0 (default): no scans;
+                             non-finite values propagate */
 } fetiF_options;
 
 /* Preparation (Alg. 2, "preparation"; Sec. IV-B "Preparation"): nested

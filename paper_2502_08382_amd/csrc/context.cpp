@@ -1102,6 +1102,7 @@ extern "C" fetiF_status fetiF_create(fetiF_ctx* out, int device, int64_t n_lambd
     // the device address of the static scratch of fetiF_apply_static, looked
     // up here once per device (with the device current)
     CK(static_scratch_address(device, &c->dScratch));
+    if (c->opt.debug_checks) CK(dalloc(c, &c->dDbg, 1));
     CK(dalloc(c, &c->dL, (size_t)c->total_L));
     CK(dalloc(c, &c->dX, (size_t)c->total_X));
     {
@@ -1458,6 +1459,23 @@ extern "C" fetiF_status fetiF_factor_upload(fetiF_ctx c, int32_t first, int32_t 
 
 // ======================================================================== assemble
 
+// Debug scan (option debug_checks): waits for the stream's work, then reports
+// the first NaN or Inf among x[0, n) (elements of precision prec) as
+// FETIF_ENONFINITE, naming the call and the vector.
+static fetiF_status debug_scan(fetiF_ctx c, int prec, const void* x, int64_t n, const char* call, const char* what,
+                        hipStream_t st)
+{
+    HIPCHK(c, launch_first_nonfinite(prec, x, n, c->dDbg, st));
+    unsigned long long first = ~0ull;
+    HIPCHK(c, hipMemcpyAsync(&first, c->dDbg, sizeof first, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (first != ~0ull)
+        return fail(c, FETIF_ENONFINITE,
+                    std::string(call) + ": " + what + " holds a NaN or Inf at index " + std::to_string(first));
+    return FETIF_OK;
+}
+
+
 extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
 {
     if (!c) return FETIF_EINVAL;
@@ -1483,6 +1501,7 @@ extern "C" fetiF_status fetiF_assemble(fetiF_ctx c, void* stream)
         HIPCHK(c, t3.stop());
     }
     c->assembled = true;
+    if (c->opt.debug_checks) return debug_scan(c, c->prec, c->dF, c->total_F, "fetiF_assemble", "the stored F~", st);
     return FETIF_OK;
 }
 
@@ -1589,6 +1608,7 @@ fetiF_status apply_checks(fetiF_ctx c, const double* lambda_d, const double* q_d
 
 }  // namespace
 
+
 extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double* q_d, void* stream)
 {
     if (!c) return FETIF_EINVAL;
@@ -1596,7 +1616,12 @@ extern "C" fetiF_status fetiF_apply(fetiF_ctx c, const double* lambda_d, double*
     if (s0 != FETIF_OK) return s0;
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
-    return apply_with_partials(c, lambda_d, q_d, c->dZ, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    if (c->opt.debug_checks)
+        if (fetiF_status s1 = debug_scan(c, 0, lambda_d, c->n_lambda, "fetiF_apply", "lambda", st)) return s1;
+    const fetiF_status s2 = apply_with_partials(c, lambda_d, q_d, c->dZ, st);
+    if (s2 != FETIF_OK || !c->opt.debug_checks) return s2;
+    return debug_scan(c, 0, q_d, c->n_lambda, "fetiF_apply", "q", st);
 }
 
 extern "C" fetiF_status fetiF_apply_static(fetiF_ctx c, const double* lambda_d, double* q_d, void* stream)
@@ -1616,7 +1641,12 @@ extern "C" fetiF_status fetiF_apply_static(fetiF_ctx c, const double* lambda_d, 
     if (!c->dScratch) return fail(c, FETIF_ESTATE, "static scratch address not set");
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
-    return apply_with_partials(c, lambda_d, q_d, c->dScratch, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    if (c->opt.debug_checks)
+        if (fetiF_status s1 = debug_scan(c, 0, lambda_d, c->n_lambda, "fetiF_apply_static", "lambda", st)) return s1;
+    const fetiF_status s2 = apply_with_partials(c, lambda_d, q_d, c->dScratch, st);
+    if (s2 != FETIF_OK || !c->opt.debug_checks) return s2;
+    return debug_scan(c, 0, q_d, c->n_lambda, "fetiF_apply_static", "q", st);
 }
 
 extern "C" fetiF_status fetiF_apply_host(fetiF_ctx c, const double* lambda_h, double* q_h, int32_t cpu_scatter_gather,
@@ -1817,12 +1847,17 @@ extern "C" fetiF_status fetiF_apply_implicit(fetiF_ctx c, const double* lambda_d
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(c, order_after_upload(c, st));
-    PhaseTimer t6(c, st, 6);
-    HIPCHK(c, launch_scatter_dual(1, c->nsub, c->dSubRow, c->dSubM, c->dStartRows, c->dSignsSorted, c->dDmap,
-                                  lambda_d, nullptr, c->dXv, c->total_rows, st));
-    HIPCHK(c, solve_all(c, 1, st));
-    HIPCHK(c, launch_xgather(1, c->n_lambda, c->dXGptr, c->dXGent, c->dXv, nullptr, q_d, st));
-    HIPCHK(c, t6.stop());
+    if (c->opt.debug_checks)
+        if (fetiF_status s1 = debug_scan(c, 0, lambda_d, c->n_lambda, "fetiF_apply_implicit", "lambda", st)) return s1;
+    {
+        PhaseTimer t6(c, st, 6);
+        HIPCHK(c, launch_scatter_dual(1, c->nsub, c->dSubRow, c->dSubM, c->dStartRows, c->dSignsSorted, c->dDmap,
+                                      lambda_d, nullptr, c->dXv, c->total_rows, st));
+        HIPCHK(c, solve_all(c, 1, st));
+        HIPCHK(c, launch_xgather(1, c->n_lambda, c->dXGptr, c->dXGent, c->dXv, nullptr, q_d, st));
+        HIPCHK(c, t6.stop());
+    }
+    if (c->opt.debug_checks) return debug_scan(c, 0, q_d, c->n_lambda, "fetiF_apply_implicit", "q", st);
     return FETIF_OK;
 }
 
@@ -1852,18 +1887,32 @@ extern "C" fetiF_status fetiF_apply_backward(fetiF_ctx c, const double* g_d, con
     if (!g_d || !dlambda_d || g_d == dlambda_d) return fail(c, FETIF_EINVAL, "g/dlambda NULL or overlapping");
     if (dtheta_d && !lambda_d) return fail(c, FETIF_EINVAL, "dtheta needs lambda");
     if (dtheta_d && !c->has_elems) return fail(c, FETIF_EINVAL, "dtheta needs element data at create");
-    fetiF_status st0 = fetiF_apply(c, g_d, dlambda_d, stream);
-    if (st0 != FETIF_OK || !dtheta_d) return st0;
+    if (fetiF_status sa = apply_checks(c, g_d, dlambda_d)) return sa;
     DeviceGuard dg(c->device);
     if (!dg.ok) return hip_fail(c, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
+    const bool dbg = c->opt.debug_checks != 0;
+    if (dbg) {
+        if (fetiF_status s1 = debug_scan(c, 0, g_d, c->n_lambda, "fetiF_apply_backward", "g", st)) return s1;
+        if (dtheta_d)
+            if (fetiF_status s1 = debug_scan(c, 0, lambda_d, c->n_lambda, "fetiF_apply_backward", "lambda", st)) return s1;
+    }
+    // dlambda = F g (F~ is symmetric)
+    fetiF_status st0 = apply_with_partials(c, g_d, dlambda_d, c->dZ, st);
+    if (st0 != FETIF_OK) return st0;
+    if (dbg)
+        if (fetiF_status s1 = debug_scan(c, 0, dlambda_d, c->n_lambda, "fetiF_apply_backward", "dlambda", st)) return s1;
+    if (!dtheta_d) return FETIF_OK;
     HIPCHK(c, order_after_upload(c, st));
-    PhaseTimer t6(c, st, 6);
-    HIPCHK(c, launch_scatter_dual(2, c->nsub, c->dSubRow, c->dSubM, c->dStartRows, c->dSignsSorted, c->dDmap, g_d,
-                                  lambda_d, c->dXv, c->total_rows, st));
-    HIPCHK(c, solve_all(c, 2, st));
-    HIPCHK(c, launch_elem_adjoint(c->nelem_total, c->dElems, c->dEpos, c->dDK, c->dXv, dtheta_d, st));
-    HIPCHK(c, t6.stop());
+    {
+        PhaseTimer t6(c, st, 6);
+        HIPCHK(c, launch_scatter_dual(2, c->nsub, c->dSubRow, c->dSubM, c->dStartRows, c->dSignsSorted, c->dDmap,
+                                      g_d, lambda_d, c->dXv, c->total_rows, st));
+        HIPCHK(c, solve_all(c, 2, st));
+        HIPCHK(c, launch_elem_adjoint(c->nelem_total, c->dElems, c->dEpos, c->dDK, c->dXv, dtheta_d, st));
+        HIPCHK(c, t6.stop());
+    }
+    if (dbg) return debug_scan(c, 0, dtheta_d, c->nelem_total, "fetiF_apply_backward", "dtheta", st);
     return FETIF_OK;
 }
 

@@ -138,6 +138,7 @@ struct fetiF_ctx_s {
     int32_t* dEpos = nullptr;
     double* dDK = nullptr;
     void* dF = nullptr;
+    unsigned long long* dDbg = nullptr;   // first non-finite index of a debug scan (option debug_checks)
     void* dZ = nullptr;
     void* dScratch = nullptr;  // device address of the static scratch (fetiF_apply_static)
     // host-vector application (fetiF_apply_host): host copies of the sorted

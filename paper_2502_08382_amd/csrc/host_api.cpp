@@ -66,6 +66,7 @@ void options_defaults(const fetiF_options* in, fetiF_options& o)
     o.trsm_panel = std::max(16, std::min(96, (o.trsm_panel + 15) / 16 * 16));
     if (o.assembly_groups <= 0) o.assembly_groups = 1;
     o.schur_order = o.schur_order != 0 ? 1 : 0;
+    o.debug_checks = o.debug_checks != 0 ? 1 : 0;
 }
 
 }  // namespace fetif

@@ -381,6 +381,29 @@ __global__ __launch_bounds__(NT) void rtf_kernel(const CoarseSub* __restrict__ c
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
+// Debug scan: the smallest index of a NaN or Inf among x[0, n) (an element
+// is non-finite when its exponent bits are all ones), kept by a vector atomic
+// minimum on first[0].
+template <int BYTES>
+__global__ __launch_bounds__(NT) void first_nonfinite_kernel(const void* __restrict__ x, int64_t n,
+                                                             unsigned long long* __restrict__ first)
+{
+    unsigned long long mine = ~0ull;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        bool bad;
+        if constexpr (BYTES == 8) bad = ((static_cast<const uint64_t*>(x)[i] >> 52) & 0x7ff) == 0x7ff;
+        else if constexpr (BYTES == 4) bad = ((static_cast<const uint32_t*>(x)[i] >> 23) & 0xff) == 0xff;
+        else bad = ((static_cast<const uint16_t*>(x)[i] >> 7) & 0xff) == 0xff;
+        if (bad) {
+            mine = (unsigned long long)i;
+            break;
+        }
+    }
+    if (mine != ~0ull) atomicMin(first, mine);
+}
+
+__global__ void set_all_ones_kernel(unsigned long long* p) { *p = ~0ull; }
+
 }  // namespace
 
 hipError_t launch_gt(int32_t nsub, const CoarseSub* cs, const double* gv, const int32_t* dmap, const double* w,
@@ -503,6 +526,21 @@ hipError_t launch_load_primal_rhs(int32_t nsub, const int32_t* sub_rowbase, cons
 {
     hipLaunchKernelGGL(load_primal_rhs_kernel, dim3(nsub), dim3(NT), 0, st, sub_rowbase, sub_mbase, xperm,
                        start_rows, signs, dmap, f, lam, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_first_nonfinite(int prec, const void* x, int64_t n, unsigned long long* first, hipStream_t st)
+{
+    // the sentinel by a kernel, not a memset node (the call may sit in a graph)
+    hipLaunchKernelGGL(set_all_ones_kernel, dim3(1), dim3(1), 0, st, first);
+    if (n <= 0) return hipGetLastError();
+    const unsigned groups = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 4096);
+    if (prec == 0)
+        hipLaunchKernelGGL(first_nonfinite_kernel<8>, dim3(groups), dim3(NT), 0, st, x, n, first);
+    else if (prec == 1)
+        hipLaunchKernelGGL(first_nonfinite_kernel<4>, dim3(groups), dim3(NT), 0, st, x, n, first);
+    else
+        hipLaunchKernelGGL(first_nonfinite_kernel<2>, dim3(groups), dim3(NT), 0, st, x, n, first);
     return hipGetLastError();
 }
 

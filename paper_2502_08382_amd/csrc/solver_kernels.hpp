@@ -86,4 +86,10 @@ hipError_t launch_load_primal_rhs(int32_t nsub, const int32_t* sub_rowbase, cons
                                   const int32_t* xperm, const int32_t* start_rows, const int8_t* signs,
                                   const int32_t* dmap, const double* f, const double* lam, double* x, hipStream_t st);
 
+
+// Debug scan: first[0] = the index of the first element of x[0, n) that is
+// NaN or Inf, all ones when there is none; elements of precision prec (0
+// FP64, 1 FP32, 2 BF16 bits).
+hipError_t launch_first_nonfinite(int prec, const void* x, int64_t n, unsigned long long* first, hipStream_t st);
+
 }  // namespace fetif

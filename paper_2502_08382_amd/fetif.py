@@ -21,7 +21,7 @@ _PREC = {"f64": F64, "fp64": F64, "float64": F64, "f32": F32, "fp32": F32, "floa
          "bf16": BF16, "bfloat16": BF16}
 
 _STATUS = {0: "FETIF_OK", 1: "FETIF_EINVAL", 2: "FETIF_ENOMEM", 3: "FETIF_ESTATE",
-           4: "FETIF_EDEVICE", 5: "FETIF_ENOTSPD", 6: "FETIF_ENOTSUP"}
+           4: "FETIF_EDEVICE", 5: "FETIF_ENOTSPD", 6: "FETIF_ENOTSUP", 7: "FETIF_ENONFINITE"}
 
 
 class FetiError(RuntimeError):
@@ -46,7 +46,8 @@ class _Opt(ctypes.Structure):
                 ("trsm_chunk", ctypes.c_int32), ("apply_rows", ctypes.c_int32),
                 ("apply_nontemporal", ctypes.c_int32), ("apply_split", ctypes.c_int32),
                 ("trsm_panel", ctypes.c_int32), ("apply_seg", ctypes.c_int32),
-                ("assembly_groups", ctypes.c_int32), ("schur_order", ctypes.c_int32)]
+                ("assembly_groups", ctypes.c_int32), ("schur_order", ctypes.c_int32),
+                ("debug_checks", ctypes.c_int32)]
 
 
 class _PcpgOpt(ctypes.Structure):
@@ -214,10 +215,11 @@ class _SubArrays:
 
 
 def _options(f_storage="f64", leaf_nodes=0, nthreads=0, apply_band=0, trsm_chunk=0, apply_rows=0,
-             apply_nontemporal=-1, apply_split=-1, trsm_panel=0, apply_seg=-1, assembly_groups=0, schur_order=0):
+             apply_nontemporal=-1, apply_split=-1, trsm_panel=0, apply_seg=-1, assembly_groups=0, schur_order=0,
+             debug_checks=0):
     prec = _PREC[f_storage] if isinstance(f_storage, str) else int(f_storage)
     return _Opt(prec, leaf_nodes, nthreads, apply_band, trsm_chunk, apply_rows, apply_nontemporal, apply_split,
-                trsm_panel, apply_seg, assembly_groups, int(schur_order))
+                trsm_panel, apply_seg, assembly_groups, int(schur_order), int(bool(debug_checks)))
 
 
 def read_probe(buf, region_bytes, out, stream=None):

@@ -253,3 +253,53 @@ def test_backward_full_size(torch_cuda):
     say(f"central differences on {len(picks)} elements (all of subdomain {full}): max |fd - gpu|/bound "
         f"{worst_fd:.2e}")
     ctx.close()
+
+
+def test_debug_checks_report_non_finite_values(torch_cuda):
+    """Option debug_checks: a NaN in lambda (fetiF_apply, fetiF_apply_static,
+    fetiF_apply_implicit) or in g (fetiF_apply_backward) is reported as
+    FETIF_ENONFINITE naming the vector and its first bad index; with finite
+    inputs the results equal those of a context without checks, bitwise."""
+    from paper_2502_08382_amd import FetiError
+    t = torch_cuda
+    prob = _cases()["C5s"]()
+    ref = make_context(prob, with_elements=True)
+    dbg = make_context(prob, with_elements=True, debug_checks=1)
+    for c in (ref, dbg):
+        c.factor_upload([s.Kreg.data for s in prob.subs])
+        c.assemble()
+    ne = sum(len(s.theta) for s in prob.subs)
+    lam, g = _dev(t, prob.lam), _dev(t, prob.mu)
+    outs = {}
+    for name, c in (("ref", ref), ("dbg", dbg)):
+        q, qs, qi = (t.empty(prob.n_lambda, dtype=t.float64, device="cuda") for _ in range(3))
+        dl, dth = t.empty(prob.n_lambda, dtype=t.float64, device="cuda"), t.empty(ne, dtype=t.float64, device="cuda")
+        c.apply(lam, q)
+        c.apply_static(lam, qs)
+        c.apply_implicit(lam, qi)
+        c.apply_backward(g, lam, dl, dth)
+        t.cuda.synchronize()
+        outs[name] = [x.cpu().numpy() for x in (q, qs, qi, dl, dth)]
+    for a, b in zip(outs["ref"], outs["dbg"]):
+        assert np.array_equal(a, b)
+    bad = lam.clone()
+    bad[7] = float("nan")
+    q = t.empty_like(lam)
+    for call in (lambda: dbg.apply(bad, q), lambda: dbg.apply_static(bad, q), lambda: dbg.apply_implicit(bad, q)):
+        with pytest.raises(FetiError) as e:
+            call()
+        say("debug check:", e.value)
+        assert e.value.status == 7 and "lambda" in str(e.value) and "index 7" in str(e.value)
+    gb = g.clone()
+    gb[3] = float("inf")
+    dl, dth = t.empty_like(lam), t.empty(ne, dtype=t.float64, device="cuda")
+    with pytest.raises(FetiError) as e:
+        dbg.apply_backward(gb, lam, dl, dth)
+    say("debug check:", e.value)
+    assert e.value.status == 7 and "g holds" in str(e.value) and "index 3" in str(e.value)
+    # without the option the NaN propagates and nothing is raised
+    ref.apply(bad, q)
+    t.cuda.synchronize()
+    assert np.isnan(q.cpu().numpy()).any()
+    ref.close()
+    dbg.close()

@@ -43,7 +43,9 @@ def _build_hostsim(out, sanitizer):
             text = f.read()
         for m in re.finditer(r"hipError_t\s+(launch_\w+)\s*\(([^;]*?)\);", text, re.S):
             check = "hostsim_check_stream(st); " if re.search(r"hipStream_t\s+st\b", m.group(2)) else ""
-            stubs.append(f"hipError_t {m.group(1)}({m.group(2)}) {{ {check}return hipSuccess; }}")
+            # the debug scan reports "nothing found" (its sentinel) in host memory
+            extra = "*first = ~0ull; " if m.group(1) == "launch_first_nonfinite" else ""
+            stubs.append(f"hipError_t {m.group(1)}({m.group(2)}) {{ {check}{extra}return hipSuccess; }}")
     # the static scratch of the allocation-free apply: host memory here
     stubs.append("hipError_t static_scratch_address(int, void** out) "
                  "{ static unsigned char* buf = new unsigned char[kStaticScratchBytes]; *out = buf; return hipSuccess; }")
@@ -174,7 +176,7 @@ def flow(prob, with_elements=False, **opts):
 flow(config_problem(1), with_elements=True)
 flow(make_problem(1, "heat", [[7]], 0.0, dirichlet_axis=0, seed=1), with_elements=True)
 flow(make_problem(1, "heat", [[5, 5, 12]], 0.0, dirichlet_axis=0, seed=1), assembly_groups=2, nthreads=1)
-flow(config_problem(5, scale=(2, 5)), with_elements=True, assembly_groups=3, nthreads=2)
+flow(config_problem(5, scale=(2, 5)), with_elements=True, assembly_groups=3, nthreads=2, debug_checks=1)
 flow(config_problem(2, scale=(3, 6), elem="simplex"), assembly_groups=8, nthreads=1, f_storage="f32")
 flow(make_problem(3, "elasticity", [[3, 4, 2], [3, 2], [2, 3]], 0.3, dirichlet_axis=2, seed=3),
      assembly_groups=5, nthreads=2, f_storage="bf16")
