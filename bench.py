@@ -226,8 +226,8 @@ def decision_table():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=3, help="workload 1..5 (default 3, the largest)")
     ap.add_argument("--elem", default="box", choices=["box", "simplex"],
                     help="the workload's box elements, or the same grid cut into linear simplices")
