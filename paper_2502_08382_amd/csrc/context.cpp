@@ -451,9 +451,20 @@ bool plan_trsm(fetiF_ctx c, int32_t panel, int32_t chunk, TrsmPlan& T)
     for (size_t t = 0; t < T.tsns.size(); ++t)
         T.level_maxns[tlevel[t]] = std::max(T.level_maxns[tlevel[t]], T.tsns[t].ncols);
     const int32_t wmax = std::max(1, std::min(4, chunk / 16));
+    // a level whose panels mostly have few RHS columns gets narrower
+    // work-groups (more of them per CU): W covers 90 % of its panels' widths
+    std::vector<std::vector<int32_t>> lw(tmaxlev + 1);
+    for (size_t t = 0; t < T.tsns.size(); ++t) lw[tlevel[t]].push_back(T.tsns[t].w);
     for (int32_t L = 0; L <= tmaxlev; ++L) {
         const int32_t mx = std::max(1, T.level_maxns[L]);
         int32_t W = wmax;
+        if (!lw[L].empty()) {
+            std::vector<int32_t>& v = lw[L];
+            const size_t k = (v.size() * 9) / 10;
+            std::nth_element(v.begin(), v.begin() + (ptrdiff_t)std::min(k, v.size() - 1), v.end());
+            const int32_t w90 = v[std::min(k, v.size() - 1)];
+            while (W > 1 && 16 * (W / 2) >= w90) W /= 2;
+        }
         while (W > 1 && trsm_lds_bytes(W, mx) > 80 * 1024) W /= 2;   // keep two work-groups per CU
         if (trsm_lds_bytes(W, mx) > 160 * 1024) return false;
         T.level_waves[L] = W;
